@@ -1,0 +1,195 @@
+/*
+ * pd.h -- C ABI of the MI355X population-dynamics (cloning) library for
+ * large deviations of the activity of the periodic symmetric simple
+ * exclusion process (SSEP).
+ *
+ * The method is the cloning algorithm of T. Brewer, S. R. Clark, R. Bradford,
+ * R. L. Jack, "Efficient characterisation of large deviations using population
+ * dynamics" (arXiv:1711.05095):
+ *   - Nc clones of the SSEP (L sites, N particles, hop rate 1 to each empty
+ *     neighbour, periodic; Sec. 3.1) evolve independently for an interval
+ *     Delta t in continuous time (the dynamical stage, Sec. 2.3 and Sec. 4);
+ *   - each clone carries its cloning factor Upsilon^beta (eq. upsbdef): with
+ *     the modified dynamics of Sec. 3.2 (every rate times e^{-s}) it is
+ *     exp(-(1 - e^{-s}) * integral of r(C) dt) (eq. def-ups-ssep); with the
+ *     unmodified dynamics it is e^{-s K^beta} (Sec. 3.1); with a guide g it
+ *     is the compensating factor of eqs. modpdef and upsdef (Sec. 2.2);
+ *   - the cloning stage replaces the population by Nc clones pulled from the
+ *     old one by the [eq] rule of Sec. 4.1 (eq. alpha-Ups) or the [iid] rule;
+ *   - after M = t_obs / Delta t repetitions, psi-hat (eq. psihat) estimates
+ *     the scaled cumulant generating function and k-hat (eq. khat, divided
+ *     also by Nc) the biased activity per site.
+ *
+ * Conventions for every function:
+ *   - The return value is a pd_status: PD_OK (0) or a negative error.  No
+ *     C++ exception crosses this boundary.  pd_last_error() returns a
+ *     human-readable message for the last failure on a context.
+ *   - Invalid arguments return PD_EINVAL before any device work is queued.
+ *     A failing HIP call returns PD_EDEVICE.
+ *   - Device memory is owned by the caller: pd_workspace_bytes() says how
+ *     much, pd_create() takes a device pointer to it (256-byte aligned), and
+ *     the memory must outlive the context.  The library allocates no device
+ *     memory of its own; pd_destroy() frees only the host-side context.
+ *   - All device work is queued on the HIP stream given to pd_create()
+ *     (NULL means the default stream).  Calls that return results to the
+ *     host (pd_scgf, pd_get_*, pd_save) synchronise that stream.
+ *   - A context holds n independent instances (a batch); functions that take
+ *     `inst` act on one of them, the others on all.  A context is not
+ *     thread-safe; use one context per host thread and stream.
+ *
+ * Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by `seed`; the
+ * counter of every draw is (draw index, clone slot, interval beta, tag |
+ * instance << 8), so results depend only on the parameters, never on how the
+ * GPU schedules the work.
+ */
+#ifndef PD_H
+#define PD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PD_OK = 0,
+    PD_EINVAL = -1,       /* invalid argument or parameter set */
+    PD_ENOMEM = -2,       /* workspace or host buffer too small */
+    PD_EDEVICE = -3,      /* a HIP call failed; see pd_last_error */
+    PD_ESTATE = -4,       /* call out of order (e.g. two dynamical stages in a row) */
+    PD_EUNSUPPORTED = -5  /* parameter combination not supported by this build */
+} pd_status;
+
+typedef enum {
+    PD_SEL_EQ = 0,        /* equally spaced points, one offset d per interval (Sec. 4.1) */
+    PD_SEL_IID = 1        /* independent uniform points (Sec. 4.1, [iid]) */
+} pd_selection;
+
+typedef enum {
+    PD_W_MODIFIED = 0,    /* rates x e^{-s}; Ups = exp(-(1-e^{-s}) int r dt) (Sec. 3.2) */
+    PD_W_DIRECT = 1,      /* unmodified rates; Ups = e^{-s K^beta} (Sec. 3.1) */
+    PD_W_GUIDED = 2       /* rates x e^{-s+g}; exact compensating weight (Sec. 2.2) */
+} pd_weight_mode;
+
+#define PD_MAX_L 512      /* states are at most 8 words of 64 sites */
+
+typedef struct {
+    int32_t  L;           /* sites, 2 <= L <= PD_MAX_L */
+    int32_t  N;           /* particles, 0 <= N <= L (N = 0 or L: no hop, psi-hat = 0) */
+    double   s;           /* biasing field, finite */
+    int64_t  Nc;          /* clones, 1 <= Nc <= 2^31 - 1 */
+    double   t_obs;       /* observation time, > 0 */
+    double   dt;          /* cloning interval Delta t, > 0; M = llround(t_obs/dt) >= 1
+                             and |M dt - t_obs| <= 1e-9 t_obs, else PD_EINVAL */
+    uint64_t seed;        /* Philox key */
+    int32_t  selection;   /* pd_selection */
+    int32_t  weight_mode; /* pd_weight_mode */
+    uint32_t instance;    /* Philox counter tag, < 2^24; distinct per instance of a batch */
+    int32_t  log_cycles;  /* >= 0: keep per-interval (ln mean Ups, mean K^beta) for the
+                             first log_cycles intervals (see pd_get_log) */
+    int64_t  burn_in;     /* >= 0: intervals left out of psi_burn (pd_estimates) */
+} pd_params;
+
+typedef struct {
+    double   psi;         /* psi-hat = (1/(beta dt)) sum over completed intervals */
+    double   psi_burn;    /* the same sum over intervals beyond burn_in, / ((beta-burn_in) dt) */
+    double   k_hat;       /* sum_j K_j / (Nc L beta dt) over the current population */
+    double   t;           /* beta * dt */
+    int64_t  cycles;      /* beta: completed (dynamics, cloning) cycles */
+    uint64_t hops;        /* every hop performed by every clone so far */
+} pd_estimates;
+
+typedef struct pd_ctx pd_ctx;   /* opaque, host-side, owned by the library */
+
+/* Bytes of device workspace for a batch of n instances (n >= 1). */
+pd_status pd_workspace_bytes(const pd_params* params, int32_t n, size_t* bytes);
+
+/* Validates the n parameter sets, lays out the workspace, and queues the
+ * initial condition on `hip_stream`: every clone a uniform N-subset of the L
+ * sites (the steady state at fixed N, Sec. 3.1), K = 0.  `d_workspace` is a
+ * caller-owned device buffer of at least pd_workspace_bytes() bytes. */
+pd_status pd_create(const pd_params* params, int32_t n, void* d_workspace, size_t bytes,
+                    void* hip_stream, pd_ctx** out);
+
+/* Releases the host-side context.  Does not touch the caller's device memory. */
+pd_status pd_destroy(pd_ctx* ctx);
+
+/* Dynamical stage of the next interval beta for every instance (Sec. 2.3):
+ * each clone runs the continuous-time SSEP for Delta t and gets its hop count
+ * K^beta, the integral of r dt and ln Upsilon^beta.  It also forms ln of the
+ * population mean of Upsilon^beta (eq. psihat) and adds it to psi.
+ * PD_ESTATE if the previous call was also pd_step. Asynchronous. */
+pd_status pd_step(pd_ctx* ctx);
+
+/* Cloning stage of interval beta (Sec. 4.1): new clone j is pulled, with its
+ * accumulated K, from the old clone whose interval of the cumulative
+ * Upsilon line holds the point alpha_j.  PD_ESTATE unless pd_step came
+ * immediately before. Asynchronous. */
+pd_status pd_resample(pd_ctx* ctx);
+
+/* `cycles` repetitions of (pd_step, pd_resample), replayed from captured HIP
+ * graphs.  PD_ESTATE if a pd_step is waiting for its pd_resample. */
+pd_status pd_run(pd_ctx* ctx, int64_t cycles);
+
+/* Estimates of instance 0 (synchronises the stream). */
+pd_status pd_scgf(pd_ctx* ctx, double* psi, double* k_hat, int64_t* cycles_done);
+
+/* Estimates of instance `inst` (synchronises the stream). */
+pd_status pd_estimates_get(pd_ctx* ctx, int32_t inst, pd_estimates* out);
+
+/* Host image of a population: uint64 state words [W][Nc] (word w of clone j
+ * at w*Nc + j; site i is bit i%64 of word i/64, bits >= L are zero), then
+ * uint64 K[Nc] (hops accumulated along the clone's ancestry).  W = ceil(L/64). */
+pd_status pd_population_bytes(const pd_params* params, size_t* bytes);
+
+/* Copies the current population of instance `inst` to `host` (synchronises). */
+pd_status pd_get_population(pd_ctx* ctx, int32_t inst, void* host, size_t bytes);
+
+/* Replaces the current population of instance `inst` (synchronises).
+ * Every clone must hold exactly N particles in its first L bits (PD_EINVAL
+ * otherwise).  Clears a pending dynamical stage. */
+pd_status pd_set_population(pd_ctx* ctx, int32_t inst, const void* host, size_t bytes);
+
+/* Per-clone outputs of the last dynamical stage of instance `inst`, indexed
+ * by clone slot: K^beta (uint32), integral of r dt (double), ln Upsilon^beta
+ * (double).  Any pointer may be NULL.  Synchronises. */
+pd_status pd_get_step_outputs(pd_ctx* ctx, int32_t inst, uint32_t* Kb, double* A, double* ell);
+
+/* Ancestor map of the last cloning stage of instance `inst`: anc[j] = old
+ * clone that new clone j was pulled from.  PD_ESTATE if no cloning stage has
+ * run since the last dynamical stage.  Synchronises. */
+pd_status pd_get_ancestors(pd_ctx* ctx, int32_t inst, int32_t* anc);
+
+/* Per-interval log of instance `inst` (params.log_cycles > 0): for interval
+ * beta = 1..n_rows, lbeta[beta-1] = ln((1/Nc) sum_i Upsilon_i^beta) and
+ * mean_kb[beta-1] = population mean of K^beta before cloning.  Synchronises. */
+pd_status pd_get_log(pd_ctx* ctx, int32_t inst, double* lbeta, double* mean_kb, int32_t n_rows);
+
+/* Checkpoint of the whole context (all instances: populations and estimator
+ * sums) into a host buffer of pd_save_bytes() bytes, and its restore into a
+ * context created with the same parameters.  A restored run continues
+ * bit-identically. Both synchronise. */
+pd_status pd_save_bytes(pd_ctx* ctx, size_t* bytes);
+pd_status pd_save(pd_ctx* ctx, void* host, size_t bytes);
+pd_status pd_load(pd_ctx* ctx, const void* host, size_t bytes);
+
+/* Guide for PD_W_GUIDED instances: `d_table` is a caller-owned device array
+ * of 8192 floats, h(window) for every configuration of 13 consecutive sites
+ * (site c-6 in bit 0 ... site c+6 in bit 12).  The guide potential is
+ * f(C) = sum over sites c of h(window at c) and the log-ratio across a hop is
+ * g = f(C after) - f(C before).  Entries must be multiples of 2^-20 with
+ * magnitude <= 64 (then every sum of them is exact in FP64); PD_EINVAL
+ * otherwise.  The table must outlive its use. Synchronises. */
+pd_status pd_set_guide(pd_ctx* ctx, const float* d_table, size_t n);
+
+/* Human-readable message of the last error on ctx (or of the last failed
+ * pd_create when ctx is NULL). */
+const char* pd_last_error(const pd_ctx* ctx);
+const char* pd_status_str(pd_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PD_H */

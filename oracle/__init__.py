@@ -65,6 +65,10 @@ def lib():
         _lib.orc_resample.argtypes = [P(Params), ctypes.c_uint32] + [ctypes.c_void_p] * 6
         _lib.orc_resample.restype = ctypes.c_double
         _lib.orc_run.argtypes = [P(Params), P(Result), ctypes.c_void_p, ctypes.c_void_p]
+        _lib.orc_step_slots.argtypes = [P(Params), ctypes.c_uint32, ctypes.c_int64] + \
+            [ctypes.c_void_p] * 6
+        _lib.orc_init_slots.argtypes = [P(Params), ctypes.c_int64, ctypes.c_void_p,
+                                        ctypes.c_void_p]
     return _lib
 
 
@@ -105,6 +109,25 @@ class Oracle:
         lib().orc_step(ctypes.byref(self.p), beta, _ptr(occ), _ptr(K), _ptr(Kb), _ptr(A),
                        _ptr(ell))
         return Kb, A, ell
+
+    def step_slots(self, beta, slots, occ, K):
+        """Dynamical stage for the clones in the given slots only (occ[i] is the
+        clone of slot slots[i]); in place.  Returns (Kb, A, ell)."""
+        slots = np.ascontiguousarray(slots, np.int64)
+        n = slots.shape[0]
+        assert occ.dtype == np.uint8 and occ.shape == (n, self.L) and occ.flags.c_contiguous
+        Kb = np.zeros(n, np.uint32)
+        A = np.zeros(n, np.float64)
+        ell = np.zeros(n, np.float64)
+        lib().orc_step_slots(ctypes.byref(self.p), beta, n, _ptr(slots), _ptr(occ), _ptr(K),
+                             _ptr(Kb), _ptr(A), _ptr(ell))
+        return Kb, A, ell
+
+    def init_slots(self, slots):
+        slots = np.ascontiguousarray(slots, np.int64)
+        occ = np.zeros((slots.shape[0], self.L), np.uint8)
+        lib().orc_init_slots(ctypes.byref(self.p), slots.shape[0], _ptr(slots), _ptr(occ))
+        return occ
 
     def eq_offset(self, beta):
         return lib().orc_eq_offset(ctypes.byref(self.p), beta)

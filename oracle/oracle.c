@@ -134,27 +134,38 @@ static uint64_t mulhi64(uint64_t a, uint64_t b)
  * site i is taken with probability (N - taken)/(L - i)).  Site i uses the
  * 64-bit number formed from words 2i and 2i+1 of the INIT stream of slot j;
  * the test "u * (L-i) / 2^64 < N - taken" is exact integer arithmetic. */
-int orc_init(const orc_params* p, uint8_t* occ, uint64_t* K)
+static void init_clone(const orc_params* p, int64_t slot, uint8_t* n)
 {
     const int L = p->L;
-    for (int64_t j = 0; j < p->Nc; ++j) {
-        uint8_t* n = occ + (size_t)j * L;
-        int taken = 0;
-        uint32_t x[4];
-        for (int i = 0; i < L; ++i) {
-            if ((i & 1) == 0)
-                draw(p, ORC_TAG_INIT, (uint32_t)(i / 2), (uint32_t)j, 0u, x);
-            uint64_t u = ((i & 1) == 0) ? (((uint64_t)x[0] << 32) | x[1])
-                                        : (((uint64_t)x[2] << 32) | x[3]);
-            if (mulhi64(u, (uint64_t)(L - i)) < (uint64_t)(p->N - taken)) {
-                n[i] = 1;
-                ++taken;
-            } else {
-                n[i] = 0;
-            }
+    int taken = 0;
+    uint32_t x[4];
+    for (int i = 0; i < L; ++i) {
+        if ((i & 1) == 0)
+            draw(p, ORC_TAG_INIT, (uint32_t)(i / 2), (uint32_t)slot, 0u, x);
+        uint64_t u = ((i & 1) == 0) ? (((uint64_t)x[0] << 32) | x[1])
+                                    : (((uint64_t)x[2] << 32) | x[3]);
+        if (mulhi64(u, (uint64_t)(L - i)) < (uint64_t)(p->N - taken)) {
+            n[i] = 1;
+            ++taken;
+        } else {
+            n[i] = 0;
         }
+    }
+}
+
+int orc_init(const orc_params* p, uint8_t* occ, uint64_t* K)
+{
+    for (int64_t j = 0; j < p->Nc; ++j) {
+        init_clone(p, j, occ + (size_t)j * p->L);
         K[j] = 0;
     }
+    return 0;
+}
+
+/* Initial configuration of a sample of slots. */
+int orc_init_slots(const orc_params* p, int64_t n, const int64_t* slots, uint8_t* occ)
+{
+    for (int64_t i = 0; i < n; ++i) init_clone(p, slots[i], occ + (size_t)i * p->L);
     return 0;
 }
 
@@ -317,6 +328,23 @@ int orc_step(const orc_params* p, uint32_t beta, uint8_t* occ, uint64_t* K, uint
         uint32_t kb = step_clone(p, es, c, beta, j, occ + (size_t)j * p->L, &A[j], &ell[j]);
         Kb[j] = kb;
         K[j] += kb;
+    }
+    return 0;
+}
+
+/* The dynamical stage for a sample of clones: clone i of the arrays is the
+ * clone in slot slots[i] of the population (the slot enters its random
+ * stream).  Lets a test check single clones of a population too large to
+ * step here in full. */
+int orc_step_slots(const orc_params* p, uint32_t beta, int64_t n, const int64_t* slots,
+                   uint8_t* occ, uint64_t* K, uint32_t* Kb, double* A, double* ell)
+{
+    const double es = exp(-p->s);
+    const double c = -expm1(-p->s);
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t kb = step_clone(p, es, c, beta, slots[i], occ + (size_t)i * p->L, &A[i], &ell[i]);
+        Kb[i] = kb;
+        K[i] += kb;
     }
     return 0;
 }

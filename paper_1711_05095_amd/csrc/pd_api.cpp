@@ -1,0 +1,644 @@
+// Host runtime of the library: the C ABI declared in include/pd.h.
+//
+// The runtime validates parameters, carves the caller's workspace into the
+// per-instance arrays, orders the tiles of all instances by estimated cost
+// (largest first) for the dynamical stage, and queues the kernels.  Which of
+// the two state buffers holds the population, and whether it is still to be
+// read through the ancestor map, is tracked here on the host: it changes
+// deterministically with every call, so a captured graph of an even number of
+// cycles can be replayed with fixed kernel arguments.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pd.h"
+#include "pd_internal.hpp"
+#include "pd_launch.hpp"
+
+using namespace pd;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+constexpr size_t kAlign = 256;
+constexpr double kMaxEventsPerInterval = 16777216.0;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int words_of(int L) { return (L + 63) / 64; }
+
+int64_t cycles_of(const pd_params& p) { return llround(p.t_obs / p.dt); }
+
+std::string validate(const pd_params& p)
+{
+    if (p.L < 2 || p.L > PD_MAX_L) return "L must be in [2, 512]";
+    if (p.N < 0 || p.N > p.L) return "N must be in [0, L]";
+    if (!std::isfinite(p.s) || std::fabs(p.s) > 700.0) return "s must be finite with |s| <= 700";
+    if (p.Nc < 1 || p.Nc > INT32_MAX) return "Nc must be in [1, 2^31 - 1]";
+    if (!(p.t_obs > 0.0) || !std::isfinite(p.t_obs)) return "t_obs must be positive and finite";
+    if (!(p.dt > 0.0) || !std::isfinite(p.dt)) return "dt must be positive and finite";
+    const double Md = p.t_obs / p.dt;
+    if (!(Md < 4.0e9)) return "t_obs / dt must be below 2^32";
+    const int64_t M = cycles_of(p);
+    if (M < 1) return "t_obs / dt must round to at least 1";
+    if (std::fabs((double)M * p.dt - p.t_obs) > 1e-9 * p.t_obs)
+        return "t_obs must be an integer multiple of dt";
+    {
+        // expected hops of one clone in one interval, at most e^{-s} L dt
+        const double rate = (p.weight_mode == PD_W_DIRECT ? 1.0 : std::exp(-p.s)) * (double)p.L;
+        if (!(rate * p.dt <= kMaxEventsPerInterval))
+            return "expected hops per clone per interval (e^{-s} L dt) must be <= 2^24";
+    }
+    if (p.selection != PD_SEL_EQ && p.selection != PD_SEL_IID) return "unknown selection";
+    if (p.weight_mode < PD_W_MODIFIED || p.weight_mode > PD_W_GUIDED) return "unknown weight mode";
+    if (p.instance >= (1u << 24)) return "instance must be below 2^24";
+    if (p.log_cycles < 0) return "log_cycles must be >= 0";
+    if (p.burn_in < 0) return "burn_in must be >= 0";
+    return "";
+}
+
+struct Layout {
+    size_t state[2], K[2], Kb, A, ell, anc, ykey, tmax, tsum, thops, toff, inv, log, ctl;
+    size_t end;
+    int ntiles;
+};
+
+// Byte offsets of one instance's arrays, starting at `base`.
+Layout layout_of(const pd_params& p, size_t base)
+{
+    Layout o;
+    const size_t Nc = (size_t)p.Nc;
+    const int W = words_of(p.L);
+    o.ntiles = (int)((Nc + kTile - 1) / kTile);
+    size_t at = align_up(base);
+    auto take = [&](size_t bytes) { size_t r = at; at = align_up(at + bytes); return r; };
+    o.state[0] = take(8 * Nc * W);
+    o.state[1] = take(8 * Nc * W);
+    o.K[0] = take(8 * Nc);
+    o.K[1] = take(8 * Nc);
+    o.Kb = take(4 * Nc);
+    o.A = take(8 * Nc);
+    o.ell = take(8 * Nc);
+    o.anc = take(4 * Nc);
+    o.ykey = (p.selection == PD_SEL_IID) ? take(8 * Nc) : 0;
+    o.tmax = take(8 * (size_t)o.ntiles);
+    o.tsum = take(8 * (size_t)o.ntiles);
+    o.thops = take(8 * (size_t)o.ntiles);
+    o.toff = take(8 * ((size_t)o.ntiles + 1));
+    o.inv = take(8 * ((size_t)p.L + 1));
+    o.log = take(16 * (size_t)std::max(p.log_cycles, 1));
+    o.ctl = take(sizeof(InstCtl));
+    o.end = at;
+    return o;
+}
+
+struct Plan {
+    size_t insts_off, tiles_off, total;
+    std::vector<Layout> lay;
+    int ntiles;
+};
+
+Plan plan_of(const pd_params* p, int n)
+{
+    Plan pl;
+    pl.insts_off = 0;
+    size_t at = align_up(sizeof(InstDev) * (size_t)n);
+    int nt = 0;
+    for (int i = 0; i < n; ++i) nt += (int)((p[i].Nc + kTile - 1) / kTile);
+    pl.ntiles = nt;
+    pl.tiles_off = at;
+    at = align_up(at + sizeof(TileDesc) * (size_t)nt);
+    for (int i = 0; i < n; ++i) {
+        pl.lay.push_back(layout_of(p[i], at));
+        at = pl.lay.back().end;
+    }
+    pl.total = at;
+    return pl;
+}
+
+}  // namespace
+
+struct pd_ctx {
+    hipStream_t stream = nullptr;
+    int n = 0;
+    std::vector<pd_params> params;
+    std::vector<InstDev> dev;        // host copies of the descriptors
+    Plan plan;
+    char* ws = nullptr;
+    InstDev* d_insts = nullptr;
+    TileDesc* d_tiles = nullptr;
+    std::vector<TileDesc> tiles;     // host copy, step order
+    struct WGroup { int W, base, count; };
+    std::vector<WGroup> groups;      // step launches, one per word count
+    bool any_iid = false;
+    bool any_guided = false;
+    int cur = 0;                     // buffer holding the population
+    bool perm = false;               // population = state[cur][anc[j]]
+    bool stepped = false;            // a dynamical stage awaits its cloning stage
+    bool anc_valid = false;          // anc holds the last cloning stage's map
+    int64_t beta = 0;                // completed cycles (host mirror)
+    int graph_cycles = 16;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    std::string err;
+};
+
+#define PD_HIP(call)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            ctx->err = std::string(#call) + ": " + hipGetErrorString(e_);               \
+            return PD_EDEVICE;                                                          \
+        }                                                                               \
+    } while (0)
+
+namespace {
+
+pd_status fail(pd_ctx* ctx, pd_status st, const std::string& msg)
+{
+    if (ctx) ctx->err = msg; else g_create_error = msg;
+    return st;
+}
+
+pd_status enqueue_cycle(pd_ctx* ctx, int use_anc, int src)
+{
+    for (const auto& g : ctx->groups)
+        PD_HIP(launch_step(g.W, ctx->d_insts, ctx->d_tiles, g.base, g.count, src, use_anc,
+                           ctx->stream));
+    PD_HIP(launch_resample(ctx->d_insts, ctx->d_tiles, (int)ctx->tiles.size(), ctx->stream));
+    return PD_OK;
+}
+
+pd_status check_inst(pd_ctx* ctx, int32_t inst)
+{
+    if (!ctx) return PD_EINVAL;
+    if (inst < 0 || inst >= ctx->n) return fail(ctx, PD_EINVAL, "instance index out of range");
+    return PD_OK;
+}
+
+// Makes state[cur] hold the population in slot order.
+pd_status materialise(pd_ctx* ctx)
+{
+    if (!ctx->perm) return PD_OK;
+    for (const auto& g : ctx->groups)
+        PD_HIP(launch_gather(g.W, ctx->d_insts, ctx->d_tiles, g.base, g.count, ctx->cur,
+                             ctx->stream));
+    ctx->cur ^= 1;
+    ctx->perm = false;
+    return PD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pd_status pd_workspace_bytes(const pd_params* params, int32_t n, size_t* bytes)
+{
+    if (!params || n < 1 || !bytes) return fail(nullptr, PD_EINVAL, "null argument or n < 1");
+    for (int i = 0; i < n; ++i) {
+        std::string m = validate(params[i]);
+        if (!m.empty()) return fail(nullptr, PD_EINVAL, "instance " + std::to_string(i) + ": " + m);
+    }
+    *bytes = plan_of(params, n).total;
+    return PD_OK;
+}
+
+pd_status pd_create(const pd_params* params, int32_t n, void* d_workspace, size_t bytes,
+                    void* hip_stream, pd_ctx** out)
+{
+    if (!params || n < 1 || !out || !d_workspace)
+        return fail(nullptr, PD_EINVAL, "null argument or n < 1");
+    *out = nullptr;
+    for (int i = 0; i < n; ++i) {
+        std::string m = validate(params[i]);
+        if (!m.empty()) return fail(nullptr, PD_EINVAL, "instance " + std::to_string(i) + ": " + m);
+        if (params[i].weight_mode == PD_W_GUIDED)
+            return fail(nullptr, PD_EUNSUPPORTED, "guided weights are not available in this build");
+    }
+    if ((uintptr_t)d_workspace % kAlign != 0)
+        return fail(nullptr, PD_EINVAL, "workspace must be 256-byte aligned");
+    Plan pl = plan_of(params, n);
+    if (bytes < pl.total) return fail(nullptr, PD_ENOMEM, "workspace too small");
+
+    pd_ctx* ctx = new pd_ctx();
+    ctx->stream = (hipStream_t)hip_stream;
+    ctx->n = n;
+    ctx->params.assign(params, params + n);
+    ctx->plan = pl;
+    ctx->ws = (char*)d_workspace;
+    ctx->d_insts = (InstDev*)(ctx->ws + pl.insts_off);
+    ctx->d_tiles = (TileDesc*)(ctx->ws + pl.tiles_off);
+
+    // descriptors and rate tables
+    std::vector<std::vector<double>> inv(n);
+    for (int i = 0; i < n; ++i) {
+        const pd_params& p = params[i];
+        const Layout& o = pl.lay[i];
+        InstDev d;
+        std::memset(&d, 0, sizeof d);
+        d.L = p.L; d.N = p.N; d.W = words_of(p.L); d.mode = p.weight_mode;
+        d.selection = p.selection; d.ntiles = o.ntiles; d.log_cycles = p.log_cycles;
+        d.key0 = (uint32_t)p.seed; d.key1 = (uint32_t)(p.seed >> 32);
+        d.tag_hi = p.instance << 8;
+        d.s = p.s;
+        d.es = std::exp(-p.s);
+        d.c = -std::expm1(-p.s);
+        d.dt = p.dt;
+        d.Nc = p.Nc;
+        d.burn_in = p.burn_in;
+        char* b = ctx->ws;
+        d.state[0] = (uint64_t*)(b + o.state[0]);
+        d.state[1] = (uint64_t*)(b + o.state[1]);
+        d.K[0] = (uint64_t*)(b + o.K[0]);
+        d.K[1] = (uint64_t*)(b + o.K[1]);
+        d.Kb = (uint32_t*)(b + o.Kb);
+        d.A = (double*)(b + o.A);
+        d.ell = (double*)(b + o.ell);
+        d.anc = (int32_t*)(b + o.anc);
+        d.ykey = o.ykey ? (double*)(b + o.ykey) : nullptr;
+        d.tile_max = (double*)(b + o.tmax);
+        d.tile_sum = (double*)(b + o.tsum);
+        d.tile_hops = (uint64_t*)(b + o.thops);
+        d.tile_off = (double*)(b + o.toff);
+        d.inv_rate = (const double*)(b + o.inv);
+        d.log = (double*)(b + o.log);
+        d.guide = nullptr;
+        d.ctl = (InstCtl*)(b + o.ctl);
+        ctx->dev.push_back(d);
+        // 1 / (total rate) for every escape count r: r e^{-s} (modified) or r
+        inv[i].assign((size_t)p.L + 1, 0.0);
+        for (int r = 1; r <= p.L; ++r)
+            inv[i][r] = 1.0 / ((p.weight_mode == PD_W_MODIFIED ? d.es : 1.0) * (double)r);
+        if (p.selection == PD_SEL_IID) ctx->any_iid = true;
+    }
+
+    // tiles: grouped by word count, largest expected work first within a group
+    struct Cand { TileDesc t; int W; double cost; };
+    std::vector<Cand> cand;
+    for (int i = 0; i < n; ++i) {
+        const pd_params& p = params[i];
+        const double rbar = p.L > 1 ? 2.0 * p.N * (double)(p.L - p.N) / (double)(p.L - 1) : 0.0;
+        const double rate = (p.weight_mode == PD_W_MODIFIED ? std::exp(-p.s) : 1.0) * rbar;
+        const int nt = pl.lay[i].ntiles;
+        for (int t = 0; t < nt; ++t) {
+            TileDesc td;
+            td.inst = i;
+            td.tile = t;
+            td.first = t * kTile;
+            td.count = (int)std::min<int64_t>(kTile, p.Nc - (int64_t)t * kTile);
+            cand.push_back({td, words_of(p.L), td.count * (rate * p.dt + 1.0)});
+        }
+    }
+    std::stable_sort(cand.begin(), cand.end(), [](const Cand& a, const Cand& b) {
+        if (a.W != b.W) return a.W < b.W;
+        return a.cost > b.cost;
+    });
+    for (size_t k = 0; k < cand.size(); ++k) {
+        ctx->tiles.push_back(cand[k].t);
+        if (ctx->groups.empty() || ctx->groups.back().W != cand[k].W)
+            ctx->groups.push_back({cand[k].W, (int)k, 0});
+        ctx->groups.back().count++;
+    }
+
+    auto bail = [&](pd_status st) { g_create_error = ctx->err; delete ctx; return st; };
+#define PD_HIP_CREATE(call)                                                             \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            ctx->err = std::string(#call) + ": " + hipGetErrorString(e_);               \
+            return bail(PD_EDEVICE);                                                    \
+        }                                                                               \
+    } while (0)
+    PD_HIP_CREATE(hipMemcpyAsync(ctx->d_insts, ctx->dev.data(), sizeof(InstDev) * (size_t)n,
+                                 hipMemcpyHostToDevice, ctx->stream));
+    PD_HIP_CREATE(hipMemcpyAsync(ctx->d_tiles, ctx->tiles.data(),
+                                 sizeof(TileDesc) * ctx->tiles.size(), hipMemcpyHostToDevice,
+                                 ctx->stream));
+    for (int i = 0; i < n; ++i)
+        PD_HIP_CREATE(hipMemcpyAsync((void*)ctx->dev[i].inv_rate, inv[i].data(),
+                                     sizeof(double) * inv[i].size(), hipMemcpyHostToDevice,
+                                     ctx->stream));
+    PD_HIP_CREATE(launch_init(ctx->d_insts, n, ctx->d_tiles, (int)ctx->tiles.size(), ctx->stream));
+    // the host vectors above are pageable: wait before they go out of scope
+    PD_HIP_CREATE(hipStreamSynchronize(ctx->stream));
+#undef PD_HIP_CREATE
+    *out = ctx;
+    return PD_OK;
+}
+
+pd_status pd_destroy(pd_ctx* ctx)
+{
+    if (!ctx) return PD_EINVAL;
+    for (auto& g : ctx->graph)
+        if (g) (void)hipGraphExecDestroy(g);
+    delete ctx;
+    return PD_OK;
+}
+
+pd_status pd_step(pd_ctx* ctx)
+{
+    if (!ctx) return PD_EINVAL;
+    if (ctx->stepped) return fail(ctx, PD_ESTATE, "pd_step called twice without pd_resample");
+    for (const auto& g : ctx->groups)
+        PD_HIP(launch_step(g.W, ctx->d_insts, ctx->d_tiles, g.base, g.count, ctx->cur,
+                           ctx->perm ? 1 : 0, ctx->stream));
+    ctx->cur ^= 1;
+    ctx->perm = false;
+    ctx->stepped = true;
+    ctx->anc_valid = false;
+    return PD_OK;
+}
+
+pd_status pd_resample(pd_ctx* ctx)
+{
+    if (!ctx) return PD_EINVAL;
+    if (!ctx->stepped) return fail(ctx, PD_ESTATE, "pd_resample needs a pd_step first");
+    PD_HIP(launch_resample(ctx->d_insts, ctx->d_tiles, (int)ctx->tiles.size(), ctx->stream));
+    ctx->perm = true;
+    ctx->stepped = false;
+    ctx->anc_valid = true;
+    ctx->beta += 1;
+    return PD_OK;
+}
+
+pd_status pd_run(pd_ctx* ctx, int64_t cycles)
+{
+    if (!ctx || cycles < 0) return PD_EINVAL;
+    if (ctx->stepped) return fail(ctx, PD_ESTATE, "a pd_step awaits its pd_resample");
+    int64_t left = cycles;
+    if (left > 0 && !ctx->perm) {
+        pd_status st = enqueue_cycle(ctx, 0, ctx->cur);
+        if (st != PD_OK) return st;
+        ctx->cur ^= 1;
+        ctx->perm = true;
+        --left;
+    }
+    const int G = ctx->graph_cycles;
+    if (ctx->stream != nullptr && G > 0 && left >= G) {
+        hipGraphExec_t& ex = ctx->graph[ctx->cur];
+        if (!ex) {
+            hipGraph_t g = nullptr;
+            PD_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+            pd_status st = PD_OK;
+            for (int c = 0; c < G && st == PD_OK; ++c) st = enqueue_cycle(ctx, 1, ctx->cur ^ (c & 1));
+            hipError_t e = hipStreamEndCapture(ctx->stream, &g);
+            if (st != PD_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+            PD_HIP(e);
+            hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            PD_HIP(ei);
+        }
+        while (left >= G) {
+            PD_HIP(hipGraphLaunch(ex, ctx->stream));
+            left -= G;   // G is even: the population returns to buffer cur
+        }
+    }
+    while (left > 0) {
+        pd_status st = enqueue_cycle(ctx, 1, ctx->cur);
+        if (st != PD_OK) return st;
+        ctx->cur ^= 1;
+        --left;
+    }
+    ctx->perm = ctx->perm || cycles > 0;
+    ctx->anc_valid = cycles > 0 ? true : ctx->anc_valid;
+    ctx->beta += cycles;
+    return PD_OK;
+}
+
+pd_status pd_estimates_get(pd_ctx* ctx, int32_t inst, pd_estimates* out)
+{
+    pd_status st = check_inst(ctx, inst);
+    if (st != PD_OK) return st;
+    if (!out) return fail(ctx, PD_EINVAL, "null output");
+    const InstDev& d = ctx->dev[inst];
+    const pd_params& p = ctx->params[inst];
+    PD_HIP(launch_zero_ksum(ctx->d_insts, ctx->n, ctx->stream));
+    PD_HIP(launch_ksum(ctx->d_insts, ctx->d_tiles, (int)ctx->tiles.size(), ctx->cur,
+                       ctx->perm ? 1 : 0, ctx->stream));
+    InstCtl c;
+    PD_HIP(hipMemcpyAsync(&c, d.ctl, sizeof c, hipMemcpyDeviceToHost, ctx->stream));
+    PD_HIP(hipStreamSynchronize(ctx->stream));
+    const double t = (double)c.beta * p.dt;
+    out->cycles = c.beta;
+    out->t = t;
+    out->hops = c.hops;
+    out->psi = c.beta > 0 ? (c.psi_sum + c.psi_comp) / t : 0.0;
+    out->psi_burn = c.beta > p.burn_in
+                        ? (c.psib_sum + c.psib_comp) / ((double)(c.beta - p.burn_in) * p.dt) : 0.0;
+    out->k_hat = c.beta > 0 ? (double)c.ksum / ((double)p.Nc * (double)p.L * t) : 0.0;
+    return PD_OK;
+}
+
+pd_status pd_scgf(pd_ctx* ctx, double* psi, double* k_hat, int64_t* cycles_done)
+{
+    pd_estimates e;
+    pd_status st = pd_estimates_get(ctx, 0, &e);
+    if (st != PD_OK) return st;
+    if (psi) *psi = e.psi;
+    if (k_hat) *k_hat = e.k_hat;
+    if (cycles_done) *cycles_done = e.cycles;
+    return PD_OK;
+}
+
+pd_status pd_population_bytes(const pd_params* params, size_t* bytes)
+{
+    if (!params || !bytes) return PD_EINVAL;
+    std::string m = validate(*params);
+    if (!m.empty()) return fail(nullptr, PD_EINVAL, m);
+    *bytes = 8 * (size_t)params->Nc * (size_t)(words_of(params->L) + 1);
+    return PD_OK;
+}
+
+pd_status pd_get_population(pd_ctx* ctx, int32_t inst, void* host, size_t bytes)
+{
+    pd_status st = check_inst(ctx, inst);
+    if (st != PD_OK) return st;
+    const pd_params& p = ctx->params[inst];
+    const size_t Nc = (size_t)p.Nc, W = (size_t)words_of(p.L);
+    if (!host || bytes < 8 * Nc * (W + 1)) return fail(ctx, PD_ENOMEM, "host buffer too small");
+    st = materialise(ctx);
+    if (st != PD_OK) return st;
+    const InstDev& d = ctx->dev[inst];
+    PD_HIP(hipMemcpyAsync(host, d.state[ctx->cur], 8 * Nc * W, hipMemcpyDeviceToHost, ctx->stream));
+    PD_HIP(hipMemcpyAsync((char*)host + 8 * Nc * W, d.K[ctx->cur], 8 * Nc, hipMemcpyDeviceToHost,
+                          ctx->stream));
+    PD_HIP(hipStreamSynchronize(ctx->stream));
+    return PD_OK;
+}
+
+pd_status pd_set_population(pd_ctx* ctx, int32_t inst, const void* host, size_t bytes)
+{
+    pd_status st = check_inst(ctx, inst);
+    if (st != PD_OK) return st;
+    const pd_params& p = ctx->params[inst];
+    const size_t Nc = (size_t)p.Nc, W = (size_t)words_of(p.L);
+    if (!host || bytes < 8 * Nc * (W + 1)) return fail(ctx, PD_ENOMEM, "host buffer too small");
+    const uint64_t* words = (const uint64_t*)host;
+    for (size_t j = 0; j < Nc; ++j) {
+        int cnt = 0;
+        for (size_t w = 0; w < W; ++w) {
+            uint64_t v = words[w * Nc + j];
+            const int hi_bits = p.L - 64 * (int)w;
+            if (hi_bits < 64 && (v >> hi_bits) != 0)
+                return fail(ctx, PD_EINVAL, "state has a bit set at or beyond site L");
+            cnt += __builtin_popcountll(v);
+        }
+        if (cnt != p.N) return fail(ctx, PD_EINVAL, "state does not hold N particles");
+    }
+    st = materialise(ctx);   // keep the other instances' populations in slot order
+    if (st != PD_OK) return st;
+    const InstDev& d = ctx->dev[inst];
+    PD_HIP(hipMemcpyAsync(d.state[ctx->cur], host, 8 * Nc * W, hipMemcpyHostToDevice, ctx->stream));
+    PD_HIP(hipMemcpyAsync(d.K[ctx->cur], (const char*)host + 8 * Nc * W, 8 * Nc,
+                          hipMemcpyHostToDevice, ctx->stream));
+    PD_HIP(hipStreamSynchronize(ctx->stream));
+    ctx->stepped = false;
+    ctx->anc_valid = false;
+    return PD_OK;
+}
+
+pd_status pd_get_step_outputs(pd_ctx* ctx, int32_t inst, uint32_t* Kb, double* A, double* ell)
+{
+    pd_status st = check_inst(ctx, inst);
+    if (st != PD_OK) return st;
+    const InstDev& d = ctx->dev[inst];
+    const size_t Nc = (size_t)ctx->params[inst].Nc;
+    if (Kb) PD_HIP(hipMemcpyAsync(Kb, d.Kb, 4 * Nc, hipMemcpyDeviceToHost, ctx->stream));
+    if (A) PD_HIP(hipMemcpyAsync(A, d.A, 8 * Nc, hipMemcpyDeviceToHost, ctx->stream));
+    if (ell) PD_HIP(hipMemcpyAsync(ell, d.ell, 8 * Nc, hipMemcpyDeviceToHost, ctx->stream));
+    PD_HIP(hipStreamSynchronize(ctx->stream));
+    return PD_OK;
+}
+
+pd_status pd_get_ancestors(pd_ctx* ctx, int32_t inst, int32_t* anc)
+{
+    pd_status st = check_inst(ctx, inst);
+    if (st != PD_OK) return st;
+    if (!ctx->anc_valid) return fail(ctx, PD_ESTATE, "no cloning stage since the last step");
+    if (!anc) return fail(ctx, PD_EINVAL, "null output");
+    const InstDev& d = ctx->dev[inst];
+    PD_HIP(hipMemcpyAsync(anc, d.anc, 4 * (size_t)ctx->params[inst].Nc, hipMemcpyDeviceToHost,
+                          ctx->stream));
+    PD_HIP(hipStreamSynchronize(ctx->stream));
+    return PD_OK;
+}
+
+pd_status pd_get_log(pd_ctx* ctx, int32_t inst, double* lbeta, double* mean_kb, int32_t n_rows)
+{
+    pd_status st = check_inst(ctx, inst);
+    if (st != PD_OK) return st;
+    const pd_params& p = ctx->params[inst];
+    if (n_rows < 0 || n_rows > p.log_cycles) return fail(ctx, PD_EINVAL, "n_rows exceeds log_cycles");
+    if (n_rows == 0) return PD_OK;
+    std::vector<double> buf(2 * (size_t)n_rows);
+    PD_HIP(hipMemcpyAsync(buf.data(), ctx->dev[inst].log, buf.size() * 8, hipMemcpyDeviceToHost,
+                          ctx->stream));
+    PD_HIP(hipStreamSynchronize(ctx->stream));
+    for (int r = 0; r < n_rows; ++r) {
+        if (lbeta) lbeta[r] = buf[2 * r];
+        if (mean_kb) mean_kb[r] = buf[2 * r + 1];
+    }
+    return PD_OK;
+}
+
+// Checkpoint: magic, n, host beta, then per instance: InstCtl, population image.
+static const uint64_t kMagic = 0x31315044434c4e31ull;
+
+pd_status pd_save_bytes(pd_ctx* ctx, size_t* bytes)
+{
+    if (!ctx || !bytes) return PD_EINVAL;
+    size_t b = 3 * 8;
+    for (const auto& p : ctx->params)
+        b += sizeof(InstCtl) + 8 * (size_t)p.Nc * (size_t)(words_of(p.L) + 1);
+    *bytes = b;
+    return PD_OK;
+}
+
+pd_status pd_save(pd_ctx* ctx, void* host, size_t bytes)
+{
+    size_t need = 0;
+    pd_status st = pd_save_bytes(ctx, &need);
+    if (st != PD_OK) return st;
+    if (ctx->stepped) return fail(ctx, PD_ESTATE, "save between pd_step and pd_resample");
+    if (!host || bytes < need) return fail(ctx, PD_ENOMEM, "host buffer too small");
+    st = materialise(ctx);
+    if (st != PD_OK) return st;
+    uint64_t* h = (uint64_t*)host;
+    h[0] = kMagic;
+    h[1] = (uint64_t)ctx->n;
+    h[2] = (uint64_t)ctx->beta;
+    char* at = (char*)host + 24;
+    for (int i = 0; i < ctx->n; ++i) {
+        const InstDev& d = ctx->dev[i];
+        const size_t Nc = (size_t)ctx->params[i].Nc, W = (size_t)words_of(ctx->params[i].L);
+        PD_HIP(hipMemcpyAsync(at, d.ctl, sizeof(InstCtl), hipMemcpyDeviceToHost, ctx->stream));
+        at += sizeof(InstCtl);
+        PD_HIP(hipMemcpyAsync(at, d.state[ctx->cur], 8 * Nc * W, hipMemcpyDeviceToHost, ctx->stream));
+        at += 8 * Nc * W;
+        PD_HIP(hipMemcpyAsync(at, d.K[ctx->cur], 8 * Nc, hipMemcpyDeviceToHost, ctx->stream));
+        at += 8 * Nc;
+    }
+    PD_HIP(hipStreamSynchronize(ctx->stream));
+    return PD_OK;
+}
+
+pd_status pd_load(pd_ctx* ctx, const void* host, size_t bytes)
+{
+    size_t need = 0;
+    pd_status st = pd_save_bytes(ctx, &need);
+    if (st != PD_OK) return st;
+    if (!host || bytes < need) return fail(ctx, PD_ENOMEM, "checkpoint too small");
+    const uint64_t* h = (const uint64_t*)host;
+    if (h[0] != kMagic || h[1] != (uint64_t)ctx->n)
+        return fail(ctx, PD_EINVAL, "not a checkpoint of this configuration");
+    const char* at = (const char*)host + 24;
+    for (int i = 0; i < ctx->n; ++i) {
+        const InstDev& d = ctx->dev[i];
+        const size_t Nc = (size_t)ctx->params[i].Nc, W = (size_t)words_of(ctx->params[i].L);
+        PD_HIP(hipMemcpyAsync(d.ctl, at, sizeof(InstCtl), hipMemcpyHostToDevice, ctx->stream));
+        at += sizeof(InstCtl);
+        PD_HIP(hipMemcpyAsync(d.state[ctx->cur], at, 8 * Nc * W, hipMemcpyHostToDevice, ctx->stream));
+        at += 8 * Nc * W;
+        PD_HIP(hipMemcpyAsync(d.K[ctx->cur], at, 8 * Nc, hipMemcpyHostToDevice, ctx->stream));
+        at += 8 * Nc;
+    }
+    PD_HIP(hipStreamSynchronize(ctx->stream));
+    ctx->beta = (int64_t)h[2];
+    ctx->perm = false;
+    ctx->stepped = false;
+    ctx->anc_valid = false;
+    return PD_OK;
+}
+
+pd_status pd_set_guide(pd_ctx* ctx, const float* d_table, size_t n)
+{
+    if (!ctx) return PD_EINVAL;
+    (void)d_table;
+    (void)n;
+    return fail(ctx, PD_EUNSUPPORTED, "guided weights are not available in this build");
+}
+
+const char* pd_last_error(const pd_ctx* ctx)
+{
+    return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+const char* pd_status_str(pd_status s)
+{
+    switch (s) {
+        case PD_OK: return "ok";
+        case PD_EINVAL: return "invalid argument";
+        case PD_ENOMEM: return "buffer too small";
+        case PD_EDEVICE: return "device error";
+        case PD_ESTATE: return "call out of order";
+        case PD_EUNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,63 @@
+// Device-side data structures shared by the kernels and the host runtime of
+// the library.  Internal: not part of the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pd {
+
+constexpr int kTile = 256;          // clones per tile = threads per block
+constexpr int kMaxWords = 8;        // 64-site words per state
+constexpr int kMaxSites = 512;      // L <= kMaxSites
+
+enum : uint32_t { TAG_INIT = 1, TAG_DYN = 2, TAG_RESAMPLE = 3, TAG_IID = 4 };
+enum : int32_t { MODE_MODIFIED = 0, MODE_DIRECT = 1, MODE_GUIDED = 2 };
+enum : int32_t { SEL_EQ = 0, SEL_IID = 1 };
+
+// Mutable per-instance state that lives in device memory, so that captured
+// graphs advance it on every replay.
+struct InstCtl {
+    int64_t beta;          // completed cycles
+    uint32_t tiles_done;   // step kernel: tiles finished this interval
+    uint32_t tiles_done2;  // resample kernel: tiles finished this interval
+    double lmax;           // max_i ln Ups_i of the current interval
+    double lbeta;          // ln mean Ups of the current interval
+    double psi_sum, psi_comp;    // Neumaier sum of lbeta over all intervals
+    double psib_sum, psib_comp;  // ... over intervals beyond burn_in
+    uint64_t hops;         // hops performed so far
+    uint64_t ksum;         // scratch: sum of K over the population (estimates)
+    uint64_t pad_[4];
+};
+
+// Per-instance descriptor (written by the host at creation, read-only after).
+struct InstDev {
+    int32_t L, N, W, mode;
+    int32_t selection, ntiles, log_cycles, pad0;
+    uint32_t key0, key1, tag_hi, pad1;
+    double s, es, c, dt;
+    int64_t Nc, burn_in;
+    uint64_t* state[2];    // [W][Nc] words, two buffers
+    uint64_t* K[2];        // [Nc] accumulated hops, two buffers
+    uint32_t* Kb;          // [Nc] hops of the last interval
+    double* A;             // [Nc] integral of r dt over the last interval
+    double* ell;           // [Nc] ln Ups of the last interval
+    int32_t* anc;          // [Nc] ancestor map of the last cloning stage
+    double* ykey;          // [Nc] interval ends in spacing units ([iid] only)
+    double* tile_max;      // [ntiles]
+    double* tile_sum;      // [ntiles] sum of exp(ell - tile_max)
+    uint64_t* tile_hops;   // [ntiles]
+    double* tile_off;      // [ntiles + 1] exclusive prefix of the tile sums, scale lmax
+    const double* inv_rate;// [L + 1] 1 / (total hop rate) for r = 0..L
+    double* log;           // [log_cycles][2] (lbeta, mean K^beta)
+    const float* guide;    // [8192] guide table (guided mode)
+    InstCtl* ctl;
+};
+
+struct TileDesc {
+    int32_t inst;          // instance index
+    int32_t tile;          // tile index within the instance
+    int32_t first;         // first clone slot
+    int32_t count;         // clones in the tile (<= kTile)
+};
+
+}  // namespace pd

@@ -1,0 +1,66 @@
+"""The C-ABI library loads and exports every function include/pd.h declares;
+host-side validation (no GPU needed: these calls queue no device work)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1711_05095_amd import pd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    text = open(os.path.join(ROOT, "include", "pd.h")).read()
+    return sorted(set(re.findall(r"^(?:pd_status|const char\*)\s+(pd_\w+)\(", text, re.M)))
+
+
+def test_header_and_binding_agree():
+    assert declared() == sorted(pd.EXPORTS)
+
+
+def test_library_exports_every_symbol():
+    lib = pd.lib()
+    for name in declared():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings():
+    assert pd.lib().pd_status_str(pd.PD_EINVAL) == b"invalid argument"
+
+
+def good(**kw):
+    base = dict(L=100, N=50, s=0.002, Nc=100_000, t_obs=2000.0, dt=0.5)
+    base.update(kw)
+    return pd.make_params(**base)
+
+
+def test_workspace_bytes_scales():
+    small = pd.pd_workspace_bytes(good(Nc=1000))
+    big = pd.pd_workspace_bytes(good())
+    assert big > 90 * small
+    batch = pd.pd_workspace_bytes([good(), good(L=400, N=200)])
+    assert batch > big
+
+
+@pytest.mark.parametrize("kw", [dict(L=1), dict(L=513), dict(N=-1), dict(N=101),
+                                dict(s=float("nan")), dict(s=701.0), dict(s=-30.0), dict(dt=1e6, t_obs=1e6), dict(Nc=0), dict(Nc=2**31),
+                                dict(dt=0.0), dict(t_obs=-1.0), dict(t_obs=1000.25, dt=0.5),
+                                dict(selection=7), dict(weight_mode=9),
+                                dict(instance=1 << 24), dict(log_cycles=-1), dict(burn_in=-2)])
+def test_invalid_parameters_rejected(kw):
+    with pytest.raises(pd.PdError) as e:
+        pd.pd_workspace_bytes(good(**kw))
+    assert e.value.status == pd.PD_EINVAL
+
+
+def test_create_rejects_without_device_work():
+    p = good()
+    arr = (pd.PdParams * 1)(p)
+    ctx = ctypes.c_void_p()
+    # null workspace: rejected before anything touches the GPU
+    assert pd.lib().pd_create(arr, 1, None, 0, None, ctypes.byref(ctx)) == pd.PD_EINVAL
+    # misaligned workspace pointer
+    assert pd.lib().pd_create(arr, 1, ctypes.c_void_p(8), 1 << 40, None,
+                              ctypes.byref(ctx)) == pd.PD_EINVAL

@@ -1,0 +1,295 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Integer results (occupancies, hop counts, accumulated K, ancestor maps) must be
+bit-identical for identical Philox counters; floating-point results (the
+integral of r dt, ln Upsilon, psi-hat) agree to 1e-12 relative per interval
+and 1e-9 relative on a whole run.  The only allowed integer difference is a
+selection decided by a point within rounding (1e-9 of the spacing) of an
+interval end, which the tests certify case by case (the GPU sums the weights
+in a tiled order, the oracle sequentially).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from layout import pack, unpack
+from oracle import ed
+from paper_1711_05095_amd import inputs, pd
+
+pytestmark = pytest.mark.gpu
+
+MOD, DIR = pd.PD_W_MODIFIED, pd.PD_W_DIRECT
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pd.lib()  # raises if the library is not built
+
+
+def make(L, N, s, Nc, dt, M=1, seed=0, mode=MOD, sel=pd.PD_SEL_EQ, instance=0, log_cycles=0,
+         burn_in=0):
+    p = pd.make_params(L, N, s, Nc, M * dt, dt, seed=seed, selection=sel, weight_mode=mode,
+                       instance=instance, log_cycles=log_cycles, burn_in=burn_in)
+    o = oracle.Oracle(L, N, s, Nc, dt, M=M, seed=seed, instance=instance, mode=mode,
+                      selection=sel, burn_in=burn_in)
+    return p, o
+
+
+def check_selection(anc_gpu, ell, d, what):
+    """GPU ancestor map == oracle selection on the same log-weights, except at
+    certified near-ties."""
+    anc_o, lm = oracle.select(ell, d=d)
+    diff = np.nonzero(anc_gpu != anc_o)[0]
+    if diff.size:
+        w = np.exp(ell - ell.max())
+        y = np.cumsum(w) * len(ell) / w.sum()
+        for j in diff:
+            near = np.min(np.abs(y - (j + d)))
+            assert near < 1e-9 * max(1.0, j), (what, j, anc_gpu[j], anc_o[j], near)
+    assert diff.size <= 2, (what, diff.size)
+    return lm
+
+
+INIT_CASES = [(10, 5, 1000), (2, 1, 7), (64, 32, 300), (65, 20, 257), (100, 50, 1000),
+              (128, 64, 513), (400, 200, 600), (512, 100, 256), (30, 0, 100), (30, 30, 100),
+              (13, 6, 1)]
+
+
+@pytest.mark.parametrize("L,N,Nc", INIT_CASES)
+def test_init_bit_exact(L, N, Nc):
+    print(f"init L={L} N={N} Nc={Nc}", flush=True)
+    p, o = make(L, N, 0.1, Nc, 0.5, seed=77 + L)
+    S = pd.Sampler(p)
+    words, K = S.get_population()
+    occ, K0 = o.init()
+    assert np.array_equal(words, pack(occ))
+    assert np.array_equal(K, K0)
+
+
+STEP_CASES = [
+    (10, 5, 0.4, MOD, 0.1, 1000), (10, 5, -0.4, DIR, 0.1, 1000), (10, 5, 0.0, MOD, 3.0, 300),
+    (100, 50, 0.002, MOD, 0.5, 1000), (100, 50, -0.001, DIR, 0.5, 700),
+    (65, 30, -0.1, MOD, 1.0, 777), (64, 63, 0.2, MOD, 1.0, 256), (128, 1, 0.3, DIR, 2.0, 300),
+    (400, 200, 1.25e-4, MOD, 1.0, 300), (512, 256, 0.0, DIR, 0.3, 256),
+    (2, 1, 0.3, MOD, 2.0, 64), (3, 1, -0.2, MOD, 1.5, 65), (20, 0, 0.5, MOD, 1.0, 50),
+    (20, 20, 0.5, DIR, 1.0, 50), (13, 6, 0.7, MOD, 5.0, 1),
+]
+
+
+@pytest.mark.parametrize("L,N,s,mode,dt,Nc", STEP_CASES)
+def test_one_cycle_bit_exact(L, N, s, mode, dt, Nc):
+    print(f"step L={L} N={N} s={s} mode={mode} dt={dt} Nc={Nc}", flush=True)
+    p, o = make(L, N, s, Nc, dt, M=4, seed=1234, mode=mode, instance=5)
+    S = pd.Sampler(p)
+    occ = inputs.random_population(L, N, Nc, seed=L * 1000 + Nc)
+    K = inputs.random_counts(Nc, seed=Nc)
+    S.set_population(pack(occ), K)
+    S.step()
+    w_gpu, K_gpu = S.get_population()
+    Kb_g, A_g, ell_g = S.step_outputs()
+
+    occ_o, K_o = occ.copy(), K.copy()
+    Kb_o, A_o, ell_o = o.step(1, occ_o, K_o)
+    assert np.array_equal(Kb_g, Kb_o)
+    assert np.array_equal(w_gpu, pack(occ_o))
+    assert np.array_equal(K_gpu, K_o)
+    assert np.allclose(A_g, A_o, rtol=1e-12, atol=1e-300)
+    assert np.allclose(ell_g, ell_o, rtol=1e-12, atol=1e-300)
+
+    S.resample()
+    anc = S.ancestors()
+    assert np.all(np.diff(anc) >= 0) and anc.min() >= 0 and anc.max() < Nc
+    lm = check_selection(anc, ell_g, o.eq_offset(1), "cycle 1")
+    w2, K2 = S.get_population()
+    assert np.array_equal(w2, w_gpu[:, anc]) and np.array_equal(K2, K_gpu[anc])
+    e = S.estimates()
+    assert e["cycles"] == 1 and e["hops"] == int(Kb_o.sum())
+    assert e["psi"] * dt == pytest.approx(lm, rel=1e-12, abs=1e-15)
+
+
+@pytest.mark.parametrize("L,N,s,mode,Nc", [(10, 5, 0.4, MOD, 1000), (10, 5, -0.3, DIR, 600),
+                                           (100, 50, 0.003, MOD, 1500), (200, 100, -0.0005, MOD, 513)])
+def test_lockstep_cycles(L, N, s, mode, Nc):
+    """Many cycles through the fused gather: every interval's state, K and
+    ancestor map equal the oracle's."""
+    print(f"lockstep L={L} s={s} mode={mode} Nc={Nc}", flush=True)
+    dt = 0.1 if L == 10 else 0.5
+    M = 25
+    p, o = make(L, N, s, Nc, dt, M=M, seed=99, mode=mode)
+    S = pd.Sampler(p)
+    occ, K = o.init()
+    for beta in range(1, M + 1):
+        S.step()
+        Kb_o, A_o, ell_o = o.step(beta, occ, K)
+        w_gpu, K_gpu = S.get_population()
+        assert np.array_equal(w_gpu, pack(occ)), beta
+        assert np.array_equal(K_gpu, K), beta
+        S.resample()
+        anc = S.ancestors()
+        check_selection(anc, ell_o, o.eq_offset(beta), "interval %d" % beta)
+        occ, K = np.ascontiguousarray(occ[anc]), K[anc]   # identical unless a certified near-tie
+    assert S.estimates()["cycles"] == M
+
+
+@pytest.mark.parametrize("s,mode", [(-0.4, MOD), (0.4, MOD), (0.2, DIR), (-0.2, DIR)])
+def test_whole_run_psi(s, mode):
+    w = inputs.SMALL
+    M = int(round(w["t_obs"] / w["dt"]))
+    print(f"whole run s={s} mode={mode}", flush=True)
+    p, o = make(w["L"], w["N"], s, w["Nc"], w["dt"], M=M, seed=w["seed0"], mode=mode)
+    S = pd.Sampler(p)
+    S.run(M)
+    e = S.estimates()
+    r = o.run()
+    assert e["cycles"] == M
+    assert e["hops"] == r["hops"]
+    assert e["psi"] == pytest.approx(r["psi"], rel=1e-9)
+    assert e["k_hat"] == pytest.approx(r["k_hat"], rel=1e-12)
+
+
+@pytest.mark.parametrize("mode", [MOD, DIR])
+def test_zero_bias_exact_identity(mode):
+    p, _ = make(10, 5, 0.0, 1000, 0.1, M=200, seed=3, mode=mode)
+    S = pd.Sampler(p)
+    S.run(199)
+    S.step()
+    S.resample()
+    assert np.array_equal(S.ancestors(), np.arange(1000, dtype=np.int32))
+    e = S.estimates()
+    assert e["psi"] == 0.0 and e["cycles"] == 200
+
+
+def test_graph_run_equals_stepwise_and_checkpoint():
+    L, N, Nc, M = 100, 50, 2000, 40
+    p, _ = make(L, N, 0.0015, Nc, 0.5, M=M, seed=5)
+    A = pd.Sampler(p)
+    A.run(M)                       # graph replays
+    B = pd.Sampler(p)
+    for _ in range(M):             # single launches
+        B.step()
+        B.resample()
+    ea, eb = A.estimates(), B.estimates()
+    assert ea == eb
+    wa, Ka = A.get_population()
+    wb, Kb = B.get_population()
+    assert np.array_equal(wa, wb) and np.array_equal(Ka, Kb)
+    # checkpoint half way, restore into a fresh context, continue
+    C = pd.Sampler(p)
+    C.run(M // 2)
+    blob = C.save()
+    D = pd.Sampler(p)
+    D.load(blob)
+    D.run(M - M // 2)
+    assert D.estimates() == ea
+    wd, Kd = D.get_population()
+    assert np.array_equal(wd, wa) and np.array_equal(Kd, Ka)
+
+
+def test_batch_equals_separate():
+    specs = [(10, 5, 0.3, 1000, 0.1), (100, 50, 0.002, 3000, 0.5), (400, 200, 1e-4, 700, 1.0),
+             (65, 32, -0.05, 257, 0.5)]
+    M = 12
+    params = [pd.make_params(L, N, s, Nc, M * dt, dt, seed=40 + i, instance=i)
+              for i, (L, N, s, Nc, dt) in enumerate(specs)]
+    B = pd.Sampler(params)
+    B.run(M)
+    for i, q in enumerate(params):
+        S = pd.Sampler(q)
+        S.run(M)
+        assert S.estimates() == B.estimates(i)
+        ws, Ks = S.get_population()
+        wb, Kb = B.get_population(i)
+        assert np.array_equal(ws, wb) and np.array_equal(Ks, Kb)
+
+
+def test_small_workload_matches_exact_diagonalisation():
+    """All 9 biases x 16 seeds of the L=10 workload as one batch; the mean of
+    psi-hat over seeds is within 3 sigma of (1/t_obs) ln Z(s, t_obs)."""
+    w = inputs.SMALL
+    M = int(round(w["t_obs"] / w["dt"]))
+    R = 16
+    params = []
+    for si, s in enumerate(w["s_values"]):
+        for r in range(R):
+            params.append(pd.make_params(w["L"], w["N"], s, w["Nc"], w["t_obs"], w["dt"],
+                                         seed=w["seed0"] + r, instance=si))
+    B = pd.Sampler(params)
+    B.run(M)
+    for si, s in enumerate(w["s_values"]):
+        psis = np.array([B.estimates(si * R + r)["psi"] for r in range(R)])
+        target = ed.finite_time_scgf(w["L"], w["N"], s, w["t_obs"])
+        sig = psis.std(ddof=1) / np.sqrt(R)
+        assert abs(psis.mean() - target) < 3 * sig + 2e-4, (s, psis.mean(), target, sig)
+        if s == 0.0:
+            assert np.all(psis == 0.0)
+
+
+def test_edge_fillings_and_single_particle():
+    for N in (0, 12):
+        p, _ = make(12, N, 0.5, 300, 0.5, M=20, seed=1)
+        S = pd.Sampler(p)
+        S.run(20)
+        e = S.estimates()
+        assert e["psi"] == 0.0 and e["hops"] == 0 and e["k_hat"] == 0.0
+    s = 0.3
+    p, _ = make(10, 1, s, 500, 0.1, M=100, seed=2)
+    S = pd.Sampler(p)
+    S.run(100)
+    assert S.estimates()["psi"] == pytest.approx(2 * (np.exp(-s) - 1), abs=1e-12)
+
+
+def test_call_order_and_validation():
+    p, _ = make(10, 5, 0.1, 100, 0.1, M=10)
+    S = pd.Sampler(p)
+    with pytest.raises(pd.PdError) as e:
+        S.resample()
+    assert e.value.status == pd.PD_ESTATE
+    S.step()
+    with pytest.raises(pd.PdError) as e:
+        S.step()
+    assert e.value.status == pd.PD_ESTATE
+    with pytest.raises(pd.PdError) as e:
+        S.ancestors()
+    assert e.value.status == pd.PD_ESTATE
+    S.resample()
+    bad = pack(inputs.random_population(10, 4, 100, 0))
+    with pytest.raises(pd.PdError) as e:
+        S.set_population(bad, np.zeros(100, np.uint64))
+    assert e.value.status == pd.PD_EINVAL
+
+
+@pytest.mark.parametrize("L,N,lam,Nc,dt", [(100, 50, 20.0, 100_000, 0.5),
+                                           (400, 200, 20.0, 1_000_000, 1.0)])
+def test_full_size_sampled(L, N, lam, Nc, dt):
+    """At the full workload sizes: one cycle from a GPU-evolved population,
+    2000 sampled clones stepped by the oracle; the whole selection checked
+    against the oracle's on the GPU's log-weights."""
+    print(f"full size L={L} Nc={Nc}", flush=True)
+    s = inputs.s_of_lambda(lam, L)
+    p, o = make(L, N, s, Nc, dt, M=10, seed=2024)
+    S = pd.Sampler(p)
+    S.run(3)
+    words, K = S.get_population()
+    rng = np.random.default_rng(0)
+    slots = np.sort(rng.choice(Nc, 2000, replace=False))
+    occ_s = unpack(words[:, slots], L)
+    K_s = K[slots].copy()
+    assert np.all(occ_s.sum(axis=1) == N)
+    S.step()
+    w_gpu, K_gpu = S.get_population()
+    Kb_g, A_g, ell_g = S.step_outputs()
+    Kb_o, A_o, ell_o = o.step_slots(4, slots, occ_s, K_s)
+    assert np.array_equal(Kb_g[slots], Kb_o)
+    assert np.array_equal(w_gpu[:, slots], pack(occ_s))
+    assert np.array_equal(K_gpu[slots], K_s)
+    assert np.allclose(ell_g[slots], ell_o, rtol=1e-12, atol=1e-300)
+    S.resample()
+    anc = S.ancestors()
+    check_selection(anc, ell_g, o.eq_offset(4), "full size")
+    counts = np.bincount(anc, minlength=Nc)
+    wgt = np.exp(ell_g - ell_g.max())
+    mean = Nc * wgt / wgt.sum()
+    assert np.all(counts >= np.floor(mean - 1e-6)) and np.all(counts <= np.ceil(mean + 1e-6))
