@@ -10,6 +10,7 @@ in a tiled order, the oracle sequentially).
 """
 import numpy as np
 import pytest
+import torch
 
 import oracle
 from layout import pack, unpack
@@ -23,7 +24,6 @@ MOD, DIR = pd.PD_W_MODIFIED, pd.PD_W_DIRECT
 
 @pytest.fixture(scope="module", autouse=True)
 def _gpu():
-    import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     pd.lib()  # raises if the library is not built
