@@ -1,0 +1,164 @@
+"""Throughput of the cloning algorithm on one MI355X: clone-hops per second.
+
+Workload (the L=100 transition sweep): periodic SSEP with L=100, N=50, 32
+scaled biases lambda = s L^2 evenly spaced over [-10, 20], Nc = 1e5 clones
+each, Delta t = 0.5, t_obs = 2000 (4000 cloning intervals), [eq] selection,
+modified (e^{-s}-scaled) dynamics, uniform random initial configurations,
+Philox seeds 2000 + i.  All 32 instances run as one batch: one step = one
+cloning interval of the whole sweep (the dynamical stage of 3.2e6 clones,
+then the cloning stage of each instance).  The reported value is the number of
+hops performed in the timed steps divided by their wall time; the cloning
+stage is inside the timed region.
+
+Usage: python bench.py [--steps K] [--warmup W] [--nc NC] [--no-cpu-baseline]
+By default W + K = 4000 so that the run covers exactly t_obs = 2000.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_1711_05095_amd import inputs, pd  # noqa: E402
+
+# Published MI355X figures (vector ALU): 256 CUs x 64 lanes x 2.4 GHz.
+PEAK_VALU_LANE_OPS = 256 * 64 * 2.4e9
+PEAK_HBM_GBS = 8000.0
+# VALU instructions on the main path of one event of the step kernel (W = 2):
+# counted from the kernel's gfx950 assembly, see the design notes.
+VALU_PER_EVENT_W2 = 175
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=16)
+    ap.add_argument("--nc", type=int, default=100_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-cycles", type=int, default=8)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (for PMC byte-counter scaling)")
+    a = ap.parse_args()
+    if a.steps is None:
+        M = int(round(inputs.SWEEP["t_obs"] / inputs.SWEEP["dt"]))
+        a.steps = max(1, M - a.warmup)
+    return a
+
+
+def calibrate_copy():
+    import torch
+    n = 1 << 30
+    src = torch.empty(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n}), flush=True)
+
+
+def cpu_baseline(nc, cycles):
+    """The test oracle (plain single-threaded C) on a bounded sample of the
+    same workload: instance lambda = 20, Nc clones, `cycles` intervals."""
+    import oracle
+    w = inputs.SWEEP
+    s = inputs.s_of_lambda(20.0, w["L"])
+    o = oracle.Oracle(w["L"], w["N"], s, nc, w["dt"], M=cycles, seed=w["seed0"])
+    t0 = time.perf_counter()
+    r = o.run()
+    dt = time.perf_counter() - t0
+    return {"value": r["hops"] / dt, "unit": "clone-hops/s", "cores": 1, "kind": "oracle",
+            "sample": "lambda=20 instance of the sweep, Nc=%d, %d intervals (%d hops, "
+                      "init included), %.1f s" % (nc, cycles, r["hops"], dt)}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    if a.calibrate_copy:
+        calibrate_copy()
+        return
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w = inputs.SWEEP
+    L, N, dt = w["L"], w["N"], w["dt"]
+    total = a.warmup + a.steps
+    params = [pd.make_params(L, N, inputs.s_of_lambda(lam, L), a.nc, total * dt, dt,
+                             seed=w["seed0"] + i, instance=i)
+              for i, lam in enumerate(w["lambdas"])]
+    S = pd.Sampler(params)
+    st = S.stream
+
+    for _ in range(a.warmup):
+        S.step()
+        S.resample()
+    torch.cuda.synchronize()
+    hops0 = sum(S.estimates(i)["hops"] for i in range(S.n))
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(a.steps):
+        ev[k][0].record(st)
+        S.step()
+        ev[k][1].record(st)
+        S.resample()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    est = [S.estimates(i) for i in range(S.n)]
+    hops = sum(e["hops"] for e in est) - hops0
+    step_ms = np.array([s_.elapsed_time(e_) for s_, e_ in ev])
+    value = hops / elapsed
+    # events of the step kernel = hops + one closing draw per clone per interval
+    events_per_launch = (hops + a.steps * a.nc * S.n) / a.steps
+    step_s = float(step_ms.mean()) / 1e3
+    achieved = events_per_launch * VALU_PER_EVENT_W2 / step_s
+
+    out = {
+        "metric": "clone-hops/s",
+        "value": value,
+        "unit": "clone-hops/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": elapsed / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "L=100 N=50 transition sweep: 32 lambdas in [-10,20], "
+                               "Nc=%d each, dt=0.5, t_obs=%g, [eq], modified dynamics, "
+                               "one batch" % (a.nc, total * dt),
+                   "instances": S.n, "Nc": a.nc, "L": L, "N": N, "dt": dt,
+                   "intervals": total},
+        "roofline": {"bound": "alu", "kernel": "k_step<2>",
+                     "achieved": achieved / 1e12, "peak": PEAK_VALU_LANE_OPS / 1e12,
+                     "unit": "T VALU lane-instr/s", "frac": achieved / PEAK_VALU_LANE_OPS,
+                     "traffic": None,
+                     "per_unit": "%d VALU instr per event" % VALU_PER_EVENT_W2,
+                     "events_per_launch": events_per_launch,
+                     "step_ms_mean": float(step_ms.mean()),
+                     "step_ms_median": float(np.median(step_ms))},
+        "physics": {"lambda": w["lambdas"][::8],
+                    "psi": [est[i]["psi"] for i in range(0, S.n, 8)],
+                    "k_hat": [est[i]["k_hat"] for i in range(0, S.n, 8)]},
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(a.nc, a.cpu_cycles)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
