@@ -29,9 +29,14 @@ from paper_1711_05095_amd import inputs, pd  # noqa: E402
 # Published MI355X figures (vector ALU): 256 CUs x 64 lanes x 2.4 GHz.
 PEAK_VALU_LANE_OPS = 256 * 64 * 2.4e9
 PEAK_HBM_GBS = 8000.0
-# VALU instructions on the main path of one event of the step kernel (W = 2):
-# counted from the kernel's gfx950 assembly, see the design notes.
-VALU_PER_EVENT_W2 = 175
+# VALU instructions in one pass of the event loop of the step kernel (W = 2),
+# counted from its gfx950 assembly by paper_1711_05095_amd.isa_count (a test
+# keeps this constant equal to that count).
+VALU_PER_EVENT_W2 = 215
+# HBM bytes the cloning stage must move per clone: ln Ups read (8) by the
+# resample scan, ancestor written (4); the gather of the states is fused into
+# the next dynamical stage's load.
+RESAMPLE_BYTES_PER_CLONE = 12
 
 
 def parse():
@@ -42,6 +47,9 @@ def parse():
     ap.add_argument("--nc", type=int, default=100_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cycles", type=int, default=8)
+    ap.add_argument("--variant", type=int, default=None,
+                    help="step kernel variant (default: chosen by the autotuner)")
+    ap.add_argument("--refill", type=int, default=8)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (for PMC byte-counter scaling)")
     a = ap.parse_args()
@@ -98,14 +106,18 @@ def main():
     S = pd.Sampler(params)
     st = S.stream
 
+    if a.variant is None:
+        tuning = S.autotune(3)           # restores the population afterwards
+    else:
+        S.set_tuning(a.variant, a.refill, 16)
+        tuning = S.tuning()
     for _ in range(a.warmup):
         S.step()
         S.resample()
     torch.cuda.synchronize()
     hops0 = sum(S.estimates(i)["hops"] for i in range(S.n))
 
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(a.steps)]
+    ev = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(a.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(a.steps):
@@ -113,12 +125,15 @@ def main():
         S.step()
         ev[k][1].record(st)
         S.resample()
+        ev[k][2].record(st)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
     est = [S.estimates(i) for i in range(S.n)]
     hops = sum(e["hops"] for e in est) - hops0
-    step_ms = np.array([s_.elapsed_time(e_) for s_, e_ in ev])
+    step_ms = np.array([e0.elapsed_time(e1) for e0, e1, _ in ev])
+    res_ms = np.array([e1.elapsed_time(e2) for _, e1, e2 in ev])
+    res_bytes = RESAMPLE_BYTES_PER_CLONE * a.nc * S.n
     value = hops / elapsed
     # events of the step kernel = hops + one closing draw per clone per interval
     events_per_launch = (hops + a.steps * a.nc * S.n) / a.steps
@@ -151,6 +166,12 @@ def main():
                      "events_per_launch": events_per_launch,
                      "step_ms_mean": float(step_ms.mean()),
                      "step_ms_median": float(np.median(step_ms))},
+        "resample": {"bound": "hbm", "kernel": "k_resample",
+                     "achieved": res_bytes / (float(res_ms.mean()) / 1e3) / 1e9,
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": res_bytes / (float(res_ms.mean()) / 1e3) / 1e9 / PEAK_HBM_GBS,
+                     "bytes_per_launch": res_bytes, "ms_mean": float(res_ms.mean())},
+        "tuning": tuning,
         "physics": {"lambda": w["lambdas"][::8],
                     "psi": [est[i]["psi"] for i in range(0, S.n, 8)],
                     "k_hat": [est[i]["k_hat"] for i in range(0, S.n, 8)]},

@@ -183,6 +183,27 @@ pd_status pd_load(pd_ctx* ctx, const void* host, size_t bytes);
  * otherwise.  The table must outlive its use. Synchronises. */
 pd_status pd_set_guide(pd_ctx* ctx, const float* d_table, size_t n);
 
+/* Launch configuration of the dynamical stage.  It never changes results
+ * (every random number is keyed by clone slot, never by lane or block), only
+ * speed. */
+typedef struct {
+    int32_t step_variant; /* 0: one clone per lane; 1, 2, 3: persistent waves,
+                             each lane working through a queue of clones,
+                             compiled for 4, 6 and 8 waves per SIMD */
+    int32_t refill;       /* variant 1: finished lanes (1..64) that trigger a refill */
+    int32_t graph_cycles; /* cycles per captured graph in pd_run (even, 0: no graph) */
+    int32_t reserved;
+} pd_tuning;
+
+pd_status pd_get_tuning(pd_ctx* ctx, pd_tuning* out);
+pd_status pd_set_tuning(pd_ctx* ctx, const pd_tuning* tuning);
+
+/* Autotuner: times `trial_cycles` cycles of each candidate launch
+ * configuration on this context's own instances, restores the population and
+ * estimator state exactly as they were, and keeps the fastest configuration
+ * (also written to `best` if not NULL).  Synchronises. */
+pd_status pd_autotune(pd_ctx* ctx, int32_t trial_cycles, pd_tuning* best);
+
 /* Human-readable message of the last error on ctx (or of the last failed
  * pd_create when ctx is NULL). */
 const char* pd_last_error(const pd_ctx* ctx);

@@ -35,6 +35,40 @@ int words_of(int L) { return (L + 63) / 64; }
 
 int64_t cycles_of(const pd_params& p) { return llround(p.t_obs / p.dt); }
 
+pd_tuning default_tuning()
+{
+    pd_tuning t;
+    t.step_variant = 1;
+    t.refill = 8;
+    t.graph_cycles = 16;
+    t.reserved = 0;
+    return t;
+}
+
+// Table of the device logarithm (rows of [c, -ln c (multiple of 2^-42),
+// remainder, 0]) and the split of ln 2, computed in extended precision.
+std::vector<double> log_table(double* ln2_hi, double* ln2_lo)
+{
+    const long double two42 = 4398046511104.0L;
+    const long double l2 = logl(2.0L);
+    const long double l2h = nearbyintl(l2 * two42) / two42;
+    *ln2_hi = (double)l2h;
+    *ln2_lo = (double)(l2 - l2h);
+    std::vector<double> t(4 * kLogRows, 0.0);
+    for (int i = 0; i < kLogRows; ++i) {
+        const long double lo = 0.75L + (long double)i / 128.0L;
+        const long double centre = lo + 1.0L / 256.0L;
+        // the two rows touching m = 1 use c = 1 so that r = m - 1 exactly
+        const double c = (i == 31 || i == 32) ? 1.0 : (double)(1.0L / centre);
+        const long double nlc = -logl((long double)c);
+        const long double hi = nearbyintl(nlc * two42) / two42;
+        t[4 * i] = c;
+        t[4 * i + 1] = (double)hi;
+        t[4 * i + 2] = (double)(nlc - hi);
+    }
+    return t;
+}
+
 std::string validate(const pd_params& p)
 {
     if (p.L < 2 || p.L > PD_MAX_L) return "L must be in [2, 512]";
@@ -64,7 +98,7 @@ std::string validate(const pd_params& p)
 }
 
 struct Layout {
-    size_t state[2], K[2], Kb, A, ell, anc, ykey, tmax, tsum, thops, toff, inv, log, ctl;
+    size_t state[2], K[2], Kb, A, ell, anc, ykey, tmax, tsum, thops, toff, log, ctl;
     size_t end;
     int ntiles;
 };
@@ -91,7 +125,6 @@ Layout layout_of(const pd_params& p, size_t base)
     o.tsum = take(8 * (size_t)o.ntiles);
     o.thops = take(8 * (size_t)o.ntiles);
     o.toff = take(8 * ((size_t)o.ntiles + 1));
-    o.inv = take(8 * ((size_t)p.L + 1));
     o.log = take(16 * (size_t)std::max(p.log_cycles, 1));
     o.ctl = take(sizeof(InstCtl));
     o.end = at;
@@ -99,7 +132,7 @@ Layout layout_of(const pd_params& p, size_t base)
 }
 
 struct Plan {
-    size_t insts_off, tiles_off, total;
+    size_t insts_off, tiles_off, log_off, invc_off, counters_off, total;
     std::vector<Layout> lay;
     int ntiles;
 };
@@ -114,6 +147,12 @@ Plan plan_of(const pd_params* p, int n)
     pl.ntiles = nt;
     pl.tiles_off = at;
     at = align_up(at + sizeof(TileDesc) * (size_t)nt);
+    pl.log_off = at;
+    at = align_up(at + sizeof(double) * 4 * kLogRows);
+    pl.invc_off = at;
+    at = align_up(at + sizeof(double) * (kMaxSites + 1));
+    pl.counters_off = at;
+    at = align_up(at + sizeof(uint32_t) * kMaxGroups);
     for (int i = 0; i < n; ++i) {
         pl.lay.push_back(layout_of(p[i], at));
         at = pl.lay.back().end;
@@ -134,8 +173,8 @@ struct pd_ctx {
     InstDev* d_insts = nullptr;
     TileDesc* d_tiles = nullptr;
     std::vector<TileDesc> tiles;     // host copy, step order
-    struct WGroup { int W, base, count; };
-    std::vector<WGroup> groups;      // step launches, one per word count
+    std::vector<StepLaunch> steps;   // step launches, one per word count
+    pd_tuning tuning;
     bool any_iid = false;
     bool any_guided = false;
     int cur = 0;                     // buffer holding the population
@@ -165,12 +204,49 @@ pd_status fail(pd_ctx* ctx, pd_status st, const std::string& msg)
     return st;
 }
 
+// Dynamical stage of every instance and the interval statistics.
+pd_status enqueue_step(pd_ctx* ctx, int use_anc, int src)
+{
+    for (const auto& g : ctx->steps)
+        PD_HIP(launch_step(g, ctx->d_insts, ctx->d_tiles, src, use_anc, ctx->stream));
+    PD_HIP(launch_prefix(ctx->d_insts, ctx->n, ctx->stream));
+    return PD_OK;
+}
+
 pd_status enqueue_cycle(pd_ctx* ctx, int use_anc, int src)
 {
-    for (const auto& g : ctx->groups)
-        PD_HIP(launch_step(g.W, ctx->d_insts, ctx->d_tiles, g.base, g.count, src, use_anc,
-                           ctx->stream));
+    pd_status st = enqueue_step(ctx, use_anc, src);
+    if (st != PD_OK) return st;
     PD_HIP(launch_resample(ctx->d_insts, ctx->d_tiles, (int)ctx->tiles.size(), ctx->stream));
+    return PD_OK;
+}
+
+// Applies a tuning: kernel variant and grid of every step launch.
+pd_status apply_tuning(pd_ctx* ctx, const pd_tuning& t)
+{
+    if (t.step_variant < 0 || t.step_variant > 3 || t.refill < 1 || t.refill > 64 ||
+        t.graph_cycles < 0 || (t.graph_cycles & 1))
+        return fail(ctx, PD_EINVAL, "invalid tuning");
+    int dev = 0, cus = 0;
+    PD_HIP(hipGetDevice(&dev));
+    PD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    for (auto& g : ctx->steps) {
+        g.variant = t.step_variant;
+        g.refill = t.refill;
+        int per_cu = 0;
+        PD_HIP(step_occupancy(g.W, g.variant, &per_cu));
+        const int want = (g.count + 3) / 4;          // four waves per block, a tile each
+        g.blocks = std::max(1, std::min(want, std::max(1, per_cu) * std::max(1, cus)));
+    }
+    if (t.graph_cycles != ctx->tuning.graph_cycles)
+        for (auto& gx : ctx->graph)
+            if (gx) { (void)hipGraphExecDestroy(gx); gx = nullptr; }
+    // captured graphs hold the launch configuration: recapture on change
+    if (t.step_variant != ctx->tuning.step_variant || t.refill != ctx->tuning.refill)
+        for (auto& gx : ctx->graph)
+            if (gx) { (void)hipGraphExecDestroy(gx); gx = nullptr; }
+    ctx->tuning = t;
+    ctx->graph_cycles = t.graph_cycles;
     return PD_OK;
 }
 
@@ -185,7 +261,7 @@ pd_status check_inst(pd_ctx* ctx, int32_t inst)
 pd_status materialise(pd_ctx* ctx)
 {
     if (!ctx->perm) return PD_OK;
-    for (const auto& g : ctx->groups)
+    for (const auto& g : ctx->steps)
         PD_HIP(launch_gather(g.W, ctx->d_insts, ctx->d_tiles, g.base, g.count, ctx->cur,
                              ctx->stream));
     ctx->cur ^= 1;
@@ -235,7 +311,8 @@ pd_status pd_create(const pd_params* params, int32_t n, void* d_workspace, size_
     ctx->d_tiles = (TileDesc*)(ctx->ws + pl.tiles_off);
 
     // descriptors and rate tables
-    std::vector<std::vector<double>> inv(n);
+    double ln2_hi = 0.0, ln2_lo = 0.0;
+    const std::vector<double> logt = log_table(&ln2_hi, &ln2_lo);
     for (int i = 0; i < n; ++i) {
         const pd_params& p = params[i];
         const Layout& o = pl.lay[i];
@@ -265,15 +342,16 @@ pd_status pd_create(const pd_params* params, int32_t n, void* d_workspace, size_
         d.tile_sum = (double*)(b + o.tsum);
         d.tile_hops = (uint64_t*)(b + o.thops);
         d.tile_off = (double*)(b + o.toff);
-        d.inv_rate = (const double*)(b + o.inv);
+        d.inv_scale = (p.weight_mode == PD_W_MODIFIED) ? 1.0 / d.es : 1.0;
+        d.inv_count = (const double*)(b + pl.invc_off);
         d.log = (double*)(b + o.log);
         d.guide = nullptr;
         d.ctl = (InstCtl*)(b + o.ctl);
+        d.log_tab = (const double*)(b + pl.log_off);
+        d.ln2_hi = ln2_hi;
+        d.ln2_lo = ln2_lo;
+        d.next_tile = (uint32_t*)(b + pl.counters_off);
         ctx->dev.push_back(d);
-        // 1 / (total rate) for every escape count r: r e^{-s} (modified) or r
-        inv[i].assign((size_t)p.L + 1, 0.0);
-        for (int r = 1; r <= p.L; ++r)
-            inv[i][r] = 1.0 / ((p.weight_mode == PD_W_MODIFIED ? d.es : 1.0) * (double)r);
         if (p.selection == PD_SEL_IID) ctx->any_iid = true;
     }
 
@@ -300,9 +378,22 @@ pd_status pd_create(const pd_params* params, int32_t n, void* d_workspace, size_
     });
     for (size_t k = 0; k < cand.size(); ++k) {
         ctx->tiles.push_back(cand[k].t);
-        if (ctx->groups.empty() || ctx->groups.back().W != cand[k].W)
-            ctx->groups.push_back({cand[k].W, (int)k, 0});
-        ctx->groups.back().count++;
+        if (ctx->steps.empty() || ctx->steps.back().W != cand[k].W) {
+            if ((int)ctx->steps.size() == kMaxGroups) {
+                delete ctx;
+                return fail(nullptr, PD_EUNSUPPORTED, "too many distinct word counts");
+            }
+            StepLaunch sl;
+            sl.W = cand[k].W;
+            sl.variant = 0;
+            sl.base = (int)k;
+            sl.count = 0;
+            sl.blocks = 1;
+            sl.refill = 8;
+            sl.counter = (uint32_t*)(ctx->ws + pl.counters_off) + ctx->steps.size();
+            ctx->steps.push_back(sl);
+        }
+        ctx->steps.back().count++;
     }
 
     auto bail = [&](pd_status st) { g_create_error = ctx->err; delete ctx; return st; };
@@ -319,11 +410,19 @@ pd_status pd_create(const pd_params* params, int32_t n, void* d_workspace, size_
     PD_HIP_CREATE(hipMemcpyAsync(ctx->d_tiles, ctx->tiles.data(),
                                  sizeof(TileDesc) * ctx->tiles.size(), hipMemcpyHostToDevice,
                                  ctx->stream));
-    for (int i = 0; i < n; ++i)
-        PD_HIP_CREATE(hipMemcpyAsync((void*)ctx->dev[i].inv_rate, inv[i].data(),
-                                     sizeof(double) * inv[i].size(), hipMemcpyHostToDevice,
-                                     ctx->stream));
+    std::vector<double> invc(kMaxSites + 1, 0.0);
+    for (int r = 1; r <= kMaxSites; ++r) invc[r] = 1.0 / (double)r;
+    PD_HIP_CREATE(hipMemcpyAsync(ctx->ws + pl.invc_off, invc.data(), sizeof(double) * invc.size(),
+                                 hipMemcpyHostToDevice, ctx->stream));
+    PD_HIP_CREATE(hipMemcpyAsync(ctx->ws + pl.log_off, logt.data(), sizeof(double) * logt.size(),
+                                 hipMemcpyHostToDevice, ctx->stream));
     PD_HIP_CREATE(launch_init(ctx->d_insts, n, ctx->d_tiles, (int)ctx->tiles.size(), ctx->stream));
+    {
+        pd_tuning t = default_tuning();
+        ctx->tuning = t;
+        ctx->tuning.step_variant = -1;   // force the first application
+        if (apply_tuning(ctx, t) != PD_OK) return bail(PD_EDEVICE);
+    }
     // the host vectors above are pageable: wait before they go out of scope
     PD_HIP_CREATE(hipStreamSynchronize(ctx->stream));
 #undef PD_HIP_CREATE
@@ -344,9 +443,10 @@ pd_status pd_step(pd_ctx* ctx)
 {
     if (!ctx) return PD_EINVAL;
     if (ctx->stepped) return fail(ctx, PD_ESTATE, "pd_step called twice without pd_resample");
-    for (const auto& g : ctx->groups)
-        PD_HIP(launch_step(g.W, ctx->d_insts, ctx->d_tiles, g.base, g.count, ctx->cur,
-                           ctx->perm ? 1 : 0, ctx->stream));
+    {
+        pd_status st = enqueue_step(ctx, ctx->perm ? 1 : 0, ctx->cur);
+        if (st != PD_OK) return st;
+    }
     ctx->cur ^= 1;
     ctx->perm = false;
     ctx->stepped = true;
@@ -621,6 +721,81 @@ pd_status pd_set_guide(pd_ctx* ctx, const float* d_table, size_t n)
     (void)d_table;
     (void)n;
     return fail(ctx, PD_EUNSUPPORTED, "guided weights are not available in this build");
+}
+
+pd_status pd_get_tuning(pd_ctx* ctx, pd_tuning* out)
+{
+    if (!ctx || !out) return PD_EINVAL;
+    *out = ctx->tuning;
+    return PD_OK;
+}
+
+pd_status pd_set_tuning(pd_ctx* ctx, const pd_tuning* t)
+{
+    if (!ctx || !t) return PD_EINVAL;
+    return apply_tuning(ctx, *t);
+}
+
+pd_status pd_autotune(pd_ctx* ctx, int32_t trial_cycles, pd_tuning* best)
+{
+    if (!ctx || trial_cycles < 1) return PD_EINVAL;
+    if (ctx->stepped) return fail(ctx, PD_ESTATE, "autotune between pd_step and pd_resample");
+    // the trials advance the population: keep a checkpoint and restore it
+    size_t nb = 0;
+    pd_status st = pd_save_bytes(ctx, &nb);
+    if (st != PD_OK) return st;
+    std::vector<char> snap(nb);
+    const int64_t beta0 = ctx->beta;
+    st = pd_save(ctx, snap.data(), nb);
+    if (st != PD_OK) return st;
+    const pd_tuning start = ctx->tuning;
+    std::vector<pd_tuning> cands;
+    pd_tuning t = start;
+    t.step_variant = 0;
+    cands.push_back(t);
+    for (int v : {1, 2, 3})
+        for (int rf : {4, 8, 16}) {
+            t.step_variant = v;
+            t.refill = rf;
+            cands.push_back(t);
+        }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    PD_HIP(hipEventCreate(&e0));
+    PD_HIP(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    pd_tuning chosen = start;
+    for (const auto& c : cands) {
+        st = apply_tuning(ctx, c);
+        if (st != PD_OK) break;
+        // one untimed cycle, then the timed ones (single launches, no graph)
+        for (int rep = 0; rep <= trial_cycles && st == PD_OK; ++rep) {
+            if (rep == 1) {
+                if (hipEventRecord(e0, ctx->stream) != hipSuccess) { st = PD_EDEVICE; break; }
+            }
+            st = enqueue_cycle(ctx, ctx->perm ? 1 : 0, ctx->cur);
+            if (st != PD_OK) break;
+            ctx->cur ^= 1;
+            ctx->perm = true;
+        }
+        if (st != PD_OK) break;
+        if (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            st = PD_EDEVICE;
+            break;
+        }
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { st = PD_EDEVICE; break; }
+        if (ms < best_ms) { best_ms = ms; chosen = c; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != PD_OK) return st;
+    st = pd_load(ctx, snap.data(), nb);
+    if (st != PD_OK) return st;
+    ctx->beta = beta0;
+    st = apply_tuning(ctx, chosen);
+    if (st != PD_OK) return st;
+    if (best) *best = chosen;
+    return PD_OK;
 }
 
 const char* pd_last_error(const pd_ctx* ctx)

@@ -8,6 +8,16 @@
 
 namespace pd {
 
+// Global address-space view of a pointer read from a descriptor in memory.
+// Such pointers are generic to the compiler, which then emits flat memory
+// instructions; flat stores are counted with LDS operations, so every LDS
+// read after a store in a loop would wait for the store to reach memory.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gptr(T* p)
+{
+    return (__attribute__((address_space(1))) T*)p;
+}
+
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
 // 32x32->64 multiplies by the published constants, xor with the Weyl key.
@@ -37,6 +47,39 @@ __device__ __forceinline__ double unit_open0(uint32_t a, uint32_t b)
     const double hi = (double)a * 2097152.0;          // a * 2^21, exact
     const double lo = (double)(b >> 11) + 1.0;        // < 2^21 + 1, exact
     return (hi + lo) * 0x1p-53;                       // < 2^53 + 1, exact
+}
+
+// ln u for u in (0, 1] (Tang's table-driven method).  u = m 2^e with m in
+// [0.75, 1.5); the table row i covers m in [0.75 + i/128, 0.75 + (i+1)/128)
+// and holds c ~ 1/centre (exactly 1 on the two rows touching 1, so ln u is
+// accurate to the last bit near u = 1), -ln c split into a part that is a
+// multiple of 2^-42 and a remainder.  With r = m c - 1 (one rounding, |r| <=
+// 2^-7), ln u = e ln2 - ln c + log1p(r); e*ln2_hi - ln c_hi is exact and
+// log1p(r) is its Taylor series to r^9.  The result is within about one ulp.
+__device__ __forceinline__ double log_unit(double u, const double* __restrict__ tab,
+                                           double ln2_hi, double ln2_lo)
+{
+    const int e0 = __builtin_amdgcn_frexp_exp(u);
+    const double f = __builtin_amdgcn_frexp_mant(u);   // [0.5, 1)
+    const bool low = f < 0.75;
+    const double m = low ? f * 2.0 : f;                 // [0.75, 1.5), exact
+    const double e = (double)(low ? e0 - 1 : e0);
+    const int i = (int)fma(m, 128.0, -96.0);            // exact, then truncated
+    const double c = tab[4 * i];
+    const double nlc_hi = tab[4 * i + 1];
+    const double nlc_lo = tab[4 * i + 2];
+    const double r = fma(m, c, -1.0);
+    double p = 1.0 / 9.0;
+    p = fma(p, r, -1.0 / 8.0);
+    p = fma(p, r, 1.0 / 7.0);
+    p = fma(p, r, -1.0 / 6.0);
+    p = fma(p, r, 1.0 / 5.0);
+    p = fma(p, r, -1.0 / 4.0);
+    p = fma(p, r, 1.0 / 3.0);
+    p = fma(p, r, -0.5);
+    const double l1p = fma(r * r, p, r);
+    const double t = fma(e, ln2_hi, nlc_hi);            // exact
+    return t + (fma(e, ln2_lo, nlc_lo) + l1p);
 }
 
 // floor(((a << 32) | b) * r / 2^64) for r < 2^31: a uniform index in [0, r).

@@ -9,6 +9,7 @@ namespace pd {
 constexpr int kTile = 256;          // clones per tile = threads per block
 constexpr int kMaxWords = 8;        // 64-site words per state
 constexpr int kMaxSites = 512;      // L <= kMaxSites
+constexpr int kLogRows = 96;        // rows of the logarithm table
 
 enum : uint32_t { TAG_INIT = 1, TAG_DYN = 2, TAG_RESAMPLE = 3, TAG_IID = 4 };
 enum : int32_t { MODE_MODIFIED = 0, MODE_DIRECT = 1, MODE_GUIDED = 2 };
@@ -17,9 +18,8 @@ enum : int32_t { SEL_EQ = 0, SEL_IID = 1 };
 // Mutable per-instance state that lives in device memory, so that captured
 // graphs advance it on every replay.
 struct InstCtl {
-    int64_t beta;          // completed cycles
-    uint32_t tiles_done;   // step kernel: tiles finished this interval
-    uint32_t tiles_done2;  // resample kernel: tiles finished this interval
+    int64_t beta;          // intervals whose dynamical stage has run
+    uint32_t pad_a, pad_b;
     double lmax;           // max_i ln Ups_i of the current interval
     double lbeta;          // ln mean Ups of the current interval
     double psi_sum, psi_comp;    // Neumaier sum of lbeta over all intervals
@@ -47,11 +47,17 @@ struct InstDev {
     double* tile_sum;      // [ntiles] sum of exp(ell - tile_max)
     uint64_t* tile_hops;   // [ntiles]
     double* tile_off;      // [ntiles + 1] exclusive prefix of the tile sums, scale lmax
-    const double* inv_rate;// [L + 1] 1 / (total hop rate) for r = 0..L
+    double inv_scale;      // 1 / (rate of one allowed hop): e^{s} (modified) or 1
+    const double* inv_count;// [kMaxSites + 1] 1 / r for r = 0..kMaxSites (shared)
     double* log;           // [log_cycles][2] (lbeta, mean K^beta)
     const float* guide;    // [8192] guide table (guided mode)
+    const double* log_tab; // [kLogRows][4] table of the device logarithm
+    double ln2_hi, ln2_lo; // ln 2 = ln2_hi (a multiple of 2^-42) + ln2_lo
     InstCtl* ctl;
+    uint32_t* next_tile;   // work counters of the persistent step launches
 };
+
+constexpr int kMaxGroups = 16;     // step launches per cycle (one per word count)
 
 struct TileDesc {
     int32_t inst;          // instance index

@@ -1,21 +1,29 @@
 // HIP kernels of the cloning algorithm for gfx950 (MI355X).
 //
-// One cycle of the algorithm (arXiv:1711.05095, Sec. 2.3) is two launches:
+// One cycle of the algorithm (arXiv:1711.05095, Sec. 2.3) is three launches
+// (plus one per extra word count in a mixed batch):
 //
-//   k_step     the dynamical stage (Sec. 4, first paragraph): one clone per
-//              lane, its occupancy bit-packed in registers, continuous-time
+//   k_step / k_step_q  the dynamical stage (Sec. 4, first paragraph): every
+//              clone's occupancy bit-packed in registers, continuous-time
 //              (BKL) hops for one interval Delta t driven by Philox4x32-10.
 //              A clone's state is pulled through the ancestor map of the
 //              previous cloning stage as it is loaded, so the copy of the
-//              surviving clones (Sec. 6.1) is fused into this load.  Each
-//              block reduces its tile's log-weights to (max, sum of exp); the
-//              last block of an instance forms the population mean of
-//              Upsilon (eq. psihat), the tile prefix offsets and the total.
+//              surviving clones (Sec. 6.1) is fused into this load.  Each tile
+//              of 256 clones leaves (max ln Ups, sum exp(ln Ups - max), hops).
+//              k_step runs one clone per lane; k_step_q runs persistent waves
+//              that take tiles from a counter and keep every lane busy with a
+//              queue of the tile's clones (the next one prefetched).
+//   k_prefix   per instance: ln of the population mean of Upsilon (eq.
+//              psihat) and the psi sums, and the prefix offsets of the tiles.
 //   k_resample the cloning stage (Sec. 4.1, eq. alpha-Ups): an FP64 scan of
 //              the weights over each tile on top of its prefix offset, the
 //              interval ends y_k in units of the point spacing, and for every
 //              old clone k the range of new slots j whose point j + d falls in
 //              its interval; k writes itself as the ancestor of those slots.
+//
+// No kernel communicates across workgroups through memory within a launch
+// except through the work counter of k_step_q; everything else is ordered by
+// the launch boundaries.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -64,11 +72,10 @@ __global__ __launch_bounds__(kTile) void k_init(const InstDev* __restrict__ inst
 __global__ void k_reset_ctl(const InstDev* __restrict__ insts, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < kMaxGroups) insts[0].next_tile[i] = 0;
     if (i >= n) return;
     InstCtl* c = insts[i].ctl;
     c->beta = 0;
-    c->tiles_done = 0;
-    c->tiles_done2 = 0;
     c->lmax = 0.0;
     c->lbeta = 0.0;
     c->psi_sum = c->psi_comp = 0.0;
@@ -86,24 +93,329 @@ __device__ __forceinline__ void neumaier_add(double& sum, double& comp, double x
     sum = t;
 }
 
-// The last block of an instance's step launch: population statistics of the
-// interval from the per-tile (max, sum exp, hops).  Block-wide.  Produces
-// lmax, ln mean Upsilon, and the tile offsets tile_off[0..n] (exclusive
-// prefix sums of the tile weights in the scale exp(. - lmax)), made
-// non-decreasing by a running maximum so that rounding can never reorder
-// interval ends; tile_off[n] is the total weight T.
+// ---------------------------------------------------------------------------
+// One clone through one interval.  The state is in registers; the event loop
+// is the hot loop of the whole method.
+// ---------------------------------------------------------------------------
+struct StepConst {
+    const double* invr;    // LDS: 1 / r for r = 0..kMaxSites
+    const double* logt;    // LDS: logarithm table
+    double inv_scale;      // 1 / rate of one allowed hop
+    double dt, ln2_hi, ln2_lo;
+    uint32_t beta, c3, key0, key1;
+    int L, lb;
+};
+
+// Draws and performs events until the interval ends.  Returns true when the
+// clone reached the end of the interval; A gets the final sojourn.
+template <int W>
+__device__ __forceinline__ bool one_event(const StepConst& C, uint32_t slot, uint64_t (&x)[W],
+                                          uint64_t (&m)[W], int& r, double& tau, double& A,
+                                          uint32_t& k, uint32_t& kb)
+{
+    if (r == 0) return true;
+    const uint4 y = philox10(k, slot, C.beta, C.c3, C.key0, C.key1);
+    ++k;
+    const double E = -log_unit(unit_open0(y.x, y.y), C.logt, C.ln2_hi, C.ln2_lo);
+    // waiting time E / R with R = (rate of one hop) * r
+    const double w = E * (C.inv_scale * C.invr[r]);
+    if (tau + w >= C.dt || k >= 0x80000000u) {
+        // k < 2^31 always: the host admits at most 2^24 expected hops per
+        // interval; the bound only guarantees that the loop ends
+        A = fma((double)r, C.dt - tau, A);
+        return true;
+    }
+    A = fma((double)r, w, A);
+    tau = tau + w;
+    const uint32_t q = mulhi64_small(y.z, y.w, (uint32_t)r);
+    hop<W>(x, select_bit<W>(m, q), C.L);
+    bond_mask<W>(x, C.lb, m);
+    r = popcount_words<W>(m);
+    ++kb;
+    return false;
+}
+
+// Tile aggregates from a wave's view of the tile's log-weights (an LDS array
+// of n values): lane l folds values l, l+64, l+128, ... in that order, then a
+// fixed butterfly combines the lanes.  Both step variants use exactly this
+// order, so the launch configuration never changes a rounding.
+__device__ __forceinline__ void tile_aggregate(const InstDev& I, int tile, const double* sell,
+                                               int n, uint64_t hops_lane)
+{
+    const int lane = threadIdx.x & 63;
+    double mx = -INFINITY;
+    for (int i = lane; i < n; i += 64) mx = fmax(mx, sell[i]);
+    mx = wave_reduce(mx, OpMax());
+    double sm = 0.0;
+    for (int i = lane; i < n; i += 64) sm += exp(sell[i] - mx);
+    sm = wave_reduce(sm, OpSum());
+    const uint64_t th = wave_reduce(hops_lane, OpSum());
+    if (lane == 0) {
+        gptr(I.tile_max)[tile] = mx;
+        gptr(I.tile_sum)[tile] = sm;
+        gptr(I.tile_hops)[tile] = th;
+    }
+}
+
+__device__ __forceinline__ void load_tables(const InstDev& I, double* s_log, double* s_invr,
+                                            int tid, int nthr)
+{
+    for (int i = tid; i < kLogRows * 4; i += nthr) s_log[i] = gptr(I.log_tab)[i];
+    for (int i = tid; i <= kMaxSites; i += nthr) s_invr[i] = gptr(I.inv_count)[i];
+}
+
+// ---------------------------------------------------------------------------
+// Dynamical stage, one clone per lane: block = one tile of 256 clones.
+// ---------------------------------------------------------------------------
+template <int W>
+__global__ __launch_bounds__(kTile) void k_step(const InstDev* __restrict__ insts,
+                                                const TileDesc* __restrict__ tiles, int tile_base,
+                                                int src, int use_anc)
+{
+    __shared__ double s_invr[kMaxSites + 1];
+    __shared__ double s_log[kLogRows * 4];
+    __shared__ double s_ell[kTile];
+    __shared__ uint64_t s_u[kTile];
+
+    const TileDesc td = tiles[tile_base + blockIdx.x];
+    const InstDev& I = insts[td.inst];
+    const int L = I.L;
+    load_tables(I, s_log, s_invr, threadIdx.x, kTile);
+    __syncthreads();
+
+    StepConst C;
+    C.invr = s_invr; C.logt = s_log; C.inv_scale = I.inv_scale;
+    C.dt = I.dt; C.ln2_hi = I.ln2_hi; C.ln2_lo = I.ln2_lo;
+    C.beta = (uint32_t)(I.ctl->beta + 1); C.c3 = TAG_DYN | I.tag_hi;
+    C.key0 = I.key0; C.key1 = I.key1; C.L = L; C.lb = (L - 1) & 63;
+
+    const int tid = threadIdx.x;
+    const bool valid = tid < td.count;
+    const int64_t j = td.first + tid;
+    const int64_t Nc = I.Nc;
+
+    uint32_t kb = 0;
+    double ell = -INFINITY;
+    if (valid) {
+        const int64_t from = use_anc ? (int64_t)gptr(I.anc)[j] : j;
+        uint64_t x[W], m[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) x[w] = gptr(I.state[src])[w * Nc + from];
+        const uint64_t Kfrom = gptr(I.K[src])[from];
+        bond_mask<W>(x, C.lb, m);
+        int r = popcount_words<W>(m);
+        double tau = 0.0, A = 0.0;
+        uint32_t k = 0;
+        while (!one_event<W>(C, (uint32_t)j, x, m, r, tau, A, k, kb)) {}
+        ell = (I.mode == MODE_MODIFIED) ? -I.c * A : -I.s * (double)kb;
+        const int dst = src ^ 1;
+#pragma unroll
+        for (int w = 0; w < W; ++w) gptr(I.state[dst])[w * Nc + j] = x[w];
+        gptr(I.K[dst])[j] = Kfrom + kb;
+        gptr(I.Kb)[j] = kb;
+        gptr(I.A)[j] = A;
+        gptr(I.ell)[j] = ell;
+    }
+    s_ell[tid] = ell;
+    s_u[tid] = kb;
+    __syncthreads();
+    if (tid < 64) {
+        uint64_t h = 0;
+        for (int i = tid; i < td.count; i += 64) h += s_u[i];
+        tile_aggregate(I, td.tile, s_ell, td.count, h);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Dynamical stage, persistent queued waves.  Each wave takes tiles from the
+// launch's counter; within a tile every lane runs one clone at a time and,
+// once `refill` lanes have finished theirs, all finished lanes take the next
+// clones of the tile (each lane's next clone is already loaded).
+// ---------------------------------------------------------------------------
+constexpr int kQWaves = 4;
+
+template <int W, int OCC>
+__global__ __launch_bounds__(64 * kQWaves) __attribute__((amdgpu_waves_per_eu(OCC))) void k_step_q(const InstDev* __restrict__ insts,
+                                                         const TileDesc* __restrict__ tiles,
+                                                         int tile_base, int tile_count,
+                                                         uint32_t* __restrict__ counter,
+                                                         int src, int use_anc, int refill)
+{
+    __shared__ double s_log[kLogRows * 4];
+    __shared__ double s_invr[kMaxSites + 1];
+    __shared__ double s_ell[kQWaves][kTile];
+    __shared__ int32_t s_from[kQWaves][kTile];
+
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    load_tables(insts[0], s_log, s_invr, threadIdx.x, 64 * kQWaves);
+    __syncthreads();
+
+    double* sell = s_ell[wave];
+    int32_t* sfrom = s_from[wave];
+
+    for (;;) {
+        uint32_t t = 0;
+        if (lane == 0) t = atomicAdd(counter, 1u);
+        t = __builtin_amdgcn_readfirstlane(t);
+        if ((int)t >= tile_count) break;
+        const TileDesc td = tiles[tile_base + t];
+        const InstDev& I = insts[td.inst];
+        const int L = I.L;
+        const int n = td.count;
+        const int64_t Nc = I.Nc;
+        for (int i = lane; i < n; i += 64)
+            sfrom[i] = use_anc ? gptr(I.anc)[td.first + i] : (int32_t)(td.first + i);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+        StepConst C;
+        C.invr = s_invr; C.logt = s_log; C.inv_scale = I.inv_scale;
+        C.dt = I.dt; C.ln2_hi = I.ln2_hi; C.ln2_lo = I.ln2_lo;
+        C.beta = (uint32_t)(I.ctl->beta + 1); C.c3 = TAG_DYN | I.tag_hi;
+        C.key0 = I.key0; C.key1 = I.key1; C.L = L; C.lb = (L - 1) & 63;
+        const auto st_src = gptr(I.state[src]);
+        const auto st_dst = gptr(I.state[src ^ 1]);
+        const auto K_src = gptr(I.K[src]);
+        const auto K_dst = gptr(I.K[src ^ 1]);
+        const auto Kb_out = gptr(I.Kb);
+        const auto A_out = gptr(I.A);
+        const auto ell_out = gptr(I.ell);
+        const bool modified = (I.mode == MODE_MODIFIED);
+        const double cw = modified ? -I.c : -I.s;
+
+        // lane state: current clone (slot cur) and the prefetched next (slot nxt)
+        int cur = lane < n ? lane : -1;
+        int nxt = lane + 64 < n ? lane + 64 : -1;
+        int next_free = min(128, n);
+        uint64_t x[W], m[W], px[W];
+        uint64_t Kf = 0, pK = 0;
+        if (cur >= 0) {
+            const int64_t f = sfrom[cur];
+#pragma unroll
+            for (int w = 0; w < W; ++w) x[w] = st_src[w * Nc + f];
+            Kf = K_src[f];
+        } else {
+#pragma unroll
+            for (int w = 0; w < W; ++w) x[w] = 0;
+        }
+        if (nxt >= 0) {
+            const int64_t f = sfrom[nxt];
+#pragma unroll
+            for (int w = 0; w < W; ++w) px[w] = st_src[w * Nc + f];
+            pK = K_src[f];
+        } else {
+#pragma unroll
+            for (int w = 0; w < W; ++w) px[w] = 0;
+        }
+        bond_mask<W>(x, C.lb, m);
+        int r = popcount_words<W>(m);
+        double tau = 0.0, A = 0.0;
+        uint32_t k = 0, kb = 0, hops = 0;
+        bool active = cur >= 0;
+        bool waiting = false;
+        // outputs of a finished clone, stored at the next refill (after the
+        // prefetched clone has been moved in, so that the wait for the
+        // prefetch never includes these stores)
+        uint64_t ox[W];
+        uint64_t oK = 0;
+        uint32_t okb = 0, oslot = 0;
+        double oA = 0.0, oell = 0.0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) ox[w] = 0;
+
+        for (;;) {
+            if (active) {
+                const uint32_t j = (uint32_t)(td.first + cur);
+                if (one_event<W>(C, j, x, m, r, tau, A, k, kb)) {
+                    oell = modified ? cw * A : cw * (double)kb;
+                    sell[cur] = oell;
+#pragma unroll
+                    for (int w = 0; w < W; ++w) ox[w] = x[w];
+                    oK = Kf + kb;
+                    okb = kb;
+                    oA = A;
+                    oslot = j;
+                    hops += kb;
+                    active = false;
+                    waiting = true;
+                }
+            }
+            const uint64_t wmask = __ballot(waiting);
+            const uint64_t amask = __ballot(active);
+            if (amask == 0 && wmask == 0) break;
+            if (__popcll(wmask) >= refill || amask == 0) {
+                if (waiting) {
+                    waiting = false;
+                    cur = nxt;
+                    if (cur >= 0) {
+#pragma unroll
+                        for (int w = 0; w < W; ++w) x[w] = px[w];
+                        Kf = pK;
+                        bond_mask<W>(x, C.lb, m);
+                        r = popcount_words<W>(m);
+                        tau = 0.0;
+                        A = 0.0;
+                        k = 0;
+                        kb = 0;
+                        active = true;
+                    }
+#pragma unroll
+                    for (int w = 0; w < W; ++w) st_dst[w * Nc + oslot] = ox[w];
+                    K_dst[oslot] = oK;
+                    Kb_out[oslot] = okb;
+                    A_out[oslot] = oA;
+                    ell_out[oslot] = oell;
+                    if (cur >= 0) {
+                        const int rank = __builtin_amdgcn_mbcnt_hi(
+                            (uint32_t)(wmask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)wmask, 0));
+                        nxt = next_free + rank < n ? next_free + rank : -1;
+                        if (nxt >= 0) {
+                            const int64_t f = sfrom[nxt];
+#pragma unroll
+                            for (int w = 0; w < W; ++w) px[w] = st_src[w * Nc + f];
+                            pK = K_src[f];
+                        }
+                    }
+                }
+                next_free = min(n, next_free + (int)__popcll(wmask));
+            }
+        }
+
+        // tile aggregates from the wave's copy of the log-weights
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        tile_aggregate(I, td.tile, sell, n, hops);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Interval statistics, one block per instance: lmax, ln mean Upsilon, the psi
+// sums, and the tile offsets tile_off[0..n] (exclusive prefix sums of the
+// tile weights in the scale exp(. - lmax)), made non-decreasing by a running
+// maximum so that rounding can never reorder interval ends; tile_off[n] is
+// the total weight T.  Completes the interval: beta += 1.
+// ---------------------------------------------------------------------------
 __device__ __forceinline__ double tile_weight(const InstDev& I, int b, double M)
 {
     return I.tile_sum[b] * exp(I.tile_max[b] - M);
 }
 
-__device__ void finish_interval(const InstDev& I, uint32_t beta)
+__global__ __launch_bounds__(kTile) void k_prefix(const InstDev* __restrict__ insts)
 {
     __shared__ double s_d[kTile / 64];
     __shared__ uint64_t s_u[kTile / 64];
     __shared__ double s_x[kTile];
+    const InstDev& I = insts[blockIdx.x];
     const int n = I.ntiles;
     const int tid = threadIdx.x;
+    if (blockIdx.x == 0 && tid < kMaxGroups) I.next_tile[tid] = 0;
+    const uint32_t beta = (uint32_t)(I.ctl->beta + 1);
 
     double m = -INFINITY;
     uint64_t h = 0;
@@ -153,100 +465,7 @@ __device__ void finish_interval(const InstDev& I, uint32_t beta)
             I.log[2 * (beta - 1)] = lbeta;
             I.log[2 * (beta - 1) + 1] = (double)hops / (double)I.Nc;
         }
-        c->tiles_done = 0;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Dynamical stage.
-// ---------------------------------------------------------------------------
-template <int W>
-__global__ __launch_bounds__(kTile) void k_step(const InstDev* __restrict__ insts,
-                                                const TileDesc* __restrict__ tiles, int tile_base,
-                                                int src, int use_anc)
-{
-    __shared__ double s_inv[kMaxSites + 1];
-    __shared__ double s_d[kTile / 64];
-    __shared__ uint64_t s_u[kTile / 64];
-    __shared__ int s_last;
-
-    const TileDesc td = tiles[tile_base + blockIdx.x];
-    const InstDev& I = insts[td.inst];
-    const int L = I.L;
-    for (int i = threadIdx.x; i <= L; i += kTile) s_inv[i] = I.inv_rate[i];
-    __syncthreads();
-
-    const uint32_t beta = (uint32_t)(I.ctl->beta + 1);
-    const int tid = threadIdx.x;
-    const bool valid = tid < td.count;
-    const int64_t j = td.first + tid;
-    const int64_t Nc = I.Nc;
-
-    uint32_t kb = 0;
-    double A = 0.0, ell = -INFINITY;
-    if (valid) {
-        const int64_t from = use_anc ? (int64_t)I.anc[j] : j;
-        uint64_t x[W];
-#pragma unroll
-        for (int w = 0; w < W; ++w) x[w] = I.state[src][w * Nc + from];
-        const uint64_t Kfrom = I.K[src][from];
-
-        const int lb = (L - 1) & 63;
-        const double dt = I.dt;
-        const uint32_t c3 = TAG_DYN | I.tag_hi;
-        uint64_t m[W];
-        bond_mask<W>(x, lb, m);
-        int r = popcount_words<W>(m);
-        double tau = 0.0;
-        uint32_t k = 0;
-        // k < 2^31: the host admits only parameters with at most 2^24 expected
-        // hops per interval, so this bound never binds; it only guarantees an end
-        while (r > 0 && k < 0x80000000u) {
-            const uint4 y = philox10(k, (uint32_t)j, beta, c3, I.key0, I.key1);
-            ++k;
-            const double E = -log(unit_open0(y.x, y.y));
-            const double w = E * s_inv[r];
-            if (tau + w >= dt) {
-                A = fma((double)r, dt - tau, A);
-                break;
-            }
-            A = fma((double)r, w, A);
-            tau = tau + w;
-            const uint32_t q = mulhi64_small(y.z, y.w, (uint32_t)r);
-            const int b = select_bit<W>(m, q);
-            hop<W>(x, b, L);
-            bond_mask<W>(x, lb, m);
-            r = popcount_words<W>(m);
-            ++kb;
-        }
-        ell = (I.mode == MODE_MODIFIED) ? -I.c * A : -I.s * (double)kb;
-
-        const int dst = src ^ 1;
-#pragma unroll
-        for (int w = 0; w < W; ++w) I.state[dst][w * Nc + j] = x[w];
-        I.K[dst][j] = Kfrom + kb;
-        I.Kb[j] = kb;
-        I.A[j] = A;
-        I.ell[j] = ell;
-    }
-
-    // tile aggregates
-    const double tmax = block_reduce(ell, OpMax(), s_d);
-    const double e = valid ? exp(ell - tmax) : 0.0;
-    const double tsum = block_reduce(e, OpSum(), s_d);
-    const uint64_t thops = block_reduce((uint64_t)kb, OpSum(), s_u);
-    if (tid == 0) {
-        I.tile_max[td.tile] = tmax;
-        I.tile_sum[td.tile] = tsum;
-        I.tile_hops[td.tile] = thops;
-        __threadfence();
-        const uint32_t done = atomicAdd(&I.ctl->tiles_done, 1u);
-        s_last = (done == (uint32_t)(I.ntiles - 1));
-    }
-    __syncthreads();
-    if (s_last) {
-        __threadfence();
-        finish_interval(I, beta);
+        c->beta = beta;
     }
 }
 
@@ -278,7 +497,6 @@ __global__ __launch_bounds__(kTile) void k_resample(const InstDev* __restrict__ 
 {
     __shared__ double s_d[kTile / 64];
     __shared__ int64_t s_hi[kTile];
-    __shared__ int s_last;
 
     const TileDesc td = tiles[blockIdx.x];
     const InstDev& I = insts[td.inst];
@@ -287,7 +505,7 @@ __global__ __launch_bounds__(kTile) void k_resample(const InstDev* __restrict__ 
     const int64_t k = td.first + tid;
     const int64_t Nc = I.Nc;
     const double Ncd = (double)Nc;
-    const uint32_t beta = (uint32_t)(I.ctl->beta + 1);
+    const uint32_t beta = (uint32_t)I.ctl->beta;   // k_prefix has completed the interval
     const double M = I.ctl->lmax;
     const int b = td.tile;
     const double off0 = I.tile_off[b];
@@ -295,7 +513,7 @@ __global__ __launch_bounds__(kTile) void k_resample(const InstDev* __restrict__ 
     const double T = I.tile_off[I.ntiles];
     const double d = eq_offset(I, beta);
 
-    const double w = valid ? exp(I.ell[k] - M) : 0.0;
+    const double w = valid ? exp(gptr(I.ell)[k] - M) : 0.0;
     double tot;
     double incl = block_scan_incl(w, OpSum(), s_d, tot);
     incl = block_scan_incl(incl, OpMax(), s_d, tot);  // non-decreasing in k
@@ -306,20 +524,13 @@ __global__ __launch_bounds__(kTile) void k_resample(const InstDev* __restrict__ 
     s_hi[tid] = hi;
     __syncthreads();
     if (valid) {
-        const int64_t lo = (tid == 0) ? count_points_below((off0 * Ncd) / T, d, Nc) : s_hi[tid - 1];
-        for (int64_t jj = lo; jj < hi; ++jj) I.anc[jj] = (int32_t)k;
         if (I.ykey) I.ykey[k] = (Ck * Ncd) / T;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        __threadfence();
-        const uint32_t done = atomicAdd(&I.ctl->tiles_done2, 1u);
-        s_last = (done == (uint32_t)(I.ntiles - 1));
-    }
-    __syncthreads();
-    if (s_last && tid == 0) {
-        I.ctl->beta += 1;
-        I.ctl->tiles_done2 = 0;
+        if (I.selection == SEL_EQ) {
+            const int64_t lo =
+                (tid == 0) ? count_points_below((off0 * Ncd) / T, d, Nc) : s_hi[tid - 1];
+            const auto anc = gptr(I.anc);
+            for (int64_t jj = lo; jj < hi; ++jj) anc[jj] = (int32_t)k;
+        }
     }
 }
 
@@ -340,6 +551,12 @@ __global__ __launch_bounds__(kTile) void k_ksum(const InstDev* __restrict__ inst
     }
     const uint64_t s = block_reduce(v, OpSum(), s_u);
     if (tid == 0) atomicAdd((unsigned long long*)&I.ctl->ksum, (unsigned long long)s);
+}
+
+__global__ void k_zero_ksum(const InstDev* __restrict__ insts, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) insts[i].ctl->ksum = 0;
 }
 
 // Materialise the population: dst[j] = src[anc[j]] for state and K.
@@ -365,43 +582,97 @@ __global__ __launch_bounds__(kTile) void k_gather(const InstDev* __restrict__ in
 hipError_t launch_init(const InstDev* insts, int n_inst, const TileDesc* tiles, int ntiles,
                        hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reset_ctl, dim3((n_inst + 63) / 64), dim3(64), 0, st, insts, n_inst);
+    const int nr = n_inst > kMaxGroups ? n_inst : kMaxGroups;
+    hipLaunchKernelGGL(k_reset_ctl, dim3((nr + 63) / 64), dim3(64), 0, st, insts, n_inst);
     hipLaunchKernelGGL(k_init, dim3(ntiles), dim3(kTile), 0, st, insts, tiles);
     return hipGetLastError();
 }
 
-__global__ void k_zero_ksum(const InstDev* __restrict__ insts, int n)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) insts[i].ctl->ksum = 0;
-}
+#define PD_W_SWITCH(W, CASE)                                                                  \
+    switch (W) {                                                                              \
+        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)                       \
+        default: return hipErrorInvalidValue;                                                 \
+    }
 
-hipError_t launch_zero_ksum(const InstDev* insts, int n_inst, hipStream_t st)
+hipError_t launch_step(const StepLaunch& s, const InstDev* insts, const TileDesc* tiles, int src,
+                       int use_anc, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_zero_ksum, dim3((n_inst + 63) / 64), dim3(64), 0, st, insts, n_inst);
+    if (s.count <= 0) return hipSuccess;
+    if (s.variant == 0) {
+#define PD_CASE(w)                                                                            \
+    case w:                                                                                   \
+        hipLaunchKernelGGL(k_step<w>, dim3(s.count), dim3(kTile), 0, st, insts, tiles,        \
+                           s.base, src, use_anc);                                             \
+        break;
+        PD_W_SWITCH(s.W, PD_CASE)
+#undef PD_CASE
+    } else if (s.variant == 1) {
+#define PD_CASE(w)                                                                            \
+    case w:                                                                                   \
+        hipLaunchKernelGGL((k_step_q<w, 4>), dim3(s.blocks), dim3(64 * kQWaves), 0, st, insts, \
+                           tiles, s.base, s.count, s.counter, src, use_anc, s.refill);        \
+        break;
+        PD_W_SWITCH(s.W, PD_CASE)
+#undef PD_CASE
+    } else if (s.variant == 2) {
+#define PD_CASE(w)                                                                            \
+    case w:                                                                                   \
+        hipLaunchKernelGGL((k_step_q<w, 6>), dim3(s.blocks), dim3(64 * kQWaves), 0, st, insts, \
+                           tiles, s.base, s.count, s.counter, src, use_anc, s.refill);        \
+        break;
+        PD_W_SWITCH(s.W, PD_CASE)
+#undef PD_CASE
+    } else {
+#define PD_CASE(w)                                                                            \
+    case w:                                                                                   \
+        hipLaunchKernelGGL((k_step_q<w, 8>), dim3(s.blocks), dim3(64 * kQWaves), 0, st, insts, \
+                           tiles, s.base, s.count, s.counter, src, use_anc, s.refill);        \
+        break;
+        PD_W_SWITCH(s.W, PD_CASE)
+#undef PD_CASE
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_step(int W, const InstDev* insts, const TileDesc* tiles, int tile_base,
-                       int ntiles, int src, int use_anc, hipStream_t st)
+hipError_t step_occupancy(int W, int variant, int* blocks_per_cu)
 {
-    if (ntiles <= 0) return hipSuccess;
-    switch (W) {
+    *blocks_per_cu = 0;
+    if (variant == 0) {
 #define PD_CASE(w)                                                                            \
     case w:                                                                                   \
-        hipLaunchKernelGGL(k_step<w>, dim3(ntiles), dim3(kTile), 0, st, insts, tiles,         \
-                           tile_base, src, use_anc);                                          \
-        break;
-        PD_CASE(1) PD_CASE(2) PD_CASE(3) PD_CASE(4) PD_CASE(5) PD_CASE(6) PD_CASE(7) PD_CASE(8)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_step<w>, kTile, 0);
+        PD_W_SWITCH(W, PD_CASE)
 #undef PD_CASE
-        default: return hipErrorInvalidValue;
     }
+#define PD_CASE(w)                                                                            \
+    case w:                                                                                   \
+        if (variant == 1)                                                                     \
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu,               \
+                                                                k_step_q<w, 4>, 64 * kQWaves, 0); \
+        if (variant == 2)                                                                     \
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu,               \
+                                                                k_step_q<w, 6>, 64 * kQWaves, 0); \
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_step_q<w, 8>,   \
+                                                            64 * kQWaves, 0);
+    PD_W_SWITCH(W, PD_CASE)
+#undef PD_CASE
+}
+
+hipError_t launch_prefix(const InstDev* insts, int n_inst, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_prefix, dim3(n_inst), dim3(kTile), 0, st, insts);
     return hipGetLastError();
 }
 
 hipError_t launch_resample(const InstDev* insts, const TileDesc* tiles, int ntiles, hipStream_t st)
 {
     hipLaunchKernelGGL(k_resample, dim3(ntiles), dim3(kTile), 0, st, insts, tiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_ksum(const InstDev* insts, int n_inst, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_zero_ksum, dim3((n_inst + 63) / 64), dim3(64), 0, st, insts, n_inst);
     return hipGetLastError();
 }
 
@@ -416,16 +687,13 @@ hipError_t launch_gather(int W, const InstDev* insts, const TileDesc* tiles, int
                          int ntiles, int src, hipStream_t st)
 {
     if (ntiles <= 0) return hipSuccess;
-    switch (W) {
 #define PD_CASE(w)                                                                            \
     case w:                                                                                   \
         hipLaunchKernelGGL(k_gather<w>, dim3(ntiles), dim3(kTile), 0, st, insts, tiles,       \
                            tile_base, src);                                                   \
         break;
-        PD_CASE(1) PD_CASE(2) PD_CASE(3) PD_CASE(4) PD_CASE(5) PD_CASE(6) PD_CASE(7) PD_CASE(8)
+    PD_W_SWITCH(W, PD_CASE)
 #undef PD_CASE
-        default: return hipErrorInvalidValue;
-    }
     return hipGetLastError();
 }
 

@@ -5,10 +5,24 @@
 #include "pd_internal.hpp"
 
 namespace pd {
+
+// One launch of the dynamical stage: the tiles [base, base + count) of the
+// step order, all with W words per state.
+struct StepLaunch {
+    int W;
+    int variant;           // 0: one clone per lane; 1: persistent queued waves
+    int base, count;       // tiles
+    int blocks;            // grid of the persistent variant
+    int refill;            // finished lanes that trigger a refill (variant 1)
+    uint32_t* counter;     // work counter of the persistent variant
+};
+
 hipError_t launch_init(const InstDev* insts, int n_inst, const TileDesc* tiles, int ntiles,
                        hipStream_t st);
-hipError_t launch_step(int W, const InstDev* insts, const TileDesc* tiles, int tile_base,
-                       int ntiles, int src, int use_anc, hipStream_t st);
+hipError_t launch_step(const StepLaunch& s, const InstDev* insts, const TileDesc* tiles, int src,
+                       int use_anc, hipStream_t st);
+hipError_t step_occupancy(int W, int variant, int* blocks_per_cu);
+hipError_t launch_prefix(const InstDev* insts, int n_inst, hipStream_t st);
 hipError_t launch_resample(const InstDev* insts, const TileDesc* tiles, int ntiles,
                            hipStream_t st);
 hipError_t launch_zero_ksum(const InstDev* insts, int n_inst, hipStream_t st);

@@ -23,8 +23,8 @@ PD_MAX_L = 512
 EXPORTS = ["pd_workspace_bytes", "pd_create", "pd_destroy", "pd_step", "pd_resample", "pd_run",
            "pd_scgf", "pd_estimates_get", "pd_population_bytes", "pd_get_population",
            "pd_set_population", "pd_get_step_outputs", "pd_get_ancestors", "pd_get_log",
-           "pd_save_bytes", "pd_save", "pd_load", "pd_set_guide", "pd_last_error",
-           "pd_status_str"]
+           "pd_save_bytes", "pd_save", "pd_load", "pd_set_guide", "pd_get_tuning",
+           "pd_set_tuning", "pd_autotune", "pd_last_error", "pd_status_str"]
 
 
 class PdParams(ctypes.Structure):
@@ -39,6 +39,11 @@ class PdEstimates(ctypes.Structure):
     _fields_ = [("psi", ctypes.c_double), ("psi_burn", ctypes.c_double),
                 ("k_hat", ctypes.c_double), ("t", ctypes.c_double), ("cycles", ctypes.c_int64),
                 ("hops", ctypes.c_uint64)]
+
+
+class PdTuning(ctypes.Structure):
+    _fields_ = [("step_variant", ctypes.c_int32), ("refill", ctypes.c_int32),
+                ("graph_cycles", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class PdError(RuntimeError):
@@ -79,6 +84,9 @@ def lib():
             "pd_save": [vp, vp, c.c_size_t],
             "pd_load": [vp, vp, c.c_size_t],
             "pd_set_guide": [vp, vp, c.c_size_t],
+            "pd_get_tuning": [vp, P(PdTuning)],
+            "pd_set_tuning": [vp, P(PdTuning)],
+            "pd_autotune": [vp, c.c_int32, P(PdTuning)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -212,6 +220,27 @@ def pd_load(ctx, blob):
     _check(lib().pd_load(ctx, _ptr(blob), blob.nbytes), ctx)
 
 
+def _tuning_dict(t):
+    return dict(step_variant=t.step_variant, refill=t.refill, graph_cycles=t.graph_cycles)
+
+
+def pd_get_tuning(ctx):
+    t = PdTuning()
+    _check(lib().pd_get_tuning(ctx, ctypes.byref(t)), ctx)
+    return _tuning_dict(t)
+
+
+def pd_set_tuning(ctx, step_variant, refill, graph_cycles):
+    t = PdTuning(step_variant=step_variant, refill=refill, graph_cycles=graph_cycles, reserved=0)
+    _check(lib().pd_set_tuning(ctx, ctypes.byref(t)), ctx)
+
+
+def pd_autotune(ctx, trial_cycles):
+    t = PdTuning()
+    _check(lib().pd_autotune(ctx, int(trial_cycles), ctypes.byref(t)), ctx)
+    return _tuning_dict(t)
+
+
 def pd_set_guide(ctx, table_ptr, n):
     _check(lib().pd_set_guide(ctx, ctypes.c_void_p(table_ptr), n), ctx)
 
@@ -285,3 +314,12 @@ class Sampler:
 
     def load(self, blob):
         pd_load(self.ctx, blob)
+
+    def tuning(self):
+        return pd_get_tuning(self.ctx)
+
+    def set_tuning(self, step_variant, refill=8, graph_cycles=16):
+        pd_set_tuning(self.ctx, step_variant, refill, graph_cycles)
+
+    def autotune(self, trial_cycles=3):
+        return pd_autotune(self.ctx, trial_cycles)

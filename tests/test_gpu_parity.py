@@ -188,6 +188,43 @@ def test_graph_run_equals_stepwise_and_checkpoint():
     assert np.array_equal(wd, wa) and np.array_equal(Kd, Ka)
 
 
+def test_launch_variants_bit_identical():
+    """Neither kernel variant nor refill threshold nor graph length changes any
+    result: every random number is keyed by clone slot."""
+    specs = [(10, 5, 0.3, 1000, 0.1), (100, 50, 0.002, 3000, 0.5), (400, 200, 1e-4, 700, 1.0),
+             (65, 32, -0.05, 257, 0.5), (512, 256, 0.0, 300, 0.2)]
+    M = 10
+    params = [pd.make_params(L, N, s, Nc, M * dt, dt, seed=70 + i, instance=i)
+              for i, (L, N, s, Nc, dt) in enumerate(specs)]
+    ref = None
+    for variant, refill, graph in [(0, 8, 16), (1, 1, 16), (1, 8, 0), (1, 32, 4), (1, 64, 2)]:
+        S = pd.Sampler(params)
+        S.set_tuning(variant, refill, graph)
+        S.run(M)
+        out = [(S.estimates(i), S.get_population(i)) for i in range(len(params))]
+        if ref is None:
+            ref = out
+            continue
+        for (ea, (wa, Ka)), (eb, (wb, Kb)) in zip(ref, out):
+            assert ea == eb, (variant, refill)
+            assert np.array_equal(wa, wb) and np.array_equal(Ka, Kb), (variant, refill)
+
+
+def test_autotune_leaves_the_run_unchanged():
+    p, _ = make(100, 50, 0.002, 5000, 0.5, M=30, seed=8)
+    A = pd.Sampler(p)
+    A.run(10)
+    best = A.autotune(2)
+    assert best["step_variant"] in (0, 1)
+    A.run(20)
+    B = pd.Sampler(p)
+    B.run(30)
+    assert A.estimates() == B.estimates()
+    wa, Ka = A.get_population()
+    wb, Kb = B.get_population()
+    assert np.array_equal(wa, wb) and np.array_equal(Ka, Kb)
+
+
 def test_batch_equals_separate():
     specs = [(10, 5, 0.3, 1000, 0.1), (100, 50, 0.002, 3000, 0.5), (400, 200, 1e-4, 700, 1.0),
              (65, 32, -0.05, 257, 0.5)]
