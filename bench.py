@@ -14,6 +14,7 @@ Usage: python bench.py [--steps K] [--warmup W] [--nc NC] [--no-cpu-baseline]
 By default W + K = 4000 so that the run covers exactly t_obs = 2000.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -37,6 +38,10 @@ VALU_PER_EVENT_W2 = 215
 # resample scan, ancestor written (4); the gather of the states is fused into
 # the next dynamical stage's load.
 RESAMPLE_BYTES_PER_CLONE = 12
+# HBM bytes per launch of the step kernel on this workload, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE runs scaled by a plain 1 GiB copy (factors 2 and
+# 1), valid only for the kernel source they were taken on.
+STEP_TRAFFIC = {"bytes": 233.8e6, "kernels_sha1": "88b0a28d01db"}
 
 
 def parse():
@@ -140,6 +145,11 @@ def main():
     step_s = float(step_ms.mean()) / 1e3
     achieved = events_per_launch * VALU_PER_EVENT_W2 / step_s
 
+    sha = hashlib.sha1(open(os.path.join(ROOT, "paper_1711_05095_amd", "csrc", "pd_kernels.hip"),
+                            "rb").read()).hexdigest()[:12]
+    traffic = STEP_TRAFFIC["bytes"] if (sha == STEP_TRAFFIC["kernels_sha1"]
+                                        and a.nc == 100_000) else None
+    kname = "k_step<2>" if tuning["step_variant"] == 0 else "k_step_q<2>"
     out = {
         "metric": "clone-hops/s",
         "value": value,
@@ -158,10 +168,10 @@ def main():
                                "one batch" % (a.nc, total * dt),
                    "instances": S.n, "Nc": a.nc, "L": L, "N": N, "dt": dt,
                    "intervals": total},
-        "roofline": {"bound": "alu", "kernel": "k_step<2>",
+        "roofline": {"bound": "alu", "kernel": kname,
                      "achieved": achieved / 1e12, "peak": PEAK_VALU_LANE_OPS / 1e12,
                      "unit": "T VALU lane-instr/s", "frac": achieved / PEAK_VALU_LANE_OPS,
-                     "traffic": None,
+                     "traffic": traffic,
                      "per_unit": "%d VALU instr per event" % VALU_PER_EVENT_W2,
                      "events_per_launch": events_per_launch,
                      "step_ms_mean": float(step_ms.mean()),
