@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--variant", type=int, default=None,
                     help="step kernel variant (default: chosen by the autotuner)")
     ap.add_argument("--refill", type=int, default=8)
+    ap.add_argument("--workload", choices=["sweep", "batch"], default="sweep",
+                    help="sweep: the L=100 transition sweep (default); batch: 64 uneven "
+                         "instances in one context against 64 sequential contexts")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (for PMC byte-counter scaling)")
     a = ap.parse_args()
@@ -74,6 +77,50 @@ def calibrate_copy():
     dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes": n}), flush=True)
+
+
+def bench_batch(a):
+    """64 uneven instances (L in {20..200}, N = L/2, lambda in [-10, 20], Nc
+    log-uniform in [1e3, 1e5], dt = 0.5, t_obs = 1000): all in one context
+    (one step launch per word count and one cloning launch per cycle, replayed
+    from graphs), against the same 64 instances run one after another, each
+    in its own context."""
+    import torch
+    specs = inputs.batched_instances()
+    M = int(round(specs[0]["t_obs"] / specs[0]["dt"]))
+    cycles = min(M, a.steps)
+    params = [pd.make_params(d["L"], d["N"], d["s"], d["Nc"], d["t_obs"], d["dt"], seed=d["seed"],
+                             instance=d["instance"]) for d in specs]
+    B = pd.Sampler(params)
+    tuning = B.autotune(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.run(cycles)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    hops_b = sum(B.estimates(i)["hops"] for i in range(B.n))
+    singles = [pd.Sampler(q) for q in params]
+    for S in singles:
+        S.set_tuning(tuning["step_variant"], tuning["refill"], tuning["graph_cycles"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for S in singles:
+        S.run(cycles)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    hops_s = sum(S.estimates()["hops"] for S in singles)
+    same = all(B.estimates(i) == singles[i].estimates() for i in range(B.n))
+    return {"metric": "clone-hops/s", "value": hops_b / t_batch, "unit": "clone-hops/s",
+            "n_gpus": 1, "steps": cycles, "warmup": 0, "ms_per_step": t_batch / cycles * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": "64 uneven instances: L in {20..200}, N=L/2, lambda in "
+                                   "[-10,20], Nc log-uniform in [1e3,1e5], dt=0.5, %d intervals"
+                                   % cycles, "total_clones": int(sum(d["Nc"] for d in specs))},
+            "sequential": {"value": hops_s / t_sec if (t_sec := t_seq) else None,
+                           "seconds": t_seq, "hops": hops_s},
+            "batched_seconds": t_batch, "speedup_vs_sequential": t_seq / t_batch,
+            "identical_results": same, "tuning": tuning}
 
 
 def cpu_baseline(nc, cycles):
@@ -99,6 +146,9 @@ def main():
         sys.exit(2)
     if a.calibrate_copy:
         calibrate_copy()
+        return
+    if a.workload == "batch":
+        print(json.dumps(bench_batch(a)), flush=True)
         return
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"

@@ -67,6 +67,7 @@ def lib():
         _lib.orc_run.argtypes = [P(Params), P(Result), ctypes.c_void_p, ctypes.c_void_p]
         _lib.orc_step_slots.argtypes = [P(Params), ctypes.c_uint32, ctypes.c_int64] + \
             [ctypes.c_void_p] * 6
+        _lib.orc_iid_points.argtypes = [P(Params), ctypes.c_uint32, ctypes.c_void_p]
         _lib.orc_init_slots.argtypes = [P(Params), ctypes.c_int64, ctypes.c_void_p,
                                         ctypes.c_void_p]
     return _lib
@@ -128,6 +129,12 @@ class Oracle:
         occ = np.zeros((slots.shape[0], self.L), np.uint8)
         lib().orc_init_slots(ctypes.byref(self.p), slots.shape[0], _ptr(slots), _ptr(occ))
         return occ
+
+    def iid_points(self, beta):
+        """The [iid] points of interval beta, in units of the point spacing."""
+        pts = np.empty(self.Nc, np.float64)
+        lib().orc_iid_points(ctypes.byref(self.p), beta, _ptr(pts))
+        return pts
 
     def eq_offset(self, beta):
         return lib().orc_eq_offset(ctypes.byref(self.p), beta)

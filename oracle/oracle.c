@@ -371,6 +371,13 @@ static double iid_point(const orc_params* p, uint32_t beta, int64_t j)
     return v * (double)p->Nc;
 }
 
+/* The [iid] points of interval beta for every new slot. */
+int orc_iid_points(const orc_params* p, uint32_t beta, double* pts)
+{
+    for (int64_t j = 0; j < p->Nc; ++j) pts[j] = iid_point(p, beta, j);
+    return 0;
+}
+
 /* Selection from log-weights ell[0..Nc-1].
  *   selection ORC_SEL_EQ: points j + d (d given), ORC_SEL_IID: points pts[j].
  * Writes anc[j] (the old clone new clone j is pulled from) and returns

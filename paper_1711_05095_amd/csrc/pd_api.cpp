@@ -38,7 +38,7 @@ int64_t cycles_of(const pd_params& p) { return llround(p.t_obs / p.dt); }
 pd_tuning default_tuning()
 {
     pd_tuning t;
-    t.step_variant = 1;
+    t.step_variant = 0;
     t.refill = 8;
     t.graph_cycles = 16;
     t.reserved = 0;
@@ -204,6 +204,15 @@ pd_status fail(pd_ctx* ctx, pd_status st, const std::string& msg)
     return st;
 }
 
+// Cloning stage of every instance.
+pd_status enqueue_resample(pd_ctx* ctx)
+{
+    PD_HIP(launch_resample(ctx->d_insts, ctx->d_tiles, (int)ctx->tiles.size(), ctx->stream));
+    if (ctx->any_iid)
+        PD_HIP(launch_select_iid(ctx->d_insts, ctx->d_tiles, (int)ctx->tiles.size(), ctx->stream));
+    return PD_OK;
+}
+
 // Dynamical stage of every instance and the interval statistics.
 pd_status enqueue_step(pd_ctx* ctx, int use_anc, int src)
 {
@@ -217,8 +226,7 @@ pd_status enqueue_cycle(pd_ctx* ctx, int use_anc, int src)
 {
     pd_status st = enqueue_step(ctx, use_anc, src);
     if (st != PD_OK) return st;
-    PD_HIP(launch_resample(ctx->d_insts, ctx->d_tiles, (int)ctx->tiles.size(), ctx->stream));
-    return PD_OK;
+    return enqueue_resample(ctx);
 }
 
 // Applies a tuning: kernel variant and grid of every step launch.
@@ -458,7 +466,10 @@ pd_status pd_resample(pd_ctx* ctx)
 {
     if (!ctx) return PD_EINVAL;
     if (!ctx->stepped) return fail(ctx, PD_ESTATE, "pd_resample needs a pd_step first");
-    PD_HIP(launch_resample(ctx->d_insts, ctx->d_tiles, (int)ctx->tiles.size(), ctx->stream));
+    {
+        pd_status st = enqueue_resample(ctx);
+        if (st != PD_OK) return st;
+    }
     ctx->perm = true;
     ctx->stepped = false;
     ctx->anc_valid = true;

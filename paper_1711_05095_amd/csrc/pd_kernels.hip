@@ -534,6 +534,33 @@ __global__ __launch_bounds__(kTile) void k_resample(const InstDev* __restrict__ 
     }
 }
 
+// [iid] selection (Sec. 4.1): new slot j draws its own point, uniform on the
+// cumulative line, Nc v_j in units of the point spacing with v_j in (0, 1)
+// from 53 bits of the IID stream of (slot j, interval beta), and is pulled
+// from the clone whose interval holds it: a_j = #{k : y_k <= Nc v_j}, found by
+// binary search over the interval ends y_k that k_resample wrote.
+__global__ __launch_bounds__(kTile) void k_select_iid(const InstDev* __restrict__ insts,
+                                                      const TileDesc* __restrict__ tiles)
+{
+    const TileDesc td = tiles[blockIdx.x];
+    const InstDev& I = insts[td.inst];
+    if (I.selection != SEL_IID || (int)threadIdx.x >= td.count) return;
+    const int64_t j = td.first + threadIdx.x;
+    const int64_t Nc = I.Nc;
+    const uint32_t beta = (uint32_t)I.ctl->beta;
+    const uint4 y = philox10(0u, (uint32_t)j, beta, TAG_IID | I.tag_hi, I.key0, I.key1);
+    const double hi = (double)y.x * 2097152.0;          // y.x * 2^21
+    const double lo = (double)(y.y >> 11) + 0.5;
+    const double pt = ((hi + lo) * 0x1p-53) * (double)Nc;
+    const auto yk = gptr(I.ykey);
+    int64_t a = 0, b = Nc;   // answer in [a, b]
+    while (a < b) {
+        const int64_t mid = a + (b - a) / 2;
+        if (yk[mid] <= pt) a = mid + 1; else b = mid;
+    }
+    gptr(I.anc)[j] = (int32_t)(a < Nc ? a : Nc - 1);
+}
+
 // Sum of K over the current population (through the ancestor map if any).
 __global__ __launch_bounds__(kTile) void k_ksum(const InstDev* __restrict__ insts,
                                                 const TileDesc* __restrict__ tiles, int cur,
@@ -667,6 +694,13 @@ hipError_t launch_prefix(const InstDev* insts, int n_inst, hipStream_t st)
 hipError_t launch_resample(const InstDev* insts, const TileDesc* tiles, int ntiles, hipStream_t st)
 {
     hipLaunchKernelGGL(k_resample, dim3(ntiles), dim3(kTile), 0, st, insts, tiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_iid(const InstDev* insts, const TileDesc* tiles, int ntiles,
+                             hipStream_t st)
+{
+    hipLaunchKernelGGL(k_select_iid, dim3(ntiles), dim3(kTile), 0, st, insts, tiles);
     return hipGetLastError();
 }
 

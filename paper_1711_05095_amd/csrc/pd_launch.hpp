@@ -25,6 +25,8 @@ hipError_t step_occupancy(int W, int variant, int* blocks_per_cu);
 hipError_t launch_prefix(const InstDev* insts, int n_inst, hipStream_t st);
 hipError_t launch_resample(const InstDev* insts, const TileDesc* tiles, int ntiles,
                            hipStream_t st);
+hipError_t launch_select_iid(const InstDev* insts, const TileDesc* tiles, int ntiles,
+                             hipStream_t st);
 hipError_t launch_zero_ksum(const InstDev* insts, int n_inst, hipStream_t st);
 hipError_t launch_ksum(const InstDev* insts, const TileDesc* tiles, int ntiles, int cur,
                        int use_anc, hipStream_t st);

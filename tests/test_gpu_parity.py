@@ -188,6 +188,61 @@ def test_graph_run_equals_stepwise_and_checkpoint():
     assert np.array_equal(wd, wa) and np.array_equal(Kd, Ka)
 
 
+IID = pd.PD_SEL_IID
+
+
+@pytest.mark.parametrize("L,N,s,mode,Nc", [(10, 5, 0.4, MOD, 1000), (100, 50, 0.003, DIR, 1500),
+                                           (65, 30, -0.1, MOD, 257)])
+def test_iid_cycles_bit_exact(L, N, s, mode, Nc):
+    """[iid] selection: every new slot's ancestor equals the oracle's for the
+    same points (near-ties certified), through several cycles."""
+    print(f"iid L={L} s={s} Nc={Nc}", flush=True)
+    dt, M = 0.5, 6
+    p, o = make(L, N, s, Nc, dt, M=M, seed=31, mode=mode, sel=IID)
+    S = pd.Sampler(p)
+    occ, K = o.init()
+    for beta in range(1, M + 1):
+        S.step()
+        Kb_o, A_o, ell_o = o.step(beta, occ, K)
+        w_gpu, K_gpu = S.get_population()
+        assert np.array_equal(w_gpu, pack(occ)) and np.array_equal(K_gpu, K), beta
+        S.resample()
+        anc = S.ancestors()
+        pts = o.iid_points(beta)
+        anc_o, _ = oracle.select(ell_o, points=pts)
+        diff = np.nonzero(anc != anc_o)[0]
+        if diff.size:
+            w = np.exp(ell_o - ell_o.max())
+            y = np.cumsum(w) * Nc / w.sum()
+            for j in diff:
+                assert np.min(np.abs(y - pts[j])) < 1e-9 * max(1.0, pts[j]), (beta, j)
+        assert diff.size <= 2
+        occ, K = np.ascontiguousarray(occ[anc]), K[anc]
+
+
+def test_iid_whole_run_and_variance_against_eq():
+    """[iid] whole runs match the oracle; and over seeds the spread of k-hat
+    is larger with [iid] than with [eq] (Sec. 4.3)."""
+    w = inputs.SMALL
+    M = int(round(w["t_obs"] / w["dt"]))
+    s = 0.2
+    p, o = make(w["L"], w["N"], s, w["Nc"], w["dt"], M=M, seed=5, sel=IID)
+    S = pd.Sampler(p)
+    S.run(M)
+    r = o.run()
+    e = S.estimates()
+    assert e["hops"] == r["hops"] and e["psi"] == pytest.approx(r["psi"], rel=1e-9)
+    R = 32
+    spread = {}
+    for sel in (pd.PD_SEL_EQ, IID):
+        params = [pd.make_params(w["L"], w["N"], s, w["Nc"], w["t_obs"], w["dt"], seed=900 + i,
+                                 selection=sel, instance=i) for i in range(R)]
+        B = pd.Sampler(params)
+        B.run(M)
+        spread[sel] = np.std([B.estimates(i)["k_hat"] for i in range(R)], ddof=1)
+    assert spread[pd.PD_SEL_EQ] < spread[IID], spread
+
+
 def test_launch_variants_bit_identical():
     """Neither kernel variant nor refill threshold nor graph length changes any
     result: every random number is keyed by clone slot."""
