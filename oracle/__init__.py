@@ -37,7 +37,7 @@ class Params(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("instance", ctypes.c_uint32),
                 ("mode", ctypes.c_int32), ("selection", ctypes.c_int32),
                 ("pad_", ctypes.c_int32), ("burn_in", ctypes.c_int64),
-                ("guide", ctypes.POINTER(ctypes.c_float))]
+                ("guide", ctypes.POINTER(ctypes.c_uint32))]
 
 
 class Result(ctypes.Structure):
@@ -88,9 +88,9 @@ class Oracle:
                         burn_in=burn_in)
         self._guide = None
         if guide is not None:
-            self._guide = np.ascontiguousarray(guide, dtype=np.float32)
+            self._guide = np.ascontiguousarray(guide, dtype=np.uint32)
             assert self._guide.shape == (8192,)
-            self.p.guide = self._guide.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+            self.p.guide = self._guide.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
         self.L, self.N, self.Nc = L, N, Nc
 
     def init(self):

@@ -26,7 +26,8 @@
  *                             (Sec. 3.2, eq. def-ups-ssep; Sec. 4),
  *                     mode 1: unmodified rates, cloning factor e^{-s K}
  *                             (Sec. 3.1, the biased path weight),
- *                     mode 2: guided rates e^{-s+g}, compensating factor
+ *                     mode 2: guided rates e^{-s+g} with g from a table
+ *                             over bond neighbourhoods, compensating factor
  *                             from eqs. modpdef/upsdef (Sec. 2.2).
  *   orc_select      cloning stage: [eq] (eq. alpha-Ups, Sec. 4.1) or [iid].
  *   orc_resample    cloning stage applied to a population, with the SCGF
@@ -101,7 +102,7 @@ typedef struct {
     int32_t selection;    /* ORC_SEL_EQ / ORC_SEL_IID */
     int32_t pad_;
     int64_t burn_in;      /* intervals left out of psi_burn */
-    const float* guide;   /* ORC_GUIDED: h over all 2^13 windows of 13 sites */
+    const uint32_t* guide; /* ORC_GUIDED: eg over all 2^13 bond neighbourhoods */
 } orc_params;
 
 typedef struct {
@@ -210,23 +211,97 @@ static int window13(const uint8_t* n, int L, int c)
     return w;
 }
 
-/* f(C) = sum over all sites of h(window around the site) (the guide). */
-static double guide_potential(const orc_params* p, const uint8_t* n)
+/* ---- guided dynamics (eqs. modpdef, upsdef of Sec. 2.2) ----
+ * The guide is a table eg[u] over the 13-site neighbourhood u of a bond
+ * (sites b-6 .. b+6, site b-6 in bit 0, so the bond's own sites are bits 6
+ * and 7).  The hop across an allowed bond b has rate e^{-s} eg[u_b] 2^-16,
+ * i.e. log-ratio g_b = ln(eg[u_b] 2^-16) on top of the modified rate.  With
+ * S(C) = sum of eg[u_b] over allowed bonds the escape rate is e^{-s} S 2^-16,
+ * and the compensating factor of the interval is
+ *     ln Ups = -sum_jumps g - int (r(C) - e^{-s} S(C) 2^-16) dt,
+ * which makes the weighted guided trajectories unbiased for ANY table.
+ * Random words of a clone come from one stream per interval: block n of the
+ * GUIDE stream of (slot, beta) gives words 2n and 2n+1.  Each event uses one
+ * word for the waiting time; each proposal of the hop uses one word for the
+ * uniform allowed bond and one for its acceptance with probability
+ * eg[u_b] / eg_max (exact 64-bit Bernoulli), repeated until accepted. */
+enum { ORC_TAG_GUIDE = 5 };
+
+typedef struct {
+    const orc_params* p;
+    uint32_t beta, slot, block, half;
+    uint32_t x[4];
+} word_stream;
+
+static uint64_t next_word(word_stream* ws)
 {
-    double f = 0.0;
-    for (int c = 0; c < p->L; ++c) f += (double)p->guide[window13(n, p->L, c)];
-    return f;
+    if (ws->half == 0) {
+        draw(ws->p, ORC_TAG_GUIDE, ws->block, ws->slot, ws->beta, ws->x);
+        ws->block++;
+        ws->half = 1;
+        return ((uint64_t)ws->x[0] << 32) | ws->x[1];
+    }
+    ws->half = 0;
+    return ((uint64_t)ws->x[2] << 32) | ws->x[3];
 }
 
-/* g(C, b) = f(C with bond b hopped) - f(C), computed from the definition. */
-static double guide_log_ratio(const orc_params* p, uint8_t* n, int b)
+static uint64_t guided_total(const orc_params* p, const uint8_t* n)
+{
+    uint64_t S = 0;
+    for (int b = 0; b < p->L; ++b)
+        if (is_active(n, p->L, b)) S += p->guide[window13(n, p->L, b)];
+    return S;
+}
+
+static uint32_t guide_max(const orc_params* p)
+{
+    uint32_t m = 0;
+    for (int u = 0; u < 8192; ++u)
+        if (p->guide[u] > m) m = p->guide[u];
+    return m;
+}
+
+static uint32_t step_clone_guided(const orc_params* p, double es, uint32_t egmax, uint32_t beta,
+                                  int64_t j, uint8_t* n, double* A_out, double* ell_out)
 {
     const int L = p->L;
-    double f0 = guide_potential(p, n);
-    uint8_t t = n[b]; n[b] = n[(b + 1) % L]; n[(b + 1) % L] = t;
-    double f1 = guide_potential(p, n);
-    t = n[b]; n[b] = n[(b + 1) % L]; n[(b + 1) % L] = t;
-    return f1 - f0;
+    const double dt = p->dt;
+    word_stream ws = { p, beta, (uint32_t)j, 0u, 0u, {0, 0, 0, 0} };
+    double tau = 0.0, A = 0.0, AS = 0.0, G = 0.0;
+    uint32_t kb = 0;
+    int r = escape_count(n, L);
+    uint64_t S = guided_total(p, n);
+    while (r > 0) {
+        double u = (double)((next_word(&ws) >> 11) + 1) * 0x1p-53;
+        double E = -log(u);
+        double R = es * ((double)S * 0x1p-16);
+        double w = E / R;
+        if (tau + w >= dt) {
+            A = fma((double)r, dt - tau, A);
+            AS = fma((double)S, dt - tau, AS);
+            break;
+        }
+        A = fma((double)r, w, A);
+        AS = fma((double)S, w, AS);
+        tau = tau + w;
+        int bond = -1;
+        uint32_t e = 0;
+        for (int proposal = 0; proposal < (1 << 20); ++proposal) {
+            bond = qth_active_bond(n, L, (int)mulhi64(next_word(&ws), (uint64_t)r));
+            e = p->guide[window13(n, L, bond)];
+            if (mulhi64(next_word(&ws), (uint64_t)egmax) < (uint64_t)e) break;
+        }
+        G += log((double)e * 0x1p-16);
+        uint8_t t = n[bond];
+        n[bond] = n[(bond + 1) % L];
+        n[(bond + 1) % L] = t;
+        ++kb;
+        r = escape_count(n, L);
+        S = guided_total(p, n);
+    }
+    *A_out = A;
+    *ell_out = -G - (A - (es * 0x1p-16) * AS);
+    return kb;
 }
 
 /* Advance clone j (occupancy n) through interval beta.  Returns the hops. */
@@ -235,11 +310,9 @@ static uint32_t step_clone(const orc_params* p, double es, double c, uint32_t be
 {
     const int L = p->L;
     const double dt = p->dt;
-    double tau = 0.0, A = 0.0, jump_g = 0.0, Rint = 0.0, gsum = 0.0;
+    double tau = 0.0, A = 0.0;
     uint32_t kb = 0, k = 0;
     int r = escape_count(n, L);
-    double* g = NULL;
-    if (p->mode == ORC_GUIDED) g = (double*)malloc(sizeof(double) * (size_t)L);
 
     while (r > 0) {
         uint32_t x[4];
@@ -248,72 +321,33 @@ static uint32_t step_clone(const orc_params* p, double es, double c, uint32_t be
         /* u in (0, 1] from 53 bits of words 0 and 1 */
         double u = (double)((((uint64_t)x[0] << 21) | (x[1] >> 11)) + 1) * 0x1p-53;
         double E = -log(u);
-        double R;
-        if (p->mode == ORC_MODIFIED) {
-            R = es * (double)r;
-        } else if (p->mode == ORC_DIRECT) {
-            R = (double)r;
-        } else {
-            /* guided: rate e^{-s + g_b} for every active bond b */
-            gsum = 0.0;
-            for (int b = 0; b < L; ++b) {
-                g[b] = 0.0;
-                if (is_active(n, L, b)) {
-                    g[b] = guide_log_ratio(p, n, b);
-                    gsum += exp(g[b]);
-                }
-            }
-            R = es * gsum;
-        }
+        double R = (p->mode == ORC_MODIFIED) ? es * (double)r : (double)r;
         double w = E / R;
         if (tau + w >= dt) {
             A = fma((double)r, dt - tau, A);
-            if (p->mode == ORC_GUIDED) Rint = fma(R, dt - tau, Rint);
             break;
         }
         A = fma((double)r, w, A);
-        if (p->mode == ORC_GUIDED) Rint = fma(R, w, Rint);
         tau = tau + w;
-
-        int bond;
-        if (p->mode != ORC_GUIDED) {
-            /* uniform choice among the r allowed hops */
-            uint32_t q = (uint32_t)mulhi64(((uint64_t)x[2] << 32) | x[3], (uint64_t)r);
-            bond = qth_active_bond(n, L, (int)q);
-        } else {
-            /* choice proportional to e^{g_b}: the first active bond whose
-             * cumulative weight exceeds v * sum, v in (0,1) from 53 bits */
-            double v = ((double)((((uint64_t)x[2] << 21) | (x[3] >> 11))) + 0.5) * 0x1p-53;
-            double target = v * gsum;
-            double acc = 0.0;
-            bond = -1;
-            int last = -1;
-            for (int b = 0; b < L; ++b) {
-                if (!is_active(n, L, b)) continue;
-                last = b;
-                acc += exp(g[b]);
-                if (target < acc) { bond = b; break; }
-            }
-            if (bond < 0) bond = last;
-            jump_g += g[bond];
-        }
+        /* uniform choice among the r allowed hops */
+        uint32_t q = (uint32_t)mulhi64(((uint64_t)x[2] << 32) | x[3], (uint64_t)r);
+        int bond = qth_active_bond(n, L, (int)q);
         uint8_t t = n[bond];
         n[bond] = n[(bond + 1) % L];
         n[(bond + 1) % L] = t;
         ++kb;
         r = escape_count(n, L);
     }
-    free(g);
     *A_out = A;
-    if (p->mode == ORC_MODIFIED) {
-        *ell_out = -c * A;
-    } else if (p->mode == ORC_DIRECT) {
-        *ell_out = -p->s * (double)kb;
-    } else {
-        /* ln Upsilon = -sum_jumps g - integral (r - R') dt */
-        *ell_out = -jump_g - (A - Rint);
-    }
+    *ell_out = (p->mode == ORC_MODIFIED) ? -c * A : -p->s * (double)kb;
     return kb;
+}
+
+static uint32_t step_any(const orc_params* p, double es, double c, uint32_t egmax, uint32_t beta,
+                         int64_t j, uint8_t* n, double* A_out, double* ell_out)
+{
+    if (p->mode == ORC_GUIDED) return step_clone_guided(p, es, egmax, beta, j, n, A_out, ell_out);
+    return step_clone(p, es, c, beta, j, n, A_out, ell_out);
 }
 
 /* One dynamical stage (interval beta >= 1) for the whole population.
@@ -324,8 +358,9 @@ int orc_step(const orc_params* p, uint32_t beta, uint8_t* occ, uint64_t* K, uint
 {
     const double es = exp(-p->s);
     const double c = -expm1(-p->s);
+    const uint32_t egmax = (p->mode == ORC_GUIDED) ? guide_max(p) : 0;
     for (int64_t j = 0; j < p->Nc; ++j) {
-        uint32_t kb = step_clone(p, es, c, beta, j, occ + (size_t)j * p->L, &A[j], &ell[j]);
+        uint32_t kb = step_any(p, es, c, egmax, beta, j, occ + (size_t)j * p->L, &A[j], &ell[j]);
         Kb[j] = kb;
         K[j] += kb;
     }
@@ -341,8 +376,10 @@ int orc_step_slots(const orc_params* p, uint32_t beta, int64_t n, const int64_t*
 {
     const double es = exp(-p->s);
     const double c = -expm1(-p->s);
+    const uint32_t egmax = (p->mode == ORC_GUIDED) ? guide_max(p) : 0;
     for (int64_t i = 0; i < n; ++i) {
-        uint32_t kb = step_clone(p, es, c, beta, slots[i], occ + (size_t)i * p->L, &A[i], &ell[i]);
+        uint32_t kb = step_any(p, es, c, egmax, beta, slots[i], occ + (size_t)i * p->L, &A[i],
+                               &ell[i]);
         Kb[i] = kb;
         K[i] += kb;
     }
