@@ -174,14 +174,18 @@ pd_status pd_save_bytes(pd_ctx* ctx, size_t* bytes);
 pd_status pd_save(pd_ctx* ctx, void* host, size_t bytes);
 pd_status pd_load(pd_ctx* ctx, const void* host, size_t bytes);
 
-/* Guide for PD_W_GUIDED instances: `d_table` is a caller-owned device array
- * of 8192 floats, h(window) for every configuration of 13 consecutive sites
- * (site c-6 in bit 0 ... site c+6 in bit 12).  The guide potential is
- * f(C) = sum over sites c of h(window at c) and the log-ratio across a hop is
- * g = f(C after) - f(C before).  Entries must be multiples of 2^-20 with
- * magnitude <= 64 (then every sum of them is exact in FP64); PD_EINVAL
- * otherwise.  The table must outlive its use. Synchronises. */
-pd_status pd_set_guide(pd_ctx* ctx, const float* d_table, size_t n);
+/* Guide for the PD_W_GUIDED instances of the context (Sec. 2.2: controlled
+ * dynamics with a compensating weight).  `d_table` is a caller-owned device
+ * array of 8192 uint32 entries eg[u], one per 13-site bond neighbourhood u
+ * (site b-6 in bit 0 ... site b+6 in bit 12, so the bond's own sites b, b+1
+ * are bits 6 and 7).  The hop across an allowed bond has rate
+ * e^{-s} eg[u] / 2^16, i.e. log-ratio g = ln(eg[u] / 2^16) on top of the
+ * modified rate; the cloning factor carries the exact compensation
+ * -sum_jumps g - integral (r - e^{-s} sum_b eg[u_b] / 2^16) dt, so psi-hat
+ * stays unbiased for any table.  Entries of neighbourhoods whose bits 6 and 7
+ * are equal must be 0, the others in [1, 2^31) with largest/smallest <= 1024;
+ * PD_EINVAL otherwise.  The table must outlive its use.  Synchronises. */
+pd_status pd_set_guide(pd_ctx* ctx, const uint32_t* d_table, size_t n);
 
 /* Launch configuration of the dynamical stage.  It never changes results
  * (every random number is keyed by clone slot, never by lane or block), only

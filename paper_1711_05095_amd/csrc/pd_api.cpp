@@ -177,6 +177,7 @@ struct pd_ctx {
     pd_tuning tuning;
     bool any_iid = false;
     bool any_guided = false;
+    bool guide_set = false;
     int cur = 0;                     // buffer holding the population
     bool perm = false;               // population = state[cur][anc[j]]
     bool stepped = false;            // a dynamical stage awaits its cloning stage
@@ -239,7 +240,7 @@ pd_status apply_tuning(pd_ctx* ctx, const pd_tuning& t)
     PD_HIP(hipGetDevice(&dev));
     PD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     for (auto& g : ctx->steps) {
-        g.variant = t.step_variant;
+        g.variant = g.guided ? 0 : t.step_variant;
         g.refill = t.refill;
         int per_cu = 0;
         PD_HIP(step_occupancy(g.W, g.variant, &per_cu));
@@ -301,8 +302,6 @@ pd_status pd_create(const pd_params* params, int32_t n, void* d_workspace, size_
     for (int i = 0; i < n; ++i) {
         std::string m = validate(params[i]);
         if (!m.empty()) return fail(nullptr, PD_EINVAL, "instance " + std::to_string(i) + ": " + m);
-        if (params[i].weight_mode == PD_W_GUIDED)
-            return fail(nullptr, PD_EUNSUPPORTED, "guided weights are not available in this build");
     }
     if ((uintptr_t)d_workspace % kAlign != 0)
         return fail(nullptr, PD_EINVAL, "workspace must be 256-byte aligned");
@@ -361,10 +360,11 @@ pd_status pd_create(const pd_params* params, int32_t n, void* d_workspace, size_
         d.next_tile = (uint32_t*)(b + pl.counters_off);
         ctx->dev.push_back(d);
         if (p.selection == PD_SEL_IID) ctx->any_iid = true;
+        if (p.weight_mode == PD_W_GUIDED) ctx->any_guided = true;
     }
 
     // tiles: grouped by word count, largest expected work first within a group
-    struct Cand { TileDesc t; int W; double cost; };
+    struct Cand { TileDesc t; int W; bool guided; double cost; };
     std::vector<Cand> cand;
     for (int i = 0; i < n; ++i) {
         const pd_params& p = params[i];
@@ -377,22 +377,26 @@ pd_status pd_create(const pd_params* params, int32_t n, void* d_workspace, size_
             td.tile = t;
             td.first = t * kTile;
             td.count = (int)std::min<int64_t>(kTile, p.Nc - (int64_t)t * kTile);
-            cand.push_back({td, words_of(p.L), td.count * (rate * p.dt + 1.0)});
+            cand.push_back({td, words_of(p.L), p.weight_mode == PD_W_GUIDED,
+                            td.count * (rate * p.dt + 1.0)});
         }
     }
     std::stable_sort(cand.begin(), cand.end(), [](const Cand& a, const Cand& b) {
+        if (a.guided != b.guided) return !a.guided;
         if (a.W != b.W) return a.W < b.W;
         return a.cost > b.cost;
     });
     for (size_t k = 0; k < cand.size(); ++k) {
         ctx->tiles.push_back(cand[k].t);
-        if (ctx->steps.empty() || ctx->steps.back().W != cand[k].W) {
+        if (ctx->steps.empty() || ctx->steps.back().W != cand[k].W ||
+            ctx->steps.back().guided != cand[k].guided) {
             if ((int)ctx->steps.size() == kMaxGroups) {
                 delete ctx;
                 return fail(nullptr, PD_EUNSUPPORTED, "too many distinct word counts");
             }
             StepLaunch sl;
             sl.W = cand[k].W;
+            sl.guided = cand[k].guided;
             sl.variant = 0;
             sl.base = (int)k;
             sl.count = 0;
@@ -451,6 +455,8 @@ pd_status pd_step(pd_ctx* ctx)
 {
     if (!ctx) return PD_EINVAL;
     if (ctx->stepped) return fail(ctx, PD_ESTATE, "pd_step called twice without pd_resample");
+    if (ctx->any_guided && !ctx->guide_set)
+        return fail(ctx, PD_ESTATE, "guided instances need pd_set_guide first");
     {
         pd_status st = enqueue_step(ctx, ctx->perm ? 1 : 0, ctx->cur);
         if (st != PD_OK) return st;
@@ -481,6 +487,8 @@ pd_status pd_run(pd_ctx* ctx, int64_t cycles)
 {
     if (!ctx || cycles < 0) return PD_EINVAL;
     if (ctx->stepped) return fail(ctx, PD_ESTATE, "a pd_step awaits its pd_resample");
+    if (ctx->any_guided && !ctx->guide_set)
+        return fail(ctx, PD_ESTATE, "guided instances need pd_set_guide first");
     int64_t left = cycles;
     if (left > 0 && !ctx->perm) {
         pd_status st = enqueue_cycle(ctx, 0, ctx->cur);
@@ -726,12 +734,44 @@ pd_status pd_load(pd_ctx* ctx, const void* host, size_t bytes)
     return PD_OK;
 }
 
-pd_status pd_set_guide(pd_ctx* ctx, const float* d_table, size_t n)
+pd_status pd_set_guide(pd_ctx* ctx, const uint32_t* d_table, size_t n)
 {
     if (!ctx) return PD_EINVAL;
-    (void)d_table;
-    (void)n;
-    return fail(ctx, PD_EUNSUPPORTED, "guided weights are not available in this build");
+    if (!ctx->any_guided) return fail(ctx, PD_EINVAL, "no instance uses guided weights");
+    if (!d_table || n != (size_t)kGuideEntries) return fail(ctx, PD_EINVAL, "table must hold 8192 entries");
+    std::vector<uint32_t> h(kGuideEntries);
+    PD_HIP(hipMemcpyAsync(h.data(), d_table, sizeof(uint32_t) * h.size(), hipMemcpyDeviceToHost,
+                          ctx->stream));
+    PD_HIP(hipStreamSynchronize(ctx->stream));
+    uint32_t lo = UINT32_MAX, hi = 0;
+    for (int u = 0; u < kGuideEntries; ++u) {
+        const bool allowed = ((u >> 6) ^ (u >> 7)) & 1;
+        if (!allowed) {
+            if (h[u] != 0) return fail(ctx, PD_EINVAL, "entries of non-hop neighbourhoods must be 0");
+            continue;
+        }
+        if (h[u] == 0 || h[u] >= (1u << 31)) return fail(ctx, PD_EINVAL, "entries must be in [1, 2^31)");
+        lo = std::min(lo, h[u]);
+        hi = std::max(hi, h[u]);
+    }
+    if ((uint64_t)hi > 1024ull * lo) return fail(ctx, PD_EINVAL, "largest/smallest entry must be <= 1024");
+    for (int i = 0; i < ctx->n; ++i) {
+        const pd_params& p = ctx->params[i];
+        if (p.weight_mode != PD_W_GUIDED) continue;
+        const double rate = std::exp(-p.s) * ((double)hi / 65536.0) * (double)p.L;
+        if (!(rate * p.dt <= kMaxEventsPerInterval))
+            return fail(ctx, PD_EINVAL, "guide makes more than 2^24 expected hops per interval");
+    }
+    for (int i = 0; i < ctx->n; ++i) {
+        if (ctx->params[i].weight_mode != PD_W_GUIDED) continue;
+        ctx->dev[i].guide = d_table;
+        ctx->dev[i].guide_max = hi;
+    }
+    PD_HIP(hipMemcpyAsync(ctx->d_insts, ctx->dev.data(), sizeof(InstDev) * (size_t)ctx->n,
+                          hipMemcpyHostToDevice, ctx->stream));
+    PD_HIP(hipStreamSynchronize(ctx->stream));
+    ctx->guide_set = true;
+    return PD_OK;
 }
 
 pd_status pd_get_tuning(pd_ctx* ctx, pd_tuning* out)
@@ -751,6 +791,8 @@ pd_status pd_autotune(pd_ctx* ctx, int32_t trial_cycles, pd_tuning* best)
 {
     if (!ctx || trial_cycles < 1) return PD_EINVAL;
     if (ctx->stepped) return fail(ctx, PD_ESTATE, "autotune between pd_step and pd_resample");
+    if (ctx->any_guided && !ctx->guide_set)
+        return fail(ctx, PD_ESTATE, "guided instances need pd_set_guide first");
     // the trials advance the population: keep a checkpoint and restore it
     size_t nb = 0;
     pd_status st = pd_save_bytes(ctx, &nb);

@@ -150,6 +150,42 @@ __device__ __forceinline__ int select_bit(const uint64_t (&m)[W], uint32_t q)
     return base + pos;
 }
 
+// Word i (0 <= i < W) of the register array, i not known at compile time.
+template <int W>
+__device__ __forceinline__ uint64_t word_at(const uint64_t (&x)[W], int i)
+{
+    uint64_t v = x[0];
+#pragma unroll
+    for (int w = 1; w < W; ++w)
+        if (i == w) v = x[w];
+    return v;
+}
+
+// Occupancies of sites p .. p+n-1 (bit k = site p+k), for p + n <= L, n <= 32.
+template <int W>
+__device__ __forceinline__ uint32_t lin_bits(const uint64_t (&x)[W], int p, int n)
+{
+    const int wi = p >> 6, sh = p & 63;
+    uint64_t v = word_at<W>(x, wi) >> sh;
+    if (sh + n > 64) v |= word_at<W>(x, wi + 1) << (64 - sh);
+    return (uint32_t)v & (n >= 32 ? 0xFFFFFFFFu : ((1u << n) - 1u));
+}
+
+// Occupancies of sites p, p+1, ..., p+n-1 taken mod L (0 <= p < L, n <= 32).
+template <int W>
+__device__ __forceinline__ uint32_t ring_bits(const uint64_t (&x)[W], int L, int p, int n)
+{
+    uint32_t bits = 0;
+    int got = 0;
+    while (got < n) {
+        const int take = min(n - got, L - p);
+        bits |= lin_bits<W>(x, p, take) << got;
+        got += take;
+        p = 0;
+    }
+    return bits;
+}
+
 // Exchange the occupancies across bond b (the two sites differ, so both flip).
 template <int W>
 __device__ __forceinline__ void hop(uint64_t (&x)[W], int b, int L)

@@ -11,7 +11,8 @@ constexpr int kMaxWords = 8;        // 64-site words per state
 constexpr int kMaxSites = 512;      // L <= kMaxSites
 constexpr int kLogRows = 96;        // rows of the logarithm table
 
-enum : uint32_t { TAG_INIT = 1, TAG_DYN = 2, TAG_RESAMPLE = 3, TAG_IID = 4 };
+enum : uint32_t { TAG_INIT = 1, TAG_DYN = 2, TAG_RESAMPLE = 3, TAG_IID = 4, TAG_GUIDE = 5 };
+constexpr int kGuideEntries = 8192; // 13-site bond neighbourhoods
 enum : int32_t { MODE_MODIFIED = 0, MODE_DIRECT = 1, MODE_GUIDED = 2 };
 enum : int32_t { SEL_EQ = 0, SEL_IID = 1 };
 
@@ -50,7 +51,8 @@ struct InstDev {
     double inv_scale;      // 1 / (rate of one allowed hop): e^{s} (modified) or 1
     const double* inv_count;// [kMaxSites + 1] 1 / r for r = 0..kMaxSites (shared)
     double* log;           // [log_cycles][2] (lbeta, mean K^beta)
-    const float* guide;    // [8192] guide table (guided mode)
+    const uint32_t* guide; // [8192] guide table e^g 2^16 over bond neighbourhoods
+    uint64_t guide_max;    // largest table entry (acceptance bound)
     const double* log_tab; // [kLogRows][4] table of the device logarithm
     double ln2_hi, ln2_lo; // ln 2 = ln2_hi (a multiple of 2^-42) + ln2_lo
     InstCtl* ctl;

@@ -10,7 +10,8 @@ namespace pd {
 // step order, all with W words per state.
 struct StepLaunch {
     int W;
-    int variant;           // 0: one clone per lane; 1: persistent queued waves
+    int variant;           // 0: one clone per lane; 1..3: persistent queued waves
+    bool guided;           // guided instances (always one clone per lane)
     int base, count;       // tiles
     int blocks;            // grid of the persistent variant
     int refill;            // finished lanes that trigger a refill (variant 1)

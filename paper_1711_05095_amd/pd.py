@@ -315,6 +315,12 @@ class Sampler:
     def load(self, blob):
         pd_load(self.ctx, blob)
 
+    def set_guide(self, table):
+        """table: a torch uint32-compatible int32 CUDA tensor of 8192 entries
+        (kept alive by the sampler)."""
+        self._guide = table
+        pd_set_guide(self.ctx, table.data_ptr(), table.numel())
+
     def tuning(self):
         return pd_get_tuning(self.ctx)
 

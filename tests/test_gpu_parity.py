@@ -243,6 +243,73 @@ def test_iid_whole_run_and_variance_against_eq():
     assert spread[pd.PD_SEL_EQ] < spread[IID], spread
 
 
+GUIDED = pd.PD_W_GUIDED
+
+
+def _guide_tensor(table):
+    return torch.from_numpy(table.view(np.int32).copy()).cuda()
+
+
+@pytest.mark.parametrize("L,N,s,Nc,table_seed", [(10, 5, 0.3, 1000, 1), (100, 50, 0.002, 1500, 2),
+                                                 (30, 14, -0.05, 300, 3), (400, 200, 1e-4, 257, 4),
+                                                 (6, 3, 0.5, 64, 5)])
+def test_guided_cycles_bit_exact(L, N, s, Nc, table_seed):
+    """Guided dynamics: states, hop counts and carried K bit-exact with the
+    oracle for the same guide table, weights to 1e-12, over several cycles."""
+    from guide_tables import random_table
+    print(f"guided L={L} s={s} Nc={Nc}", flush=True)
+    table = random_table(table_seed)
+    dt, M = 0.5, 5
+    p = pd.make_params(L, N, s, Nc, M * dt, dt, seed=17, weight_mode=GUIDED)
+    o = oracle.Oracle(L, N, s, Nc, dt, M=M, seed=17, mode=GUIDED, guide=table)
+    S = pd.Sampler(p)
+    S.set_guide(_guide_tensor(table))
+    occ, K = o.init()
+    for beta in range(1, M + 1):
+        S.step()
+        Kb_o, A_o, ell_o = o.step(beta, occ, K)
+        w_gpu, K_gpu = S.get_population()
+        Kb_g, A_g, ell_g = S.step_outputs()
+        assert np.array_equal(Kb_g, Kb_o), beta
+        assert np.array_equal(w_gpu, pack(occ)) and np.array_equal(K_gpu, K), beta
+        assert np.allclose(A_g, A_o, rtol=1e-12) and np.allclose(ell_g, ell_o, rtol=1e-11,
+                                                                 atol=1e-12), beta
+        S.resample()
+        anc = S.ancestors()
+        check_selection(anc, ell_o, o.eq_offset(beta), "guided interval %d" % beta)
+        occ, K = np.ascontiguousarray(occ[anc]), K[anc]
+
+
+def test_guided_whole_run_and_guide_validation():
+    from guide_tables import constant_table, random_table
+    w = inputs.SMALL
+    M = 200
+    table = random_table(9)
+    p = pd.make_params(w["L"], w["N"], 0.3, w["Nc"], M * w["dt"], w["dt"], seed=3,
+                       weight_mode=GUIDED)
+    S = pd.Sampler(p)
+    with pytest.raises(pd.PdError) as e:
+        S.run(1)
+    assert e.value.status == pd.PD_ESTATE
+    bad = table.copy()
+    bad[0] = 5   # a non-hop neighbourhood must hold 0
+    with pytest.raises(pd.PdError) as e:
+        S.set_guide(_guide_tensor(bad))
+    assert e.value.status == pd.PD_EINVAL
+    S.set_guide(_guide_tensor(table))
+    S.run(M)
+    r = oracle.Oracle(w["L"], w["N"], 0.3, w["Nc"], w["dt"], M=M, seed=3, mode=GUIDED,
+                      guide=table).run()
+    e = S.estimates()
+    assert e["hops"] == r["hops"] and e["psi"] == pytest.approx(r["psi"], rel=1e-9)
+    # constant table at s = 0: exactly the modified dynamics' identity weights
+    p0 = pd.make_params(w["L"], w["N"], 0.0, 500, 20 * w["dt"], w["dt"], weight_mode=GUIDED)
+    S0 = pd.Sampler(p0)
+    S0.set_guide(_guide_tensor(constant_table()))
+    S0.run(20)
+    assert S0.estimates()["psi"] == 0.0
+
+
 def test_launch_variants_bit_identical():
     """Neither kernel variant nor refill threshold nor graph length changes any
     result: every random number is keyed by clone slot."""
