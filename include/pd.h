@@ -89,6 +89,9 @@ typedef struct {
     int32_t  log_cycles;  /* >= 0: keep per-interval (ln mean Ups, mean K^beta) for the
                              first log_cycles intervals (see pd_get_log) */
     int64_t  burn_in;     /* >= 0: intervals left out of psi_burn (pd_estimates) */
+    int32_t  track_origin;/* 1: every clone carries the slot it descended from at the last
+                             pd_reset_origin (ancestral lines, Sec. 2.4); 0: off */
+    int32_t  reserved;    /* must be 0 */
 } pd_params;
 
 typedef struct {
@@ -160,6 +163,15 @@ pd_status pd_get_step_outputs(pd_ctx* ctx, int32_t inst, uint32_t* Kb, double* A
  * clone that new clone j was pulled from.  PD_ESTATE if no cloning stage has
  * run since the last dynamical stage.  Synchronises. */
 pd_status pd_get_ancestors(pd_ctx* ctx, int32_t inst, int32_t* anc);
+
+/* Ancestry (track_origin = 1): pd_reset_origin marks every clone of instance
+ * `inst` as its own origin (origin[j] = j); from then on a clone carries the
+ * origin of the clone it was pulled from at every cloning stage.
+ * pd_get_origin copies the current origins (int32, Nc entries); the number
+ * of clones with origin k is the descendant count of the clone that sat in
+ * slot k at the reset.  PD_ESTATE if tracking is off.  Both synchronise. */
+pd_status pd_reset_origin(pd_ctx* ctx, int32_t inst);
+pd_status pd_get_origin(pd_ctx* ctx, int32_t inst, int32_t* origin);
 
 /* Per-interval log of instance `inst` (params.log_cycles > 0): for interval
  * beta = 1..n_rows, lbeta[beta-1] = ln((1/Nc) sum_i Upsilon_i^beta) and

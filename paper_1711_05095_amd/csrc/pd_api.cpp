@@ -94,11 +94,13 @@ std::string validate(const pd_params& p)
     if (p.instance >= (1u << 24)) return "instance must be below 2^24";
     if (p.log_cycles < 0) return "log_cycles must be >= 0";
     if (p.burn_in < 0) return "burn_in must be >= 0";
+    if (p.track_origin != 0 && p.track_origin != 1) return "track_origin must be 0 or 1";
+    if (p.reserved != 0) return "reserved must be 0";
     return "";
 }
 
 struct Layout {
-    size_t state[2], K[2], Kb, A, ell, anc, ykey, tmax, tsum, thops, toff, log, ctl;
+    size_t state[2], K[2], Kb, A, ell, anc, origin[2], ykey, tmax, tsum, thops, toff, log, ctl;
     size_t end;
     int ntiles;
 };
@@ -120,6 +122,8 @@ Layout layout_of(const pd_params& p, size_t base)
     o.A = take(8 * Nc);
     o.ell = take(8 * Nc);
     o.anc = take(4 * Nc);
+    o.origin[0] = p.track_origin ? take(4 * Nc) : 0;
+    o.origin[1] = p.track_origin ? take(4 * Nc) : 0;
     o.ykey = (p.selection == PD_SEL_IID) ? take(8 * Nc) : 0;
     o.tmax = take(8 * (size_t)o.ntiles);
     o.tsum = take(8 * (size_t)o.ntiles);
@@ -178,6 +182,7 @@ struct pd_ctx {
     bool any_iid = false;
     bool any_guided = false;
     bool guide_set = false;
+    bool any_origin = false;
     int cur = 0;                     // buffer holding the population
     bool perm = false;               // population = state[cur][anc[j]]
     bool stepped = false;            // a dynamical stage awaits its cloning stage
@@ -240,7 +245,7 @@ pd_status apply_tuning(pd_ctx* ctx, const pd_tuning& t)
     PD_HIP(hipGetDevice(&dev));
     PD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     for (auto& g : ctx->steps) {
-        g.variant = g.guided ? 0 : t.step_variant;
+        g.variant = (g.guided || ctx->any_origin) ? 0 : t.step_variant;
         g.refill = t.refill;
         int per_cu = 0;
         PD_HIP(step_occupancy(g.W, g.variant, &per_cu));
@@ -344,6 +349,9 @@ pd_status pd_create(const pd_params* params, int32_t n, void* d_workspace, size_
         d.A = (double*)(b + o.A);
         d.ell = (double*)(b + o.ell);
         d.anc = (int32_t*)(b + o.anc);
+        d.origin[0] = o.origin[0] ? (int32_t*)(b + o.origin[0]) : nullptr;
+        d.origin[1] = o.origin[1] ? (int32_t*)(b + o.origin[1]) : nullptr;
+        if (p.track_origin) ctx->any_origin = true;
         d.ykey = o.ykey ? (double*)(b + o.ykey) : nullptr;
         d.tile_max = (double*)(b + o.tmax);
         d.tile_sum = (double*)(b + o.tsum);
@@ -771,6 +779,33 @@ pd_status pd_set_guide(pd_ctx* ctx, const uint32_t* d_table, size_t n)
                           hipMemcpyHostToDevice, ctx->stream));
     PD_HIP(hipStreamSynchronize(ctx->stream));
     ctx->guide_set = true;
+    return PD_OK;
+}
+
+pd_status pd_reset_origin(pd_ctx* ctx, int32_t inst)
+{
+    pd_status st = check_inst(ctx, inst);
+    if (st != PD_OK) return st;
+    if (!ctx->dev[inst].origin[0]) return fail(ctx, PD_ESTATE, "instance does not track origins");
+    if (ctx->stepped) return fail(ctx, PD_ESTATE, "reset between pd_step and pd_resample");
+    st = materialise(ctx);
+    if (st != PD_OK) return st;
+    PD_HIP(launch_iota_origin(ctx->d_insts, inst, ctx->params[inst].Nc, ctx->cur, ctx->stream));
+    PD_HIP(hipStreamSynchronize(ctx->stream));
+    return PD_OK;
+}
+
+pd_status pd_get_origin(pd_ctx* ctx, int32_t inst, int32_t* origin)
+{
+    pd_status st = check_inst(ctx, inst);
+    if (st != PD_OK) return st;
+    if (!origin) return fail(ctx, PD_EINVAL, "null output");
+    if (!ctx->dev[inst].origin[0]) return fail(ctx, PD_ESTATE, "instance does not track origins");
+    st = materialise(ctx);
+    if (st != PD_OK) return st;
+    PD_HIP(hipMemcpyAsync(origin, ctx->dev[inst].origin[ctx->cur],
+                          4 * (size_t)ctx->params[inst].Nc, hipMemcpyDeviceToHost, ctx->stream));
+    PD_HIP(hipStreamSynchronize(ctx->stream));
     return PD_OK;
 }
 

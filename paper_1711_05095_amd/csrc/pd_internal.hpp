@@ -43,6 +43,7 @@ struct InstDev {
     double* A;             // [Nc] integral of r dt over the last interval
     double* ell;           // [Nc] ln Ups of the last interval
     int32_t* anc;          // [Nc] ancestor map of the last cloning stage
+    int32_t* origin[2];    // [Nc] carried origin slots, two buffers (null: not tracked)
     double* ykey;          // [Nc] interval ends in spacing units ([iid] only)
     double* tile_max;      // [ntiles]
     double* tile_sum;      // [ntiles] sum of exp(ell - tile_max)

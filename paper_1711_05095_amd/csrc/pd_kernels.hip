@@ -215,6 +215,7 @@ __global__ __launch_bounds__(kTile) void k_step(const InstDev* __restrict__ inst
         gptr(I.Kb)[j] = kb;
         gptr(I.A)[j] = A;
         gptr(I.ell)[j] = ell;
+        if (I.origin[0]) gptr(I.origin[dst])[j] = gptr(I.origin[src])[from];
     }
     s_ell[tid] = ell;
     s_u[tid] = kb;
@@ -382,6 +383,7 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
         gptr(I.Kb)[j] = kb;
         gptr(I.A)[j] = A;
         gptr(I.ell)[j] = ell;
+        if (I.origin[0]) gptr(I.origin[dst])[j] = gptr(I.origin[src])[from];
     }
     s_ell[tid] = ell;
     s_u[tid] = kb;
@@ -768,6 +770,22 @@ __global__ __launch_bounds__(kTile) void k_gather(const InstDev* __restrict__ in
 #pragma unroll
     for (int w = 0; w < W; ++w) I.state[src ^ 1][w * Nc + j] = I.state[src][w * Nc + from];
     I.K[src ^ 1][j] = I.K[src][from];
+    if (I.origin[0]) I.origin[src ^ 1][j] = I.origin[src][from];
+}
+
+// origin[cur][j] = j for every clone of instance `inst`.
+__global__ void k_iota_origin(const InstDev* __restrict__ insts, int inst, int cur)
+{
+    const InstDev& I = insts[inst];
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < I.Nc) I.origin[cur][j] = (int32_t)j;
+}
+
+hipError_t launch_iota_origin(const InstDev* insts, int inst, int64_t Nc, int cur, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_iota_origin, dim3((unsigned)((Nc + 255) / 256)), dim3(256), 0, st, insts,
+                       inst, cur);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

@@ -28,6 +28,7 @@ hipError_t launch_resample(const InstDev* insts, const TileDesc* tiles, int ntil
                            hipStream_t st);
 hipError_t launch_select_iid(const InstDev* insts, const TileDesc* tiles, int ntiles,
                              hipStream_t st);
+hipError_t launch_iota_origin(const InstDev* insts, int inst, int64_t Nc, int cur, hipStream_t st);
 hipError_t launch_zero_ksum(const InstDev* insts, int n_inst, hipStream_t st);
 hipError_t launch_ksum(const InstDev* insts, const TileDesc* tiles, int ntiles, int cur,
                        int use_anc, hipStream_t st);

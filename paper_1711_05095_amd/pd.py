@@ -32,7 +32,8 @@ class PdParams(ctypes.Structure):
                 ("Nc", ctypes.c_int64), ("t_obs", ctypes.c_double), ("dt", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("selection", ctypes.c_int32),
                 ("weight_mode", ctypes.c_int32), ("instance", ctypes.c_uint32),
-                ("log_cycles", ctypes.c_int32), ("burn_in", ctypes.c_int64)]
+                ("log_cycles", ctypes.c_int32), ("burn_in", ctypes.c_int64),
+                ("track_origin", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class PdEstimates(ctypes.Structure):
@@ -84,6 +85,8 @@ def lib():
             "pd_save": [vp, vp, c.c_size_t],
             "pd_load": [vp, vp, c.c_size_t],
             "pd_set_guide": [vp, vp, c.c_size_t],
+            "pd_reset_origin": [vp, c.c_int32],
+            "pd_get_origin": [vp, c.c_int32, vp],
             "pd_get_tuning": [vp, P(PdTuning)],
             "pd_set_tuning": [vp, P(PdTuning)],
             "pd_autotune": [vp, c.c_int32, P(PdTuning)],
@@ -111,10 +114,11 @@ def _ptr(a):
 
 
 def make_params(L, N, s, Nc, t_obs, dt, seed=0, selection=PD_SEL_EQ, weight_mode=PD_W_MODIFIED,
-                instance=0, log_cycles=0, burn_in=0):
+                instance=0, log_cycles=0, burn_in=0, track_origin=0):
     return PdParams(L=L, N=N, s=float(s), Nc=int(Nc), t_obs=float(t_obs), dt=float(dt),
                     seed=int(seed), selection=selection, weight_mode=weight_mode,
-                    instance=instance, log_cycles=log_cycles, burn_in=int(burn_in))
+                    instance=instance, log_cycles=log_cycles, burn_in=int(burn_in),
+                    track_origin=int(track_origin), reserved=0)
 
 
 def _param_array(params):
@@ -220,6 +224,16 @@ def pd_load(ctx, blob):
     _check(lib().pd_load(ctx, _ptr(blob), blob.nbytes), ctx)
 
 
+def pd_reset_origin(ctx, inst=0):
+    _check(lib().pd_reset_origin(ctx, inst), ctx)
+
+
+def pd_get_origin(ctx, inst, Nc):
+    out = np.empty(Nc, np.int32)
+    _check(lib().pd_get_origin(ctx, inst, _ptr(out)), ctx)
+    return out
+
+
 def _tuning_dict(t):
     return dict(step_variant=t.step_variant, refill=t.refill, graph_cycles=t.graph_cycles)
 
@@ -320,6 +334,12 @@ class Sampler:
         (kept alive by the sampler)."""
         self._guide = table
         pd_set_guide(self.ctx, table.data_ptr(), table.numel())
+
+    def reset_origin(self, inst=0):
+        pd_reset_origin(self.ctx, inst)
+
+    def origin(self, inst=0):
+        return pd_get_origin(self.ctx, inst, self.params[inst].Nc)
 
     def tuning(self):
         return pd_get_tuning(self.ctx)

@@ -310,6 +310,24 @@ def test_guided_whole_run_and_guide_validation():
     assert S0.estimates()["psi"] == 0.0
 
 
+def test_origin_tracking_composes_ancestor_maps():
+    """Carried origins equal the composition of the cloning stages' ancestor
+    maps, and descendant counts sum to Nc."""
+    L, N, Nc, M = 100, 50, 3000, 12
+    p = pd.make_params(L, N, 0.002, Nc, 40 * 0.5, 0.5, seed=4, track_origin=1)
+    S = pd.Sampler(p)
+    S.run(5)
+    S.reset_origin()
+    assert np.array_equal(S.origin(), np.arange(Nc, dtype=np.int32))
+    comp = np.arange(Nc)
+    for _ in range(M):
+        S.step()
+        S.resample()
+        comp = comp[S.ancestors()]
+    assert np.array_equal(S.origin(), comp)
+    assert np.bincount(S.origin(), minlength=Nc).sum() == Nc
+
+
 def test_launch_variants_bit_identical():
     """Neither kernel variant nor refill threshold nor graph length changes any
     result: every random number is keyed by clone slot."""
