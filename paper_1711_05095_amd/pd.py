@@ -23,7 +23,7 @@ PD_MAX_L = 512
 EXPORTS = ["pd_workspace_bytes", "pd_create", "pd_destroy", "pd_step", "pd_resample", "pd_run",
            "pd_scgf", "pd_estimates_get", "pd_population_bytes", "pd_get_population",
            "pd_set_population", "pd_get_step_outputs", "pd_get_ancestors", "pd_get_log",
-           "pd_save_bytes", "pd_save", "pd_load", "pd_set_guide", "pd_get_tuning",
+           "pd_save_bytes", "pd_save", "pd_load", "pd_set_guide", "pd_reset_origin", "pd_get_origin", "pd_get_tuning",
            "pd_set_tuning", "pd_autotune", "pd_last_error", "pd_status_str"]
 
 
