@@ -1,0 +1,122 @@
+// C ABI of the guide network (include/pd_guide.h): argument checks, then the
+// kernels of pd_guide.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <string>
+
+#include "../../include/pd_guide.h"
+#include "pd_guide.hpp"
+
+using namespace pd;
+
+static_assert(PDG_PARAMS == kGuideParams, "parameter count");
+static_assert(PDG_MIN_L == kGuideMinL, "smallest ring");
+
+namespace {
+
+thread_local std::string g_guide_error;
+
+pd_status gfail(pd_status st, const std::string& msg)
+{
+    g_guide_error = msg;
+    return st;
+}
+
+pd_status gdev(hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return PD_OK;
+    return gfail(PD_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool aligned256(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
+
+std::string check_batch(const void* states, int64_t ld, int32_t L, int64_t n)
+{
+    if (!states) return "null states";
+    if (L < kGuideMinL || L > PD_MAX_L) return "L out of range";
+    if (n < 1 || n > INT32_MAX) return "n out of range";
+    if (ld < n || ld > INT32_MAX) return "ld must satisfy n <= ld <= 2^31 - 1";
+    return "";
+}
+
+// Dynamic LDS of the sample kernels grows with L; raise the limit once per L.
+pd_status smem_limit(int L)
+{
+    thread_local int done_for = 0;
+    const int LP = (L + 15) / 16 * 16;
+    if (LP <= done_for) return PD_OK;
+    pd_status st = gdev(net_set_smem_limit(PD_MAX_L), "hipFuncSetAttribute");
+    if (st == PD_OK) done_for = PD_MAX_L;
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+pd_status pdg_workspace_bytes(int64_t n, size_t* bytes)
+{
+    if (!bytes || n < 1 || n > INT32_MAX) return gfail(PD_EINVAL, "null argument or n out of range");
+    *bytes = (size_t)guide_blocks(n) * (kGuideParams + 1) * sizeof(float);
+    return PD_OK;
+}
+
+pd_status pdg_forward(const float* theta, const uint64_t* states, int64_t ld, int32_t L,
+                      int64_t n, float* f_out, void* hip_stream)
+{
+    std::string m = check_batch(states, ld, L, n);
+    if (!m.empty()) return gfail(PD_EINVAL, m);
+    if (!theta || !f_out) return gfail(PD_EINVAL, "null pointer");
+    pd_status st = smem_limit(L);
+    if (st != PD_OK) return st;
+    return gdev(launch_net(0, theta, states, ld, nullptr, L, n, f_out, nullptr, nullptr, nullptr,
+                           (hipStream_t)hip_stream),
+                "forward launch");
+}
+
+pd_status pdg_loss_grad(const float* theta, const uint64_t* states, int64_t ld,
+                        const float* counts, int32_t L, int64_t n, float* grad, float* loss,
+                        void* work, size_t work_bytes, void* hip_stream)
+{
+    std::string m = check_batch(states, ld, L, n);
+    if (!m.empty()) return gfail(PD_EINVAL, m);
+    if (!theta || !counts || !grad || !work) return gfail(PD_EINVAL, "null pointer");
+    if (!aligned256(work)) return gfail(PD_EINVAL, "workspace must be 256-byte aligned");
+    size_t need = 0;
+    pdg_workspace_bytes(n, &need);
+    if (work_bytes < need) return gfail(PD_ENOMEM, "workspace too small");
+    pd_status st = smem_limit(L);
+    if (st != PD_OK) return st;
+    return gdev(launch_net(1, theta, states, ld, counts, L, n, nullptr, (float*)work, grad, loss,
+                           (hipStream_t)hip_stream),
+                "loss/gradient launch");
+}
+
+pd_status pdg_adam(float* theta, float* m, float* v, const float* grad, int32_t step, float lr,
+                   void* hip_stream)
+{
+    if (!theta || !m || !v || !grad) return gfail(PD_EINVAL, "null pointer");
+    if (step < 1 || !(lr > 0.0f) || !std::isfinite(lr)) return gfail(PD_EINVAL, "step < 1 or lr <= 0");
+    return gdev(launch_adam(theta, m, v, grad, step, lr, (hipStream_t)hip_stream), "adam launch");
+}
+
+pd_status pdg_window_table(const float* theta, float* table, void* hip_stream)
+{
+    if (!theta || !table) return gfail(PD_EINVAL, "null pointer");
+    return gdev(launch_window_table(theta, table, (hipStream_t)hip_stream), "window table launch");
+}
+
+pd_status pdg_bond_table(const float* window_table, double gmax, uint32_t* eg, double* G,
+                         void* hip_stream)
+{
+    if (!window_table || !eg) return gfail(PD_EINVAL, "null pointer");
+    if (!(gmax >= 0.0) || !(gmax <= PDG_MAX_GMAX)) return gfail(PD_EINVAL, "gmax out of range");
+    return gdev(launch_bond_table(window_table, gmax, eg, G, (hipStream_t)hip_stream),
+                "bond table launch");
+}
+
+const char* pdg_last_error(void) { return g_guide_error.c_str(); }
+
+}  // extern "C"

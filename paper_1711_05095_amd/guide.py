@@ -1,0 +1,140 @@
+"""Learning a guide from the plain algorithm's own populations, and turning it
+into the bond table of the guided dynamics.
+
+Sec. 2.4 of the paper: after a long lag, the expected number of descendants
+of a clone in configuration C is proportional to v(C), the dominant right
+eigenvector of the tilted generator (for the SSEP the generator is symmetric,
+so left and right eigenvectors coincide).  Sec. 2.2: hop rates multiplied by
+v(C')/v(C) with the compensating weight give an unbiased estimator whose
+cloning factors barely vary.  So:
+
+  1. collect: run the plain algorithm with carried origin ids; at a snapshot
+     record every clone's configuration, reset the origins, run `lag` more
+     intervals and count each snapshot clone's descendants;
+  2. train: Poisson regression of the counts on f(C) + c0 (f the circular
+     convolutional net of include/pd_guide.h), Adam, all on the GPU kernels;
+  3. distil: window table h (f = sum of h over the sites), then the 8192-entry
+     bond table eg = 2^16 exp(average change of f across the hop), which
+     pd_set_guide takes.
+
+Everything that computes runs in libpd.so; this module moves data between
+the sampler, the host (the counts are a histogram of origin ids) and the
+training kernels.
+"""
+import numpy as np
+import torch
+
+from . import guide_net as gnet
+from . import inputs, pd
+
+
+def collect(L, N, s, Nc, dt, lag_cycles, snapshots, burn_cycles, seed, instance=0):
+    """Training data from plain (modified-rate) runs: configurations [W, n]
+    uint64 and descendant counts float32 [n], n = snapshots * Nc."""
+    cycles = burn_cycles + snapshots * lag_cycles
+    p = pd.make_params(L, N, s, Nc, cycles * dt, dt, seed=seed, instance=instance,
+                       track_origin=1)
+    sm = pd.Sampler(p)
+    try:
+        if burn_cycles:
+            sm.run(burn_cycles)
+        states, counts = [], []
+        for _ in range(snapshots):
+            words, _ = sm.get_population()
+            sm.reset_origin()
+            sm.run(lag_cycles)
+            origin = sm.origin()
+            states.append(words)
+            counts.append(np.bincount(origin, minlength=Nc).astype(np.float32))
+        return np.concatenate(states, axis=1), np.concatenate(counts)
+    finally:
+        sm.close()
+
+
+class Trainer:
+    """FP32 master parameters, Adam moments and the gradient workspace on the
+    GPU; every step is pdg_loss_grad + pdg_adam."""
+
+    def __init__(self, L, theta0=None, seed=0, lr=3e-3, batch=8192, device="cuda"):
+        self.L = L
+        self.lr = lr
+        self.batch = batch
+        th = inputs.guide_theta0(seed) if theta0 is None else np.asarray(theta0, np.float32)
+        self.theta = torch.from_numpy(th.copy()).to(device)
+        self.m = torch.zeros_like(self.theta)
+        self.v = torch.zeros_like(self.theta)
+        self.grad = torch.zeros_like(self.theta)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=device)
+        self.work = torch.empty(gnet.workspace_bytes(batch), dtype=torch.uint8, device=device)
+        self.steps = 0
+
+    @staticmethod
+    def upload(states, counts, seed=0, device="cuda"):
+        """Shuffles the samples (seeded) and moves them to the GPU:
+        (int64 [W, n], float32 [n])."""
+        perm = np.random.default_rng(seed).permutation(states.shape[1])
+        s = torch.from_numpy(np.ascontiguousarray(states[:, perm]).view(np.int64)).to(device)
+        c = torch.from_numpy(np.ascontiguousarray(counts[perm], np.float32)).to(device)
+        return s, c
+
+    def epoch(self, states, counts):
+        """One pass over the samples in minibatches; returns the mean
+        minibatch loss (synchronises)."""
+        n = states.shape[1]
+        total = torch.zeros((), dtype=torch.float64, device=self.theta.device)
+        k = 0
+        for a in range(0, n, self.batch):
+            b = min(n, a + self.batch)
+            gnet.loss_grad(self.theta, states[:, a:b], counts[a:b], self.L, self.grad, self.loss,
+                           self.work)
+            self.steps += 1
+            gnet.adam(self.theta, self.m, self.v, self.grad, self.steps, self.lr)
+            total += self.loss[0].double()
+            k += 1
+        return float(total.item()) / k
+
+    def evaluate(self, states, counts):
+        """Loss over all samples with the current parameters (no update)."""
+        n = states.shape[1]
+        work = torch.empty(gnet.workspace_bytes(n), dtype=torch.uint8, device=self.theta.device)
+        grad = torch.empty_like(self.grad)
+        gnet.loss_grad(self.theta, states, counts, self.L, grad, self.loss, work)
+        return float(self.loss.item())
+
+    def f(self, states):
+        out = torch.empty(states.shape[1], dtype=torch.float32, device=self.theta.device)
+        gnet.forward(self.theta, states, self.L, out)
+        return out
+
+    def tables(self, gmax=gnet.PDG_MAX_GMAX):
+        """(window table float32[8192], bond table int32[8192], G float64[8192]),
+        complete on return (the sampler reads the bond table on its own stream)."""
+        dev = self.theta.device
+        H = torch.empty(gnet.PDG_WINDOWS, dtype=torch.float32, device=dev)
+        eg = torch.empty(gnet.PDG_WINDOWS, dtype=torch.int32, device=dev)
+        G = torch.empty(gnet.PDG_WINDOWS, dtype=torch.float64, device=dev)
+        gnet.window_table(self.theta, H)
+        gnet.bond_table(H, gmax, eg, G)
+        torch.cuda.current_stream().synchronize()
+        return H, eg, G
+
+
+def train_guide(L, N, s, Nc=100_000, dt=0.5, lag_cycles=20, snapshots=10, burn_cycles=200,
+                epochs=8, batch=8192, lr=3e-3, gmax=gnet.PDG_MAX_GMAX, seed=0, log=None):
+    """Collect, train and distil; returns a dict with the trainer, the bond
+    table eg (int32 CUDA tensor, for Sampler.set_guide) and the loss history."""
+    states, counts = collect(L, N, s, Nc, dt, lag_cycles, snapshots, burn_cycles, seed)
+    n = states.shape[1]
+    n_val = max(n // 10, 1)
+    S, C = Trainer.upload(states, counts, seed=seed + 1)
+    tr = Trainer(L, seed=seed + 2, lr=lr, batch=batch)
+    S_tr, C_tr = S[:, n_val:], C[n_val:]
+    S_va, C_va = S[:, :n_val], C[:n_val]
+    hist = dict(train=[], val=[tr.evaluate(S_va, C_va)])
+    for e in range(epochs):
+        hist["train"].append(tr.epoch(S_tr, C_tr))
+        hist["val"].append(tr.evaluate(S_va, C_va))
+        if log:
+            log("epoch %d: train %.5f  validation %.5f" % (e + 1, hist["train"][-1], hist["val"][-1]))
+    H, eg, G = tr.tables(gmax)
+    return dict(trainer=tr, eg=eg, G=G, H=H, history=hist, samples=n)

@@ -72,3 +72,15 @@ def random_log_weights(Nc, seed, spread=1.0, zeros=0.0):
         mask = rng.random(Nc) < zeros
         ell[mask] -= 700.0
     return ell
+
+
+def guide_theta0(seed):
+    """Initial parameters of the guide network (flat float32, layout of
+    include/pd_guide.h): weights uniform in +-1/sqrt(fan-in), the last layer
+    scaled by 0.1 so that the untrained guide is close to flat; biases 0."""
+    rng = np.random.default_rng(seed)
+    th = np.zeros(5506, np.float32)
+    th[0:160] = rng.uniform(-1, 1, 160) / np.sqrt(5.0)
+    th[192:5312] = rng.uniform(-1, 1, 5120) / np.sqrt(160.0)
+    th[5344:5504] = rng.uniform(-1, 1, 160) / np.sqrt(160.0) * 0.1
+    return th

@@ -6,24 +6,63 @@ import re
 
 import pytest
 
-from paper_1711_05095_amd import pd
+from paper_1711_05095_amd import guide_net, pd
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def declared():
-    text = open(os.path.join(ROOT, "include", "pd.h")).read()
-    return sorted(set(re.findall(r"^(?:pd_status|const char\*)\s+(pd_\w+)\(", text, re.M)))
+def declared(header="pd.h", prefix="pd_"):
+    text = open(os.path.join(ROOT, "include", header)).read()
+    return sorted(set(re.findall(r"^(?:pd_status|const char\*)\s+(%s\w+)\(" % prefix, text,
+                                 re.M)))
 
 
 def test_header_and_binding_agree():
     assert declared() == sorted(pd.EXPORTS)
+    assert declared("pd_guide.h", "pdg_") == sorted(guide_net.EXPORTS)
 
 
 def test_library_exports_every_symbol():
     lib = pd.lib()
-    for name in declared():
+    for name in declared() + declared("pd_guide.h", "pdg_"):
         assert hasattr(lib, name), name
+
+
+def test_guide_constants_match_header():
+    text = open(os.path.join(ROOT, "include", "pd_guide.h")).read()
+    for name in ("PDG_PARAMS", "PDG_WINDOWS", "PDG_MIN_L", "PDG_MAX_GMAX"):
+        v = re.search(r"#define %s ([0-9.]+)" % name, text).group(1)
+        assert float(v) == getattr(guide_net, name), name
+    from oracle import guide_net as ref
+    assert guide_net.PDG_PARAMS == ref.PARAMS
+
+
+def test_guide_host_validation():
+    """Invalid arguments are rejected before any device work is queued."""
+    lib = guide_net.lib()
+    vp = ctypes.c_void_p
+    out = ctypes.c_size_t()
+    assert lib.pdg_workspace_bytes(0, ctypes.byref(out)) == pd.PD_EINVAL
+    assert lib.pdg_workspace_bytes(100, ctypes.byref(out)) == pd.PD_OK
+    assert out.value == 100 * (guide_net.PDG_PARAMS + 1) * 4
+    assert lib.pdg_workspace_bytes(10**6, ctypes.byref(out)) == pd.PD_OK
+    assert out.value == 768 * (guide_net.PDG_PARAMS + 1) * 4
+    fake = vp(4096)
+    assert lib.pdg_forward(fake, fake, 10, 4, 10, fake, None) == pd.PD_EINVAL  # L < 5
+    assert lib.pdg_forward(fake, fake, 10, 513, 10, fake, None) == pd.PD_EINVAL
+    assert lib.pdg_forward(fake, fake, 10, 20, 0, fake, None) == pd.PD_EINVAL
+    assert lib.pdg_forward(fake, fake, 9, 20, 10, fake, None) == pd.PD_EINVAL   # ld < n
+    assert lib.pdg_forward(None, fake, 10, 20, 10, fake, None) == pd.PD_EINVAL
+    assert lib.pdg_loss_grad(fake, fake, 10, fake, 20, 10, fake, None, vp(4097), 1 << 30,
+                             None) == pd.PD_EINVAL                             # misaligned
+    assert lib.pdg_loss_grad(fake, fake, 10, fake, 20, 10, fake, None, fake, 100,
+                             None) == pd.PD_ENOMEM
+    assert b"too small" in lib.pdg_last_error()
+    assert lib.pdg_adam(fake, fake, fake, fake, 0, 1e-3, None) == pd.PD_EINVAL
+    assert lib.pdg_adam(fake, fake, fake, fake, 1, -1.0, None) == pd.PD_EINVAL
+    assert lib.pdg_bond_table(fake, 3.5, fake, None, None) == pd.PD_EINVAL
+    assert lib.pdg_bond_table(fake, float("nan"), fake, None, None) == pd.PD_EINVAL
+    assert lib.pdg_window_table(None, fake, None) == pd.PD_EINVAL
 
 
 def test_status_strings():
