@@ -166,3 +166,49 @@ def adam(theta, m, v, g, step, lr, b1=0.9, b2=0.999, eps=1e-8):
     mh = m / (1 - b1 ** step)
     vh = v / (1 - b2 ** step)
     return theta - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def bond_deltas(H, occ):
+    """For every configuration in occ (uint8 [B, L], L >= 26) and every bond
+    (b, b+1) whose sites differ: the neighbourhood u of the bond (site b-6 in
+    bit 0 ... b+6 in bit 12) and d = f(C after the hop) - f(C), computed as
+    the 14 windows holding b or b+1 after minus before (the other windows do
+    not change).  Returns (u int64 [m], d float64 [m]) in (sample, bond) order."""
+    H = np.asarray(H, np.float64)
+    B, L = occ.shape
+    assert L >= 26
+    us, ds = [], []
+    for i in range(B):
+        for b in range(L):
+            if occ[i, b] == occ[i, (b + 1) % L]:
+                continue
+            w0 = 0
+            for k in range(26):
+                w0 |= int(occ[i, (b - 12 + k) % L]) << k
+            w1 = w0 ^ (3 << 12)
+            d = 0.0
+            for o in range(14):
+                d += H[(w1 >> o) & 0x1FFF] - H[(w0 >> o) & 0x1FFF]
+            us.append((w0 >> 6) & 0x1FFF)
+            ds.append(d)
+    return np.array(us, np.int64), np.array(ds)
+
+
+def distill_conditional(H, occ, gmax, min_count):
+    """Bond table conditioned on data: G[u] = mean of d over the (sample,
+    bond) pairs of occ with neighbourhood u (bond_deltas) where u occurs at
+    least min_count times, else the uniform-context average of distill();
+    eg = round(2^16 exp(clip(G, -gmax, gmax))), 0 for non-hop u.  Also
+    returns the counts."""
+    _, G = distill(H, gmax)
+    u, d = bond_deltas(H, occ)
+    cnt = np.bincount(u, minlength=8192)
+    sm = np.bincount(u, weights=d, minlength=8192)
+    seen = cnt >= max(min_count, 1)
+    G = np.where(seen, sm / np.maximum(cnt, 1), G)
+    eg = np.zeros(8192, np.uint32)
+    hop = ((np.arange(8192) >> 6) ^ (np.arange(8192) >> 7)) & 1
+    for v in np.nonzero(hop)[0]:
+        eg[v] = int(np.rint(65536.0 * np.exp(np.clip(G[v], -gmax, gmax))))
+    G = np.where(hop == 1, G, 0.0)
+    return eg, G, cnt

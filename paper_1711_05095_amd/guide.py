@@ -77,9 +77,10 @@ class Trainer:
         c = torch.from_numpy(np.ascontiguousarray(counts[perm], np.float32)).to(device)
         return s, c
 
-    def epoch(self, states, counts):
-        """One pass over the samples in minibatches; returns the mean
-        minibatch loss (synchronises)."""
+    def epoch(self, states, counts, lr=None):
+        """One pass over the samples in minibatches (learning rate `lr`, default
+        the trainer's); returns the mean minibatch loss (synchronises)."""
+        lr = self.lr if lr is None else lr
         n = states.shape[1]
         total = torch.zeros((), dtype=torch.float64, device=self.theta.device)
         k = 0
@@ -88,7 +89,7 @@ class Trainer:
             gnet.loss_grad(self.theta, states[:, a:b], counts[a:b], self.L, self.grad, self.loss,
                            self.work)
             self.steps += 1
-            gnet.adam(self.theta, self.m, self.v, self.grad, self.steps, self.lr)
+            gnet.adam(self.theta, self.m, self.v, self.grad, self.steps, lr)
             total += self.loss[0].double()
             k += 1
         return float(total.item()) / k
@@ -120,9 +121,10 @@ class Trainer:
 
 
 def train_guide(L, N, s, Nc=100_000, dt=0.5, lag_cycles=20, snapshots=10, burn_cycles=200,
-                epochs=8, batch=8192, lr=3e-3, gmax=gnet.PDG_MAX_GMAX, seed=0, log=None):
-    """Collect, train and distil; returns a dict with the trainer, the bond
-    table eg (int32 CUDA tensor, for Sampler.set_guide) and the loss history."""
+                epochs=8, batch=8192, lr=1e-3, decay=0.7, gmax=1.0, seed=0, log=None):
+    """Collect, train (learning rate lr * decay^epoch) and distil; returns a
+    dict with the trainer, the bond table eg (int32 CUDA tensor, for
+    Sampler.set_guide) and the loss history."""
     states, counts = collect(L, N, s, Nc, dt, lag_cycles, snapshots, burn_cycles, seed)
     n = states.shape[1]
     n_val = max(n // 10, 1)
@@ -132,7 +134,7 @@ def train_guide(L, N, s, Nc=100_000, dt=0.5, lag_cycles=20, snapshots=10, burn_c
     S_va, C_va = S[:, :n_val], C[:n_val]
     hist = dict(train=[], val=[tr.evaluate(S_va, C_va)])
     for e in range(epochs):
-        hist["train"].append(tr.epoch(S_tr, C_tr))
+        hist["train"].append(tr.epoch(S_tr, C_tr, lr * decay ** e))
         hist["val"].append(tr.evaluate(S_va, C_va))
         if log:
             log("epoch %d: train %.5f  validation %.5f" % (e + 1, hist["train"][-1], hist["val"][-1]))

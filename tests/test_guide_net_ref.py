@@ -92,3 +92,55 @@ def test_bf16_rounding():
     r = gn.bf16(x)
     assert r[0] == 1.0 and r[1] == 1.0 and r[2] == 1.0078125   # ties to even, then up
     assert abs(r[3] - x[3]) <= 2 ** -8 * abs(x[3])
+
+
+def test_bond_deltas_are_exact_log_ratios():
+    """On rings of L >= 26 sites the 14-window difference is the net's exact
+    f(C after the hop) - f(C), checked by running the whole circular network
+    on both configurations."""
+    th = gn.init_theta(9)
+    th[gn.OFF_W3:gn.OFF_B3] *= 10
+    H = gn.window_table(th)
+    for L in (26, 31):
+        occ = inputs.random_population(L, L // 2, 3, seed=L)
+        u, d = gn.bond_deltas(H, occ)
+        k = 0
+        for i in range(3):
+            f0, _ = gn.forward(th, occ[i:i + 1])
+            for b in range(L):
+                b2 = (b + 1) % L
+                if occ[i, b] == occ[i, b2]:
+                    continue
+                c = occ[i:i + 1].copy()
+                c[0, b], c[0, b2] = c[0, b2], c[0, b]
+                f1, _ = gn.forward(th, c)
+                assert d[k] == pytest.approx(f1[0] - f0[0], rel=1e-9, abs=1e-9)
+                want_u = sum(int(occ[i, (b - 6 + o) % L]) << o for o in range(13))
+                assert u[k] == want_u
+                k += 1
+        assert k == len(d)
+
+
+def test_conditional_table_is_the_mean_per_neighbourhood():
+    """G[u] is the plain mean of the deltas sharing u where u is seen at least
+    min_count times, and the uniform-context value elsewhere."""
+    th = gn.init_theta(10)
+    th[gn.OFF_W3:gn.OFF_B3] *= 10
+    H = gn.window_table(th)
+    occ = inputs.random_population(40, 20, 30, seed=11)
+    eg, G, cnt = gn.distill_conditional(H, occ, gmax=0.3, min_count=2)
+    u, d = gn.bond_deltas(H, occ)
+    groups = {}
+    for a, b in zip(u, d):
+        groups.setdefault(int(a), []).append(b)
+    _, G_uni = gn.distill(H, 0.3)
+    assert sum(len(v) for v in groups.values()) == cnt.sum() == len(d)
+    for v in range(8192):
+        if ((v >> 6) & 1) == ((v >> 7) & 1):
+            assert eg[v] == 0 and G[v] == 0.0 and v not in groups
+            continue
+        if len(groups.get(v, [])) >= 2:
+            assert G[v] == pytest.approx(np.mean(groups[v]), rel=1e-12, abs=1e-15)
+        else:
+            assert G[v] == G_uni[v]
+        assert eg[v] == int(np.rint(65536.0 * np.exp(np.clip(G[v], -0.3, 0.3))))
