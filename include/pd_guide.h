@@ -93,6 +93,26 @@ pd_status pdg_window_table(const float* theta, float* table, void* hip_stream);
 pd_status pdg_bond_table(const float* window_table, double gmax, uint32_t* eg, double* G,
                          void* hip_stream);
 
+/* Bond table conditioned on a sample of configurations (states as in
+ * pdg_forward; L >= PDG_COND_MIN_L so that the windows around a bond span
+ * distinct sites): for every configuration and every bond whose two sites
+ * differ, d = f(C after the hop) - f(C) exactly (the 14 windows holding b or
+ * b+1, after minus before, summed in double precision); G[u] = the mean of d
+ * over the pairs with neighbourhood u if there are at least min_count (>= 1)
+ * of them, else the uniform-context value of pdg_bond_table; eg as there.
+ * The mean over the data is the best table entry in the least-squares sense
+ * for configurations drawn like the sample, which the uniform average is not
+ * when distant sites are correlated with the neighbourhood (phase-separated
+ * populations, Sec. 3.3).  counts (uint32[8192], may be NULL) receives the
+ * number of pairs per u; G may be NULL.  `work` is device scratch of
+ * PDG_COND_WORK_BYTES bytes, 256-byte aligned. */
+#define PDG_COND_MIN_L 26
+#define PDG_COND_WORK_BYTES 163840
+pd_status pdg_bond_table_cond(const float* window_table, const uint64_t* states, int64_t ld,
+                              int32_t L, int64_t n, int32_t min_count, double gmax, uint32_t* eg,
+                              double* G, uint32_t* counts, void* work, size_t work_bytes,
+                              void* hip_stream);
+
 const char* pdg_last_error(void);
 
 #ifdef __cplusplus

@@ -471,6 +471,93 @@ __global__ __launch_bounds__(256) void k_bond_table(const float* __restrict__ H,
 }
 
 // ---------------------------------------------------------------------------
+// Bond table conditioned on data: for every configuration of a sample set and
+// every allowed bond b, d = f(C after the hop) - f(C), exactly the 14 windows
+// holding b or b+1 after minus before (the ring has L >= 26 sites, so those
+// windows span 26 distinct sites b-12..b+13); d is summed per neighbourhood u
+// (sites b-6..b+6).  Sums and counts are privatised per block in LDS and then
+// added to the global accumulators.
+// ---------------------------------------------------------------------------
+constexpr int kStatThreads = 256;
+constexpr size_t kStatSmem = 8192 * (sizeof(float) + sizeof(double) + sizeof(uint32_t));
+
+template <int W>
+__global__ __launch_bounds__(kStatThreads) void k_bond_stats(const float* __restrict__ H,
+                                                             const uint64_t* __restrict__ states,
+                                                             int64_t ld, int L, int64_t n,
+                                                             double* __restrict__ sums,
+                                                             uint32_t* __restrict__ counts)
+{
+    extern __shared__ __align__(16) char smem[];
+    double* s_sum = (double*)smem;
+    float* s_H = (float*)(s_sum + 8192);
+    uint32_t* s_cnt = (uint32_t*)(s_H + 8192);
+    for (int i = threadIdx.x; i < 8192; i += kStatThreads) {
+        s_sum[i] = 0.0;
+        s_cnt[i] = 0u;
+        s_H[i] = H[i];
+    }
+    __syncthreads();
+    const int lb = (L - 1) & 63;
+    for (int64_t i = (int64_t)blockIdx.x * kStatThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kStatThreads) {
+        uint64_t x[W], m[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) x[w] = states[w * ld + i];
+        bond_mask<W>(x, lb, m);
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            uint64_t bits = m[w];
+            while (bits) {
+                const int b = w * 64 + __builtin_ctzll(bits);
+                bits &= bits - 1;
+                const uint32_t w0 = ring_bits<W>(x, L, b >= 12 ? b - 12 : b - 12 + L, 26);
+                const uint32_t w1 = w0 ^ (3u << 12);
+                double d = 0.0;
+#pragma unroll
+                for (int o = 0; o < 14; ++o)
+                    d += ((double)s_H[(w1 >> o) & 0x1FFFu] - (double)s_H[(w0 >> o) & 0x1FFFu]);
+                const uint32_t u = (w0 >> 6) & 0x1FFFu;
+                atomicAdd(&s_sum[u], d);
+                atomicAdd(&s_cnt[u], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    for (int u = threadIdx.x; u < 8192; u += kStatThreads)
+        if (s_cnt[u]) {
+            atomicAdd(&sums[u], s_sum[u]);
+            atomicAdd(&counts[u], s_cnt[u]);
+        }
+}
+
+__global__ void k_zero_stats(double* __restrict__ sums, uint32_t* __restrict__ counts)
+{
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u < 8192) {
+        sums[u] = 0.0;
+        counts[u] = 0u;
+    }
+}
+
+// G = mean where the neighbourhood was seen at least min_count times, else the
+// uniform-context value already in G; then the clipped integer table.
+__global__ void k_cond_finish(const double* __restrict__ sums, const uint32_t* __restrict__ counts,
+                              uint32_t min_count, double gmax, double* __restrict__ G,
+                              uint32_t* __restrict__ eg, uint32_t* __restrict__ counts_out)
+{
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= 8192) return;
+    const uint32_t c = counts[u];
+    if (counts_out) counts_out[u] = c;
+    if (!((u >> 6 ^ u >> 7) & 1)) return;   // k_bond_table wrote 0 to eg and G
+    double g = G[u];
+    if (c >= min_count) g = sums[u] / (double)c;
+    G[u] = g;
+    eg[u] = (uint32_t)rint(65536.0 * exp(fmin(fmax(g, -gmax), gmax)));
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 int guide_blocks(int64_t n) { return (int)(n < kGuideBlocks ? n : kGuideBlocks); }
@@ -521,6 +608,47 @@ hipError_t launch_window_table(const float* theta, float* table, hipStream_t st)
 {
     hipLaunchKernelGGL(k_window_table, dim3(8192 / 16), dim3(64), 0, st, theta, table);
     return hipGetLastError();
+}
+
+hipError_t launch_bond_table_cond(const float* H, const uint64_t* states, int64_t ld, int L,
+                                  int64_t n, uint32_t min_count, double gmax, uint32_t* eg,
+                                  double* G, uint32_t* counts_out, void* work, hipStream_t st)
+{
+    double* sums = (double*)work;
+    uint32_t* counts = (uint32_t*)(sums + 8192);
+    double* Gw = G ? G : (double*)(counts + 8192);
+    hipLaunchKernelGGL(k_bond_table, dim3(8192), dim3(256), 0, st, H, gmax, eg, Gw);
+    hipLaunchKernelGGL(k_zero_stats, dim3(32), dim3(256), 0, st, sums, counts);
+    const int64_t want = (n + kStatThreads - 1) / kStatThreads;
+    const int blocks = (int)(want < 512 ? want : 512);
+    switch ((L + 63) / 64) {
+#define PD_STATS(w)                                                                          \
+    case w:                                                                                  \
+        hipLaunchKernelGGL(k_bond_stats<w>, dim3(blocks), dim3(kStatThreads), kStatSmem, st, \
+                           H, states, ld, L, n, sums, counts);                               \
+        break;
+        PD_STATS(1) PD_STATS(2) PD_STATS(3) PD_STATS(4) PD_STATS(5) PD_STATS(6) PD_STATS(7)
+        PD_STATS(8)
+#undef PD_STATS
+        default: return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL(k_cond_finish, dim3(32), dim3(256), 0, st, sums, counts, min_count, gmax,
+                       Gw, eg, counts_out);
+    return hipGetLastError();
+}
+
+hipError_t stats_set_smem_limit()
+{
+#define PD_ATTR(w)                                                                           \
+    {                                                                                        \
+        hipError_t e = hipFuncSetAttribute((const void*)k_bond_stats<w>,                     \
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,       \
+                                           (int)kStatSmem);                                  \
+        if (e != hipSuccess) return e;                                                       \
+    }
+    PD_ATTR(1) PD_ATTR(2) PD_ATTR(3) PD_ATTR(4) PD_ATTR(5) PD_ATTR(6) PD_ATTR(7) PD_ATTR(8)
+#undef PD_ATTR
+    return hipSuccess;
 }
 
 hipError_t launch_bond_table(const float* H, double gmax, uint32_t* eg, double* G, hipStream_t st)

@@ -24,5 +24,11 @@ hipError_t launch_adam(float* theta, float* m, float* v, const float* grad, int 
 hipError_t launch_window_table(const float* theta, float* table, hipStream_t st);
 hipError_t launch_bond_table(const float* H, double gmax, uint32_t* eg, double* G,
                              hipStream_t st);
+// work: kCondWorkBytes bytes (sums, counts, and G when G is null)
+constexpr size_t kCondWorkBytes = 8192 * (2 * sizeof(double) + sizeof(uint32_t));
+hipError_t launch_bond_table_cond(const float* H, const uint64_t* states, int64_t ld, int L,
+                                  int64_t n, uint32_t min_count, double gmax, uint32_t* eg,
+                                  double* G, uint32_t* counts_out, void* work, hipStream_t st);
+hipError_t stats_set_smem_limit();
 
 }  // namespace pd

@@ -13,6 +13,7 @@ using namespace pd;
 
 static_assert(PDG_PARAMS == kGuideParams, "parameter count");
 static_assert(PDG_MIN_L == kGuideMinL, "smallest ring");
+static_assert(PDG_COND_WORK_BYTES == kCondWorkBytes, "conditional distillation workspace");
 
 namespace {
 
@@ -115,6 +116,30 @@ pd_status pdg_bond_table(const float* window_table, double gmax, uint32_t* eg, d
     if (!(gmax >= 0.0) || !(gmax <= PDG_MAX_GMAX)) return gfail(PD_EINVAL, "gmax out of range");
     return gdev(launch_bond_table(window_table, gmax, eg, G, (hipStream_t)hip_stream),
                 "bond table launch");
+}
+
+pd_status pdg_bond_table_cond(const float* window_table, const uint64_t* states, int64_t ld,
+                              int32_t L, int64_t n, int32_t min_count, double gmax, uint32_t* eg,
+                              double* G, uint32_t* counts, void* work, size_t work_bytes,
+                              void* hip_stream)
+{
+    std::string m = check_batch(states, ld, L, n);
+    if (!m.empty()) return gfail(PD_EINVAL, m);
+    if (L < PDG_COND_MIN_L) return gfail(PD_EINVAL, "conditional distillation needs L >= 26");
+    if (!window_table || !eg || !work) return gfail(PD_EINVAL, "null pointer");
+    if (min_count < 1) return gfail(PD_EINVAL, "min_count must be >= 1");
+    if (!(gmax >= 0.0) || !(gmax <= PDG_MAX_GMAX)) return gfail(PD_EINVAL, "gmax out of range");
+    if (!aligned256(work)) return gfail(PD_EINVAL, "workspace must be 256-byte aligned");
+    if (work_bytes < kCondWorkBytes) return gfail(PD_ENOMEM, "workspace too small");
+    thread_local bool attr_done = false;
+    if (!attr_done) {
+        pd_status st = gdev(stats_set_smem_limit(), "hipFuncSetAttribute");
+        if (st != PD_OK) return st;
+        attr_done = true;
+    }
+    return gdev(launch_bond_table_cond(window_table, states, ld, L, n, (uint32_t)min_count, gmax,
+                                       eg, G, counts, work, (hipStream_t)hip_stream),
+                "conditional bond table launch");
 }
 
 const char* pdg_last_error(void) { return g_guide_error.c_str(); }

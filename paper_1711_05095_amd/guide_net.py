@@ -12,9 +12,11 @@ PDG_PARAMS = 5506
 PDG_WINDOWS = 8192
 PDG_MIN_L = 5
 PDG_MAX_GMAX = 3.45
+PDG_COND_MIN_L = 26
+PDG_COND_WORK_BYTES = 163840
 
 EXPORTS = ["pdg_workspace_bytes", "pdg_forward", "pdg_loss_grad", "pdg_adam",
-           "pdg_window_table", "pdg_bond_table", "pdg_last_error"]
+           "pdg_window_table", "pdg_bond_table", "pdg_bond_table_cond", "pdg_last_error"]
 
 _bound = False
 
@@ -33,6 +35,8 @@ def lib():
             "pdg_adam": [vp, vp, vp, vp, c.c_int32, c.c_float, vp],
             "pdg_window_table": [vp, vp, vp],
             "pdg_bond_table": [vp, c.c_double, vp, vp, vp],
+            "pdg_bond_table_cond": [vp, vp, c.c_int64, c.c_int32, c.c_int64, c.c_int32, c.c_double,
+                                    vp, vp, vp, vp, c.c_size_t, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -135,3 +139,22 @@ def bond_table(window, gmax, eg, G=None, stream=None):
     if G is not None:
         _dev(G, torch.float64, PDG_WINDOWS, "G")
     _check(lib().pdg_bond_table(_p(window), float(gmax), _p(eg), _p(G), _stream(stream)))
+
+
+def bond_table_cond(window, states, L, min_count, gmax, eg, G=None, counts=None, work=None,
+                    stream=None):
+    import torch
+    n, ld = _states(states, L)
+    _dev(window, torch.float32, PDG_WINDOWS, "window")
+    _dev(eg, torch.int32, PDG_WINDOWS, "eg")
+    if G is not None:
+        _dev(G, torch.float64, PDG_WINDOWS, "G")
+    if counts is not None:
+        _dev(counts, torch.int32, PDG_WINDOWS, "counts")
+    if work is None:
+        work = torch.empty(PDG_COND_WORK_BYTES, dtype=torch.uint8, device=window.device)
+    _dev(work, torch.uint8, None, "work")
+    _check(lib().pdg_bond_table_cond(_p(window), _p(states), ld, L, n, int(min_count),
+                                     float(gmax), _p(eg), _p(G), _p(counts), _p(work),
+                                     work.numel(), _stream(stream)))
+    return work

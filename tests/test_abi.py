@@ -30,7 +30,8 @@ def test_library_exports_every_symbol():
 
 def test_guide_constants_match_header():
     text = open(os.path.join(ROOT, "include", "pd_guide.h")).read()
-    for name in ("PDG_PARAMS", "PDG_WINDOWS", "PDG_MIN_L", "PDG_MAX_GMAX"):
+    for name in ("PDG_PARAMS", "PDG_WINDOWS", "PDG_MIN_L", "PDG_MAX_GMAX", "PDG_COND_MIN_L",
+                 "PDG_COND_WORK_BYTES"):
         v = re.search(r"#define %s ([0-9.]+)" % name, text).group(1)
         assert float(v) == getattr(guide_net, name), name
     from oracle import guide_net as ref
@@ -63,6 +64,13 @@ def test_guide_host_validation():
     assert lib.pdg_bond_table(fake, 3.5, fake, None, None) == pd.PD_EINVAL
     assert lib.pdg_bond_table(fake, float("nan"), fake, None, None) == pd.PD_EINVAL
     assert lib.pdg_window_table(None, fake, None) == pd.PD_EINVAL
+    big = guide_net.PDG_COND_WORK_BYTES
+    assert lib.pdg_bond_table_cond(fake, fake, 10, 25, 10, 1, 1.0, fake, None, None, fake, big,
+                                   None) == pd.PD_EINVAL                       # L < 26
+    assert lib.pdg_bond_table_cond(fake, fake, 10, 40, 10, 0, 1.0, fake, None, None, fake, big,
+                                   None) == pd.PD_EINVAL                       # min_count 0
+    assert lib.pdg_bond_table_cond(fake, fake, 10, 40, 10, 1, 1.0, fake, None, None, fake,
+                                   big - 1, None) == pd.PD_ENOMEM
 
 
 def test_status_strings():

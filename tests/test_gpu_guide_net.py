@@ -245,3 +245,25 @@ def test_bond_table_matches_reference(gmax):
     if gmax < 1:
         assert np.sum(np.abs(want_G[hop == 1]) > gmax) > 100   # the clip is exercised
     assert got_eg[hop == 1].max() <= 1024 * got_eg[hop == 1].min()
+
+
+@pytest.mark.parametrize("L,n,min_count", [(40, 300, 1), (100, 120, 3)])
+def test_conditional_bond_table_matches_reference(L, n, min_count):
+    th = ref.init_theta(41)
+    th[ref.OFF_W3:ref.OFF_B3] *= 30
+    H = ref.window_table(th).astype(np.float32)
+    occ = inputs.random_population(L, L // 2, n, seed=L + 3)
+    gmax = 1.0
+    eg = torch.empty(gn.PDG_WINDOWS, dtype=torch.int32, device="cuda")
+    G = torch.empty(gn.PDG_WINDOWS, dtype=torch.float64, device="cuda")
+    cnt = torch.empty(gn.PDG_WINDOWS, dtype=torch.int32, device="cuda")
+    gn.bond_table_cond(dev(H), states_dev(occ), L, min_count, gmax, eg, G, cnt)
+    torch.cuda.synchronize()
+    want_eg, want_G, want_cnt = ref.distill_conditional(H.astype(np.float64), occ, gmax, min_count)
+    assert np.array_equal(cnt.cpu().numpy(), want_cnt)          # integer: exact
+    assert np.allclose(G.cpu().numpy(), want_G, rtol=1e-12, atol=1e-12)
+    got_eg = eg.cpu().numpy().view(np.uint32)
+    x = 65536.0 * np.exp(np.clip(want_G, -gmax, gmax))
+    tie = np.abs(x - np.floor(x) - 0.5) < 1e-6
+    assert np.array_equal(got_eg[~tie], want_eg[~tie])
+    assert np.sum(want_cnt >= min_count) > 100                  # the data branch is exercised
