@@ -222,12 +222,9 @@ static int window13(const uint8_t* n, int L, int c)
  * which makes the weighted guided trajectories unbiased for ANY table.
  * Random words of a clone come from one stream per interval: block n of the
  * GUIDE stream of (slot, beta) gives words 2n and 2n+1.  Each event uses one
- * word for the waiting time and one word w for the hop: the allowed bonds, in
- * ascending order, own consecutive ranges of [0, S) of lengths eg[u_b], and
- * the hop goes across the bond whose range holds q = floor(w S / 2^64).  To
- * make every q exactly equally likely, w is redrawn (next word) while the low
- * 64 bits of w S fall below 2^64 mod S (Lemire's rule: each q is then hit by
- * exactly floor(2^64 / S) accepted words). */
+ * word for the waiting time; each proposal of the hop uses one word for the
+ * uniform allowed bond and one for its acceptance with probability
+ * eg[u_b] / eg_max (exact 64-bit Bernoulli), repeated until accepted. */
 enum { ORC_TAG_GUIDE = 5 };
 
 typedef struct {
@@ -256,7 +253,15 @@ static uint64_t guided_total(const orc_params* p, const uint8_t* n)
     return S;
 }
 
-static uint32_t step_clone_guided(const orc_params* p, double es, uint32_t beta,
+static uint32_t guide_max(const orc_params* p)
+{
+    uint32_t m = 0;
+    for (int u = 0; u < 8192; ++u)
+        if (p->guide[u] > m) m = p->guide[u];
+    return m;
+}
+
+static uint32_t step_clone_guided(const orc_params* p, double es, uint32_t egmax, uint32_t beta,
                                   int64_t j, uint8_t* n, double* A_out, double* ell_out)
 {
     const int L = p->L;
@@ -279,26 +284,12 @@ static uint32_t step_clone_guided(const orc_params* p, double es, uint32_t beta,
         A = fma((double)r, w, A);
         AS = fma((double)S, w, AS);
         tau = tau + w;
-        uint64_t q = 0;
-        for (;;) {
-            const unsigned __int128 prod = (unsigned __int128)next_word(&ws) * S;
-            const uint64_t lo = (uint64_t)prod;
-            if (lo >= S || lo >= (uint64_t)(-S) % S) {   /* (-S) % S = 2^64 mod S */
-                q = (uint64_t)(prod >> 64);
-                break;
-            }
-        }
         int bond = -1;
         uint32_t e = 0;
-        uint64_t acc = 0;
-        for (int b = 0; b < L; ++b) {
-            if (!is_active(n, L, b)) continue;
-            e = p->guide[window13(n, L, b)];
-            acc += e;
-            if (q < acc) {
-                bond = b;
-                break;
-            }
+        for (int proposal = 0; proposal < (1 << 20); ++proposal) {
+            bond = qth_active_bond(n, L, (int)mulhi64(next_word(&ws), (uint64_t)r));
+            e = p->guide[window13(n, L, bond)];
+            if (mulhi64(next_word(&ws), (uint64_t)egmax) < (uint64_t)e) break;
         }
         G += log((double)e * 0x1p-16);
         uint8_t t = n[bond];
@@ -352,10 +343,10 @@ static uint32_t step_clone(const orc_params* p, double es, double c, uint32_t be
     return kb;
 }
 
-static uint32_t step_any(const orc_params* p, double es, double c, uint32_t beta,
+static uint32_t step_any(const orc_params* p, double es, double c, uint32_t egmax, uint32_t beta,
                          int64_t j, uint8_t* n, double* A_out, double* ell_out)
 {
-    if (p->mode == ORC_GUIDED) return step_clone_guided(p, es, beta, j, n, A_out, ell_out);
+    if (p->mode == ORC_GUIDED) return step_clone_guided(p, es, egmax, beta, j, n, A_out, ell_out);
     return step_clone(p, es, c, beta, j, n, A_out, ell_out);
 }
 
@@ -367,8 +358,9 @@ int orc_step(const orc_params* p, uint32_t beta, uint8_t* occ, uint64_t* K, uint
 {
     const double es = exp(-p->s);
     const double c = -expm1(-p->s);
+    const uint32_t egmax = (p->mode == ORC_GUIDED) ? guide_max(p) : 0;
     for (int64_t j = 0; j < p->Nc; ++j) {
-        uint32_t kb = step_any(p, es, c, beta, j, occ + (size_t)j * p->L, &A[j], &ell[j]);
+        uint32_t kb = step_any(p, es, c, egmax, beta, j, occ + (size_t)j * p->L, &A[j], &ell[j]);
         Kb[j] = kb;
         K[j] += kb;
     }
@@ -384,8 +376,9 @@ int orc_step_slots(const orc_params* p, uint32_t beta, int64_t n, const int64_t*
 {
     const double es = exp(-p->s);
     const double c = -expm1(-p->s);
+    const uint32_t egmax = (p->mode == ORC_GUIDED) ? guide_max(p) : 0;
     for (int64_t i = 0; i < n; ++i) {
-        uint32_t kb = step_any(p, es, c, beta, slots[i], occ + (size_t)i * p->L, &A[i],
+        uint32_t kb = step_any(p, es, c, egmax, beta, slots[i], occ + (size_t)i * p->L, &A[i],
                                &ell[i]);
         Kb[i] = kb;
         K[i] += kb;
