@@ -12,6 +12,12 @@ stage is inside the timed region.
 
 Usage: python bench.py [--steps K] [--warmup W] [--nc NC] [--no-cpu-baseline]
 By default W + K = 4000 so that the run covers exactly t_obs = 2000.
+
+--workload batch: 64 uneven instances in one context against 64 sequential
+contexts.  --workload guide: wall time to |delta psi| <= 1e-3, guided
+against plain, at L=100 (lambda = 5, 10, 15, 20, Delta t = 0.5) and at the
+paper's phase-separated state point L=50, lambda=50 (Delta t = 10,
+t_obs = 1e4); see bench_guide.
 """
 import argparse
 import hashlib
@@ -55,7 +61,7 @@ def parse():
     ap.add_argument("--variant", type=int, default=None,
                     help="step kernel variant (default: chosen by the autotuner)")
     ap.add_argument("--refill", type=int, default=8)
-    ap.add_argument("--workload", choices=["sweep", "batch"], default="sweep",
+    ap.add_argument("--workload", choices=["sweep", "batch", "guide"], default="sweep",
                     help="sweep: the L=100 transition sweep (default); batch: 64 uneven "
                          "instances in one context against 64 sequential contexts")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -123,6 +129,89 @@ def bench_batch(a):
             "identical_results": same, "tuning": tuning}
 
 
+def _estimates(L, N, lam, Nc, t_obs, dt, reps, mode, eg=None, seed=0, inst0=1):
+    """psi-hat of `reps` independent runs (one batch) and the wall time."""
+    import torch
+    s = inputs.s_of_lambda(lam, L)
+    ps = [pd.make_params(L, N, s, Nc, t_obs, dt, seed=seed, weight_mode=mode, instance=inst0 + r)
+          for r in range(reps)]
+    S = pd.Sampler(ps)
+    if eg is not None:
+        S.set_guide(eg)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.run(int(round(t_obs / dt)))
+    est = [S.estimates(i) for i in range(reps)]
+    el = time.perf_counter() - t0
+    S.close()
+    return np.array([e["psi"] for e in est]), el
+
+
+def bench_guide(a):
+    """Wall time to |delta psi| <= 1e-3, guided against plain.
+
+    For each state point and each form (plain: modified dynamics; guided: the
+    learned guide, trained on the GPU from plain populations at Nc = 1e5 and
+    distilled on them), the cheapest (Nc, t_obs) of a grid whose RMS error over
+    8 seeds against psi_ref is <= 1e-3; psi_ref = mean of plain runs at
+    Nc = 1e6 with the same t_obs (psi-hat's large-Nc limit depends on t_obs).
+    The reported time is one run at that grid point (median of 3).  Guide
+    training (collection, training, distillation) is timed separately."""
+    import torch
+    from paper_1711_05095_amd import guide
+    points = [dict(L=100, N=50, lam=lam, dt=0.5, t_grid=[100.0, 500.0, 2000.0],
+                   nc_grid=[100, 1000, 10000, 100000], lag=100, snapshots=10, burn=400)
+              for lam in (5.0, 10.0, 15.0, 20.0)]
+    points.append(dict(L=50, N=25, lam=50.0, dt=10.0, t_grid=[10000.0],
+                       nc_grid=[1000, 3000, 10000, 30000, 100000], lag=5, snapshots=10,
+                       burn=100))
+    out = []
+    tol, reps = 1e-3, 8
+    for P in points:
+        L, N, lam, dt = P["L"], P["N"], P["lam"], P["dt"]
+        t0 = time.perf_counter()
+        g = guide.train_guide(L, N, inputs.s_of_lambda(lam, L), Nc=100_000, dt=dt,
+                              lag_cycles=P["lag"], snapshots=P["snapshots"],
+                              burn_cycles=P["burn"], epochs=10, lr=1e-3, decay=0.8, gmax=1.0,
+                              seed=9)
+        t_train = time.perf_counter() - t0
+        refs = {}
+        for t_obs in P["t_grid"]:
+            psi, _ = _estimates(L, N, lam, 1_000_000, t_obs, dt, 2, pd.PD_W_MODIFIED, seed=1,
+                                inst0=100)
+            refs[t_obs] = float(psi.mean())
+        row = {"L": L, "lambda": lam, "dt": dt, "train_seconds": t_train, "psi_ref": refs}
+        grid = sorted(((nc, t) for nc in P["nc_grid"] for t in P["t_grid"]),
+                      key=lambda q: q[0] * q[1])
+        for name, mode, eg in (("plain", pd.PD_W_MODIFIED, None),
+                               ("guided", pd.PD_W_GUIDED, g["eg"])):
+            found = None
+            for nc, t_obs in grid:
+                psi, _ = _estimates(L, N, lam, nc, t_obs, dt, reps, mode, eg, seed=2)
+                rms = float(np.sqrt(np.mean((psi - refs[t_obs]) ** 2)))
+                print("  L=%d lambda=%g %s Nc=%d t_obs=%g: rms %.2e" % (L, lam, name, nc, t_obs, rms),
+                      file=sys.stderr, flush=True)
+                if rms <= tol:
+                    times = [_estimates(L, N, lam, nc, t_obs, dt, 1, mode, eg, seed=3)[1]
+                             for _ in range(3)]
+                    found = {"Nc": nc, "t_obs": t_obs, "rms": rms,
+                             "seconds": float(np.median(times))}
+                    break
+            row[name] = found
+        if row["plain"] and row["guided"]:
+            row["plain_over_guided"] = row["plain"]["seconds"] / row["guided"]["seconds"]
+        print(json.dumps(row), file=sys.stderr, flush=True)
+        out.append(row)
+    ratios = [r["plain_over_guided"] for r in out if "plain_over_guided" in r]
+    return {"metric": "wall time to |dpsi|<=1e-3, plain/guided", "unit": "ratio",
+            "value": float(np.exp(np.mean(np.log(ratios)))) if ratios else None,
+            "higher_is_better": True, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+            "vs_baseline": None,
+            "config": {"workload": "guided vs plain: L=100 lambda 5..20 dt=0.5; L=50 lambda=50 "
+                                   "dt=10 t_obs=1e4; RMS over 8 seeds vs plain Nc=1e6"},
+            "points": out}
+
+
 def cpu_baseline(nc, cycles):
     """The test oracle (plain single-threaded C) on a bounded sample of the
     same workload: instance lambda = 20, Nc clones, `cycles` intervals."""
@@ -149,6 +238,9 @@ def main():
         return
     if a.workload == "batch":
         print(json.dumps(bench_batch(a)), flush=True)
+        return
+    if a.workload == "guide":
+        print(json.dumps(bench_guide(a)), flush=True)
         return
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"

@@ -239,6 +239,10 @@ __global__ __launch_bounds__(kTile) void k_step(const InstDev* __restrict__ inst
 // Random words come from one GUIDE stream per (slot, interval): block n gives
 // words 2n, 2n+1; an event uses one word for its waiting time and each
 // proposal one word for the bond and one for the acceptance.
+// In LDS the table keeps only the 4096 neighbourhoods of allowed bonds (bit 7
+// is the complement of bit 6 there, so it is dropped), and sum_jumps ln eg is
+// formed as the logarithm of the running product of the eg, kept in [0.5, 1)
+// by frexp with the binary exponents summed separately.
 // ---------------------------------------------------------------------------
 struct WordStream {
     uint32_t block, half;
@@ -267,6 +271,10 @@ __device__ __forceinline__ int ring_mod(int i, int L)
 
 __device__ __forceinline__ bool bond_allowed(uint32_t u) { return ((u >> 6) ^ (u >> 7)) & 1u; }
 
+// Index of an allowed neighbourhood u in the compressed table (bit 7 dropped).
+__device__ __forceinline__ uint32_t gidx(uint32_t u) { return (u & 0x7Fu) | ((u >> 8) << 7); }
+constexpr int kGuideCompact = kGuideEntries / 2;
+
 template <int W>
 __device__ __forceinline__ uint64_t guided_total(const uint64_t (&x)[W], const uint64_t (&m)[W],
                                                  int L, const uint32_t* eg)
@@ -278,7 +286,7 @@ __device__ __forceinline__ uint64_t guided_total(const uint64_t (&x)[W], const u
         while (bits) {
             const int b = w * 64 + __builtin_ctzll(bits);
             bits &= bits - 1;
-            S += eg[ring_bits<W>(x, L, ring_mod(b - 6, L), 13)];
+            S += eg[gidx(ring_bits<W>(x, L, ring_mod(b - 6, L), 13))];
         }
     }
     return S;
@@ -289,16 +297,22 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
                                                   const TileDesc* __restrict__ tiles,
                                                   int tile_base, int src, int use_anc)
 {
-    __shared__ uint32_t s_eg[kGuideEntries];
+    // the table, then (once every lane is done with it) the tile's ln Ups and hops
+    __shared__ __align__(16) char s_raw[kGuideCompact * sizeof(uint32_t)];
+    static_assert(kTile * (sizeof(double) + sizeof(uint64_t)) <= sizeof(s_raw), "aliasing");
+    uint32_t* s_eg = (uint32_t*)s_raw;
+    double* s_ell = (double*)s_raw;
+    uint64_t* s_u = (uint64_t*)(s_raw + kTile * sizeof(double));
     __shared__ double s_log[kLogRows * 4];
-    __shared__ double s_ell[kTile];
-    __shared__ uint64_t s_u[kTile];
 
     const TileDesc td = tiles[tile_base + blockIdx.x];
     const InstDev& I = insts[td.inst];
     const int L = I.L;
     for (int i = threadIdx.x; i < kLogRows * 4; i += kTile) s_log[i] = gptr(I.log_tab)[i];
-    for (int i = threadIdx.x; i < kGuideEntries; i += kTile) s_eg[i] = gptr(I.guide)[i];
+    for (int i = threadIdx.x; i < kGuideCompact; i += kTile) {
+        const uint32_t b6 = (i >> 6) & 1u;
+        s_eg[i] = gptr(I.guide)[(i & 0x7F) | ((b6 ^ 1u) << 7) | ((i >> 7) << 8)];
+    }
     __syncthreads();
 
     const int tid = threadIdx.x;
@@ -323,7 +337,8 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
         int r = popcount_words<W>(m);
         uint64_t S = guided_total<W>(x, m, L, s_eg);
         WordStream ws = {0u, 0u, make_uint4(0, 0, 0, 0)};
-        double tau = 0.0, A = 0.0, AS = 0.0, G = 0.0;
+        double tau = 0.0, A = 0.0, AS = 0.0, P = 1.0;
+        int pexp = 0;
         int events = 0;
         while (r > 0 && events < (1 << 30)) {
             ++events;
@@ -346,11 +361,13 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
                 const uint64_t wq = next_word(ws, (uint32_t)j, beta, c3, I.key0, I.key1);
                 b = select_bit<W>(m, mulhi64_small((uint32_t)(wq >> 32), (uint32_t)wq,
                                                    (uint32_t)r));
-                e = s_eg[ring_bits<W>(x, L, ring_mod(b - 6, L), 13)];
+                e = s_eg[gidx(ring_bits<W>(x, L, ring_mod(b - 6, L), 13))];
                 const uint64_t wa = next_word(ws, (uint32_t)j, beta, c3, I.key0, I.key1);
                 if (__umul64hi(wa, egmax) < (uint64_t)e) break;
             }
-            G += log_unit((double)e * 0x1p-16, s_log, I.ln2_hi, I.ln2_lo);
+            P *= (double)e;
+            pexp += __builtin_amdgcn_frexp_exp(P);
+            P = __builtin_amdgcn_frexp_mant(P);
             if (L >= 26) {
                 // the 14 bonds whose neighbourhood holds site b or b+1 are
                 // bits o..o+12 of the 26 sites from b-12, o = 0..13
@@ -361,8 +378,8 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
                 for (int o = 0; o < 14; ++o) {
                     const uint32_t u0 = (win0 >> o) & 0x1FFFu;
                     const uint32_t u1 = (win1 >> o) & 0x1FFFu;
-                    if (bond_allowed(u0)) sub += s_eg[u0];
-                    if (bond_allowed(u1)) add += s_eg[u1];
+                    if (bond_allowed(u0)) sub += s_eg[gidx(u0)];
+                    if (bond_allowed(u1)) add += s_eg[gidx(u1)];
                 }
                 hop<W>(x, b, L);
                 bond_mask<W>(x, lb, m);
@@ -375,6 +392,9 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
             r = popcount_words<W>(m);
             ++kb;
         }
+        // sum_jumps ln(eg 2^-16) = ln P + (pexp - 16 kb) ln 2
+        const double G = log_unit(P, s_log, I.ln2_hi, I.ln2_lo) +
+                         (double)(pexp - 16 * (int)kb) * (I.ln2_hi + I.ln2_lo);
         ell = -G - (A - (es * 0x1p-16) * AS);
         const int dst = src ^ 1;
 #pragma unroll
@@ -385,6 +405,7 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
         gptr(I.ell)[j] = ell;
         if (I.origin[0]) gptr(I.origin[dst])[j] = gptr(I.origin[src])[from];
     }
+    __syncthreads();   // every lane is done with the table before it is overwritten
     s_ell[tid] = ell;
     s_u[tid] = kb;
     __syncthreads();
