@@ -46,8 +46,16 @@ VALU_PER_EVENT_W2 = 215
 RESAMPLE_BYTES_PER_CLONE = 12
 # HBM bytes per launch of the step kernel on this workload, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE runs scaled by a plain 1 GiB copy (factors 2 and
-# 1), valid only for the kernel source they were taken on.
+# 1), valid only for the kernel sources they were taken on (STEP_SOURCES).
 STEP_TRAFFIC = {"bytes": 233.8e6, "kernels_sha1": "88b0a28d01db"}
+STEP_SOURCES = ["pd_kernels.hip", "pd_tile.hpp", "pd_device.hpp", "pd_internal.hpp"]
+
+
+def step_sources_sha1():
+    h = hashlib.sha1()
+    for f in STEP_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1711_05095_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:12]
 
 
 def parse():
@@ -287,8 +295,7 @@ def main():
     step_s = float(step_ms.mean()) / 1e3
     achieved = events_per_launch * VALU_PER_EVENT_W2 / step_s
 
-    sha = hashlib.sha1(open(os.path.join(ROOT, "paper_1711_05095_amd", "csrc", "pd_kernels.hip"),
-                            "rb").read()).hexdigest()[:12]
+    sha = step_sources_sha1()
     traffic = STEP_TRAFFIC["bytes"] if (sha == STEP_TRAFFIC["kernels_sha1"]
                                         and a.nc == 100_000) else None
     kname = "k_step<2>" if tuning["step_variant"] == 0 else "k_step_q<2>"

@@ -1,0 +1,223 @@
+// Guided dynamical stage for gfx950 (arXiv:1711.05095, Sec. 2.2): the
+// continuous-time SSEP with every allowed hop's rate multiplied by a guide
+// factor from a table over the bond's 13-site neighbourhood, and the exact
+// compensating weight that keeps psi-hat unbiased.  One clone per lane; the
+// tile aggregates are the plain step kernels' (pd_tile.hpp).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "pd_device.hpp"
+#include "pd_internal.hpp"
+#include "pd_launch.hpp"
+#include "pd_tile.hpp"
+
+namespace pd {
+
+// ---------------------------------------------------------------------------
+// Dynamical stage with a guide (eqs. modpdef, upsdef of Sec. 2.2), one clone
+// per lane.  The guide is the table eg[u] over 13-site bond neighbourhoods
+// (site b-6 in bit 0; the bond's sites in bits 6 and 7): the hop across an
+// allowed bond b has rate e^{-s} eg[u_b] 2^-16.  S = sum of eg over allowed
+// bonds is kept exactly in integers, so the escape rate is e^{-s} S 2^-16;
+// the hop is chosen by proposing a uniform allowed bond and accepting it with
+// probability eg / eg_max (exact 64-bit Bernoulli), and the compensating
+// factor is ln Ups = -sum_jumps ln(eg 2^-16) - int (r - e^{-s} S 2^-16) dt.
+// Random words come from one GUIDE stream per (slot, interval): block n gives
+// words 2n, 2n+1; an event uses one word for its waiting time and each
+// proposal one word for the bond and one for the acceptance.
+// In LDS the table keeps only the 4096 neighbourhoods of allowed bonds (bit 7
+// is the complement of bit 6 there, so it is dropped), and sum_jumps ln eg is
+// formed as the logarithm of the running product of the eg, kept in [0.5, 1)
+// by frexp with the binary exponents summed separately.
+// ---------------------------------------------------------------------------
+struct WordStream {
+    uint32_t block, half;
+    uint4 y;
+};
+
+__device__ __forceinline__ uint64_t next_word(WordStream& ws, uint32_t slot, uint32_t beta,
+                                              uint32_t c3, uint32_t k0, uint32_t k1)
+{
+    if (ws.half == 0) {
+        ws.y = philox10(ws.block, slot, beta, c3, k0, k1);
+        ws.block++;
+        ws.half = 1;
+        return ((uint64_t)ws.y.x << 32) | ws.y.y;
+    }
+    ws.half = 0;
+    return ((uint64_t)ws.y.z << 32) | ws.y.w;
+}
+
+// i mod L in [0, L) for i >= -L * 8.
+__device__ __forceinline__ int ring_mod(int i, int L)
+{
+    while (i < 0) i += L;
+    return i;
+}
+
+__device__ __forceinline__ bool bond_allowed(uint32_t u) { return ((u >> 6) ^ (u >> 7)) & 1u; }
+
+// Index of an allowed neighbourhood u in the compressed table (bit 7 dropped).
+__device__ __forceinline__ uint32_t gidx(uint32_t u) { return (u & 0x7Fu) | ((u >> 8) << 7); }
+constexpr int kGuideCompact = kGuideEntries / 2;
+
+template <int W>
+__device__ __forceinline__ uint64_t guided_total(const uint64_t (&x)[W], const uint64_t (&m)[W],
+                                                 int L, const uint32_t* eg)
+{
+    uint64_t S = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        uint64_t bits = m[w];
+        while (bits) {
+            const int b = w * 64 + __builtin_ctzll(bits);
+            bits &= bits - 1;
+            S += eg[gidx(ring_bits<W>(x, L, ring_mod(b - 6, L), 13))];
+        }
+    }
+    return S;
+}
+
+template <int W>
+__global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ insts,
+                                                  const TileDesc* __restrict__ tiles,
+                                                  int tile_base, int src, int use_anc)
+{
+    // the table, then (once every lane is done with it) the tile's ln Ups and hops
+    __shared__ __align__(16) char s_raw[kGuideCompact * sizeof(uint32_t)];
+    static_assert(kTile * (sizeof(double) + sizeof(uint64_t)) <= sizeof(s_raw), "aliasing");
+    uint32_t* s_eg = (uint32_t*)s_raw;
+    double* s_ell = (double*)s_raw;
+    uint64_t* s_u = (uint64_t*)(s_raw + kTile * sizeof(double));
+    __shared__ double s_log[kLogRows * 4];
+
+    const TileDesc td = tiles[tile_base + blockIdx.x];
+    const InstDev& I = insts[td.inst];
+    const int L = I.L;
+    for (int i = threadIdx.x; i < kLogRows * 4; i += kTile) s_log[i] = gptr(I.log_tab)[i];
+    for (int i = threadIdx.x; i < kGuideCompact; i += kTile) {
+        const uint32_t b6 = (i >> 6) & 1u;
+        s_eg[i] = gptr(I.guide)[(i & 0x7F) | ((b6 ^ 1u) << 7) | ((i >> 7) << 8)];
+    }
+    __syncthreads();
+
+    const int tid = threadIdx.x;
+    const bool valid = tid < td.count;
+    const int64_t j = td.first + tid;
+    const int64_t Nc = I.Nc;
+    const uint32_t beta = (uint32_t)(I.ctl->beta + 1);
+    const uint32_t c3 = TAG_GUIDE | I.tag_hi;
+    const double es = I.es, dt = I.dt;
+    const uint64_t egmax = I.guide_max;
+
+    uint32_t kb = 0;
+    double ell = -INFINITY;
+    if (valid) {
+        const int64_t from = use_anc ? (int64_t)gptr(I.anc)[j] : j;
+        uint64_t x[W], m[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) x[w] = gptr(I.state[src])[w * Nc + from];
+        const uint64_t Kfrom = gptr(I.K[src])[from];
+        const int lb = (L - 1) & 63;
+        bond_mask<W>(x, lb, m);
+        int r = popcount_words<W>(m);
+        uint64_t S = guided_total<W>(x, m, L, s_eg);
+        WordStream ws = {0u, 0u, make_uint4(0, 0, 0, 0)};
+        double tau = 0.0, A = 0.0, AS = 0.0, P = 1.0;
+        int pexp = 0;
+        int events = 0;
+        while (r > 0 && events < (1 << 30)) {
+            ++events;
+            const uint64_t wu = next_word(ws, (uint32_t)j, beta, c3, I.key0, I.key1);
+            const double E = -log_unit(unit_open0((uint32_t)(wu >> 32), (uint32_t)wu), s_log,
+                                       I.ln2_hi, I.ln2_lo);
+            const double R = es * ((double)S * 0x1p-16);
+            const double w = E / R;
+            if (tau + w >= dt) {
+                A = fma((double)r, dt - tau, A);
+                AS = fma((double)S, dt - tau, AS);
+                break;
+            }
+            A = fma((double)r, w, A);
+            AS = fma((double)S, w, AS);
+            tau = tau + w;
+            int b = 0;
+            uint32_t e = 0;
+            for (int prop = 0; prop < (1 << 20); ++prop) {
+                const uint64_t wq = next_word(ws, (uint32_t)j, beta, c3, I.key0, I.key1);
+                b = select_bit<W>(m, mulhi64_small((uint32_t)(wq >> 32), (uint32_t)wq,
+                                                   (uint32_t)r));
+                e = s_eg[gidx(ring_bits<W>(x, L, ring_mod(b - 6, L), 13))];
+                const uint64_t wa = next_word(ws, (uint32_t)j, beta, c3, I.key0, I.key1);
+                if (__umul64hi(wa, egmax) < (uint64_t)e) break;
+            }
+            P *= (double)e;
+            pexp += __builtin_amdgcn_frexp_exp(P);
+            P = __builtin_amdgcn_frexp_mant(P);
+            if (L >= 26) {
+                // the 14 bonds whose neighbourhood holds site b or b+1 are
+                // bits o..o+12 of the 26 sites from b-12, o = 0..13
+                const uint32_t win0 = ring_bits<W>(x, L, b >= 12 ? b - 12 : b - 12 + L, 26);
+                const uint32_t win1 = win0 ^ (3u << 12);
+                uint64_t add = 0, sub = 0;
+#pragma unroll
+                for (int o = 0; o < 14; ++o) {
+                    const uint32_t u0 = (win0 >> o) & 0x1FFFu;
+                    const uint32_t u1 = (win1 >> o) & 0x1FFFu;
+                    if (bond_allowed(u0)) sub += s_eg[gidx(u0)];
+                    if (bond_allowed(u1)) add += s_eg[gidx(u1)];
+                }
+                hop<W>(x, b, L);
+                bond_mask<W>(x, lb, m);
+                S = S + add - sub;
+            } else {
+                hop<W>(x, b, L);
+                bond_mask<W>(x, lb, m);
+                S = guided_total<W>(x, m, L, s_eg);
+            }
+            r = popcount_words<W>(m);
+            ++kb;
+        }
+        // sum_jumps ln(eg 2^-16) = ln P + (pexp - 16 kb) ln 2
+        const double G = log_unit(P, s_log, I.ln2_hi, I.ln2_lo) +
+                         (double)(pexp - 16 * (int)kb) * (I.ln2_hi + I.ln2_lo);
+        ell = -G - (A - (es * 0x1p-16) * AS);
+        const int dst = src ^ 1;
+#pragma unroll
+        for (int w = 0; w < W; ++w) gptr(I.state[dst])[w * Nc + j] = x[w];
+        gptr(I.K[dst])[j] = Kfrom + kb;
+        gptr(I.Kb)[j] = kb;
+        gptr(I.A)[j] = A;
+        gptr(I.ell)[j] = ell;
+        if (I.origin[0]) gptr(I.origin[dst])[j] = gptr(I.origin[src])[from];
+    }
+    __syncthreads();   // every lane is done with the table before it is overwritten
+    s_ell[tid] = ell;
+    s_u[tid] = kb;
+    __syncthreads();
+    if (tid < 64) {
+        uint64_t h = 0;
+        for (int i = tid; i < td.count; i += 64) h += s_u[i];
+        tile_aggregate(I, td.tile, s_ell, td.count, h);
+    }
+}
+
+hipError_t launch_step_guided(int W, int count, const InstDev* insts, const TileDesc* tiles,
+                              int base, int src, int use_anc, hipStream_t st)
+{
+    switch (W) {
+#define PD_CASE(w)                                                                            \
+    case w:                                                                                   \
+        hipLaunchKernelGGL(k_step_g<w>, dim3(count), dim3(kTile), 0, st, insts, tiles, base,  \
+                           src, use_anc);                                                     \
+        break;
+        PD_CASE(1) PD_CASE(2) PD_CASE(3) PD_CASE(4) PD_CASE(5) PD_CASE(6) PD_CASE(7)
+        PD_CASE(8)
+#undef PD_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace pd

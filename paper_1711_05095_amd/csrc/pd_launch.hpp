@@ -22,6 +22,8 @@ hipError_t launch_init(const InstDev* insts, int n_inst, const TileDesc* tiles, 
                        hipStream_t st);
 hipError_t launch_step(const StepLaunch& s, const InstDev* insts, const TileDesc* tiles, int src,
                        int use_anc, hipStream_t st);
+hipError_t launch_step_guided(int W, int count, const InstDev* insts, const TileDesc* tiles,
+                              int base, int src, int use_anc, hipStream_t st);
 hipError_t step_occupancy(int W, int variant, int* blocks_per_cu);
 hipError_t launch_prefix(const InstDev* insts, int n_inst, hipStream_t st);
 hipError_t launch_resample(const InstDev* insts, const TileDesc* tiles, int ntiles,

@@ -120,11 +120,26 @@ class Trainer:
         return H, eg, G
 
 
+    def tables_cond(self, states, min_count=4, gmax=1.0):
+        """As tables(), but the bond table is the mean exact log-ratio over the
+        bonds of the given configurations (pdg_bond_table_cond)."""
+        dev = self.theta.device
+        H = torch.empty(gnet.PDG_WINDOWS, dtype=torch.float32, device=dev)
+        eg = torch.empty(gnet.PDG_WINDOWS, dtype=torch.int32, device=dev)
+        G = torch.empty(gnet.PDG_WINDOWS, dtype=torch.float64, device=dev)
+        gnet.window_table(self.theta, H)
+        gnet.bond_table_cond(H, states, self.L, min_count, gmax, eg, G)
+        torch.cuda.current_stream().synchronize()
+        return H, eg, G
+
+
 def train_guide(L, N, s, Nc=100_000, dt=0.5, lag_cycles=20, snapshots=10, burn_cycles=200,
-                epochs=8, batch=8192, lr=1e-3, decay=0.7, gmax=1.0, seed=0, log=None):
-    """Collect, train (learning rate lr * decay^epoch) and distil; returns a
-    dict with the trainer, the bond table eg (int32 CUDA tensor, for
-    Sampler.set_guide) and the loss history."""
+                epochs=8, batch=8192, lr=1e-3, decay=0.7, gmax=1.0, distill="conditional",
+                min_count=4, seed=0, log=None):
+    """Collect, train (learning rate lr * decay^epoch) and distil
+    ("conditional" on the collected configurations when L >= 26, else
+    "uniform"); returns a dict with the trainer, the bond table eg (int32 CUDA
+    tensor, for Sampler.set_guide), the samples and the loss history."""
     states, counts = collect(L, N, s, Nc, dt, lag_cycles, snapshots, burn_cycles, seed)
     n = states.shape[1]
     n_val = max(n // 10, 1)
@@ -138,5 +153,8 @@ def train_guide(L, N, s, Nc=100_000, dt=0.5, lag_cycles=20, snapshots=10, burn_c
         hist["val"].append(tr.evaluate(S_va, C_va))
         if log:
             log("epoch %d: train %.5f  validation %.5f" % (e + 1, hist["train"][-1], hist["val"][-1]))
-    H, eg, G = tr.tables(gmax)
-    return dict(trainer=tr, eg=eg, G=G, H=H, history=hist, samples=n)
+    if distill == "conditional" and L >= gnet.PDG_COND_MIN_L:
+        H, eg, G = tr.tables_cond(S, min_count, gmax)
+    else:
+        H, eg, G = tr.tables(gmax)
+    return dict(trainer=tr, eg=eg, G=G, H=H, history=hist, samples=n, states=S, counts=C)
