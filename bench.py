@@ -14,7 +14,8 @@ Usage: python bench.py [--steps K] [--warmup W] [--nc NC] [--no-cpu-baseline]
 By default W + K = 4000 so that the run covers exactly t_obs = 2000.
 
 --workload batch: 64 uneven instances in one context against 64 sequential
-contexts.  --workload guide: wall time to |delta psi| <= 1e-3, guided
+contexts.  --workload guided-rate: guided against plain throughput at L=100,
+lambda=15.  --workload guide: wall time to |delta psi| <= 1e-3, guided
 against plain, at L=100 (lambda = 5, 10, 15, 20, Delta t = 0.5) and at the
 paper's phase-separated state point L=50, lambda=50 (Delta t = 10,
 t_obs = 1e4); see bench_guide.
@@ -69,7 +70,8 @@ def parse():
     ap.add_argument("--variant", type=int, default=None,
                     help="step kernel variant (default: chosen by the autotuner)")
     ap.add_argument("--refill", type=int, default=8)
-    ap.add_argument("--workload", choices=["sweep", "batch", "guide"], default="sweep",
+    ap.add_argument("--workload", choices=["sweep", "batch", "guide", "guided-rate"],
+                    default="sweep",
                     help="sweep: the L=100 transition sweep (default); batch: 64 uneven "
                          "instances in one context against 64 sequential contexts")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -220,6 +222,45 @@ def bench_guide(a):
             "points": out}
 
 
+def bench_guided_rate(a):
+    """Throughput of the guided dynamical stage against the plain one on the
+    same workload: a guide trained at L=100, lambda=15 (Nc=1e5, 10 snapshots,
+    lag 100 intervals), then 32 instances x Nc=1e5 (one lambda, 32 seeds),
+    dt=0.5, a.steps cycles each after 8 warm-up cycles."""
+    import torch
+    from paper_1711_05095_amd import guide
+    L, N, lam, dt = 100, 50, 15.0, 0.5
+    s = inputs.s_of_lambda(lam, L)
+    g = guide.train_guide(L, N, s, Nc=100_000, dt=dt, lag_cycles=100, snapshots=10,
+                          burn_cycles=400, epochs=10, lr=1e-3, decay=0.8, gmax=1.0, seed=9)
+    steps = min(a.steps, 200)
+    out = {}
+    for name, mode in (("plain", pd.PD_W_MODIFIED), ("guided", pd.PD_W_GUIDED)):
+        ps = [pd.make_params(L, N, s, 100_000, (steps + 8) * dt, dt, seed=2000 + i, instance=i,
+                             weight_mode=mode) for i in range(32)]
+        S = pd.Sampler(ps)
+        if mode == pd.PD_W_GUIDED:
+            S.set_guide(g["eg"])
+        S.run(8)
+        torch.cuda.synchronize()
+        h0 = sum(S.estimates(i)["hops"] for i in range(S.n))
+        t0 = time.perf_counter()
+        S.run(steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        h = sum(S.estimates(i)["hops"] for i in range(S.n)) - h0
+        out[name] = {"hops_per_second": h / el, "ms_per_cycle": el / steps * 1e3,
+                     "hops_per_clone_interval": h / (steps * 32 * 100_000)}
+        S.close()
+    return {"metric": "clone-hops/s, guided", "value": out["guided"]["hops_per_second"],
+            "unit": "clone-hops/s", "n_gpus": 1, "steps": steps, "warmup": 8,
+            "higher_is_better": True, "dtype": "f64", "data": "synthetic", "vs_baseline": None,
+            "config": {"workload": "L=100 N=50 lambda=15: 32 instances x Nc=1e5, dt=0.5, "
+                                   "trained guide vs plain"},
+            "plain": out["plain"], "guided": out["guided"],
+            "guided_over_plain": out["guided"]["hops_per_second"] / out["plain"]["hops_per_second"]}
+
+
 def cpu_baseline(nc, cycles):
     """The test oracle (plain single-threaded C) on a bounded sample of the
     same workload: instance lambda = 20, Nc clones, `cycles` intervals."""
@@ -249,6 +290,9 @@ def main():
         return
     if a.workload == "guide":
         print(json.dumps(bench_guide(a)), flush=True)
+        return
+    if a.workload == "guided-rate":
+        print(json.dumps(bench_guided_rate(a)), flush=True)
         return
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"

@@ -158,3 +158,57 @@ def train_guide(L, N, s, Nc=100_000, dt=0.5, lag_cycles=20, snapshots=10, burn_c
     else:
         H, eg, G = tr.tables(gmax)
     return dict(trainer=tr, eg=eg, G=G, H=H, history=hist, samples=n, states=S, counts=C)
+
+
+def mfma_flops_per_sample(L):
+    """Multiply-adds x 2 of the three layer-2 contractions (forward, weight
+    gradient, input gradient) of one sample: 3 x 2 x 32 x 160 x L."""
+    return 3 * 2 * 32 * 160 * L
+
+
+def main(argv=None):
+    """Collect, train and distil one guide, printing timings as JSON:
+    python -m paper_1711_05095_amd.guide --L 100 --lam 15 --epochs 4"""
+    import argparse
+    import json
+    import time
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--L", type=int, default=100)
+    ap.add_argument("--lam", type=float, default=15.0)
+    ap.add_argument("--Nc", type=int, default=100_000)
+    ap.add_argument("--dt", type=float, default=0.5)
+    ap.add_argument("--lag", type=int, default=100)
+    ap.add_argument("--snapshots", type=int, default=10)
+    ap.add_argument("--burn", type=int, default=400)
+    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--batch", type=int, default=8192)
+    ap.add_argument("--seed", type=int, default=0)
+    a = ap.parse_args(argv)
+    L, N = a.L, a.L // 2
+    s = inputs.s_of_lambda(a.lam, L)
+    t0 = time.perf_counter()
+    states, counts = collect(L, N, s, a.Nc, a.dt, a.lag, a.snapshots, a.burn, a.seed)
+    t_collect = time.perf_counter() - t0
+    S, C = Trainer.upload(states, counts, seed=a.seed + 1)
+    tr = Trainer(L, seed=a.seed + 2, batch=a.batch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = [tr.epoch(S, C, 1e-3 * 0.8 ** e) for e in range(a.epochs)]
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    if L >= gnet.PDG_COND_MIN_L:
+        tr.tables_cond(S, 4, 1.0)
+    else:
+        tr.tables(1.0)
+    t_distil = time.perf_counter() - t0
+    n = S.shape[1]
+    rate = n * a.epochs / t_train
+    print(json.dumps({"L": L, "lambda": a.lam, "samples": n, "collect_seconds": t_collect,
+                      "train_seconds": t_train, "epochs": a.epochs, "samples_per_second": rate,
+                      "mfma_tflops": rate * mfma_flops_per_sample(L) / 1e12,
+                      "distil_seconds": t_distil, "loss": losses}))
+
+
+if __name__ == "__main__":
+    main()
