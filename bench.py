@@ -39,7 +39,9 @@ PEAK_VALU_LANE_OPS = 256 * 64 * 2.4e9
 PEAK_HBM_GBS = 8000.0
 # VALU instructions in one pass of the event loop of the step kernel (W = 2),
 # counted from its gfx950 assembly by paper_1711_05095_amd.isa_count (a test
-# keeps this constant equal to that count).
+# keeps this constant equal to that count).  It is the algorithmic work of an
+# event for every variant: the compacting variant's loop adds 8 instructions of
+# round bookkeeping, which count as overhead.
 VALU_PER_EVENT_W2 = 215
 # HBM bytes the cloning stage must move per clone: ln Ups read (8) by the
 # resample scan, ancestor written (4); the gather of the states is fused into
@@ -48,7 +50,7 @@ RESAMPLE_BYTES_PER_CLONE = 12
 # HBM bytes per launch of the step kernel on this workload, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE runs scaled by a plain 1 GiB copy (factors 2 and
 # 1), valid only for the kernel sources they were taken on (STEP_SOURCES).
-STEP_TRAFFIC = {"bytes": 233.8e6, "kernels_sha1": "470cf944a831"}
+STEP_TRAFFIC = {"bytes": 236.3e6, "kernels_sha1": "82367e645a93"}
 STEP_SOURCES = ["pd_kernels.hip", "pd_tile.hpp", "pd_device.hpp", "pd_internal.hpp"]
 
 
@@ -69,7 +71,8 @@ def parse():
     ap.add_argument("--cpu-cycles", type=int, default=8)
     ap.add_argument("--variant", type=int, default=None,
                     help="step kernel variant (default: chosen by the autotuner)")
-    ap.add_argument("--refill", type=int, default=8)
+    ap.add_argument("--refill", type=int, default=13,
+                    help="variants 1-3: refill threshold; variant 4: first round in 16ths")
     ap.add_argument("--workload", choices=["sweep", "batch", "guide", "guided-rate"],
                     default="sweep",
                     help="sweep: the L=100 transition sweep (default); batch: 64 uneven "
@@ -306,7 +309,7 @@ def main():
     st = S.stream
 
     if a.variant is None:
-        tuning = S.autotune(3)           # restores the population afterwards
+        tuning = S.autotune(8)           # restores the population afterwards
     else:
         S.set_tuning(a.variant, a.refill, 16)
         tuning = S.tuning()
@@ -342,7 +345,7 @@ def main():
     sha = step_sources_sha1()
     traffic = STEP_TRAFFIC["bytes"] if (sha == STEP_TRAFFIC["kernels_sha1"]
                                         and a.nc == 100_000) else None
-    kname = "k_step<2>" if tuning["step_variant"] == 0 else "k_step_q<2>"
+    kname = {0: "k_step<2>", 4: "k_step_c<2>"}.get(tuning["step_variant"], "k_step_q<2>")
     out = {
         "metric": "clone-hops/s",
         "value": value,

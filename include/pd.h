@@ -205,12 +205,20 @@ pd_status pd_set_guide(pd_ctx* ctx, const uint32_t* d_table, size_t n);
 typedef struct {
     int32_t step_variant; /* 0: one clone per lane; 1, 2, 3: persistent waves,
                              each lane working through a queue of clones,
-                             compiled for 4, 6 and 8 waves per SIMD */
-    int32_t refill;       /* variant 1: finished lanes (1..64) that trigger a refill */
+                             compiled for 4, 6 and 8 waves per SIMD (not with
+                             track_origin: variant 0 runs instead); 4: one
+                             clone per lane, the unfinished clones of a tile
+                             packed into the lowest lanes between rounds of
+                             events */
+    int32_t refill;       /* variants 1-3: finished lanes (1..64) that trigger a
+                             refill; variant 4: length of the first round of
+                             events in sixteenths of the expected number per
+                             clone (later rounds: 0.15 of it) */
     int32_t graph_cycles; /* cycles per captured graph in pd_run (even, 0: no graph) */
     int32_t reserved;
 } pd_tuning;
 
+/* A new context starts with {step_variant 4, refill 13, graph_cycles 16}. */
 pd_status pd_get_tuning(pd_ctx* ctx, pd_tuning* out);
 pd_status pd_set_tuning(pd_ctx* ctx, const pd_tuning* tuning);
 

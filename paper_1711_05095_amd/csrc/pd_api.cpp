@@ -38,8 +38,8 @@ int64_t cycles_of(const pd_params& p) { return llround(p.t_obs / p.dt); }
 pd_tuning default_tuning()
 {
     pd_tuning t;
-    t.step_variant = 0;
-    t.refill = 8;
+    t.step_variant = 4;
+    t.refill = 13;
     t.graph_cycles = 16;
     t.reserved = 0;
     return t;
@@ -238,14 +238,17 @@ pd_status enqueue_cycle(pd_ctx* ctx, int use_anc, int src)
 // Applies a tuning: kernel variant and grid of every step launch.
 pd_status apply_tuning(pd_ctx* ctx, const pd_tuning& t)
 {
-    if (t.step_variant < 0 || t.step_variant > 3 || t.refill < 1 || t.refill > 64 ||
+    if (t.step_variant < 0 || t.step_variant > 4 || t.refill < 1 || t.refill > 64 ||
         t.graph_cycles < 0 || (t.graph_cycles & 1))
         return fail(ctx, PD_EINVAL, "invalid tuning");
     int dev = 0, cus = 0;
     PD_HIP(hipGetDevice(&dev));
     PD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     for (auto& g : ctx->steps) {
-        g.variant = (g.guided || ctx->any_origin) ? 0 : t.step_variant;
+        // the guided stage has one kernel; the queued variants do not carry origins
+        g.variant = g.guided ? 0
+                  : (ctx->any_origin && t.step_variant >= 1 && t.step_variant <= 3) ? 0
+                  : t.step_variant;
         g.refill = t.refill;
         int per_cu = 0;
         PD_HIP(step_occupancy(g.W, g.variant, &per_cu));
@@ -841,6 +844,11 @@ pd_status pd_autotune(pd_ctx* ctx, int32_t trial_cycles, pd_tuning* best)
     pd_tuning t = start;
     t.step_variant = 0;
     cands.push_back(t);
+    t.step_variant = 4;
+    for (int f : {10, 12, 14, 16}) {
+        t.refill = f;
+        cands.push_back(t);
+    }
     for (int v : {1, 2, 3})
         for (int rf : {4, 8, 16}) {
             t.step_variant = v;

@@ -209,6 +209,139 @@ __global__ __launch_bounds__(kTile) void k_step(const InstDev* __restrict__ inst
 }
 
 // ---------------------------------------------------------------------------
+// Dynamical stage with compaction: block = one tile of 256 clones.  A wave
+// runs until its slowest lane is done, and the number of events per clone
+// is Poisson, so a third of the lane slots idle at the end of an interval.
+// Here the tile runs in rounds of a bounded number of events; after each
+// round the unfinished clones (their registers: state, time, integral, event
+// counters, carried K and tile index) are packed through LDS into the lowest
+// lanes of the block, so emptied waves wait at the barrier and leave the
+// SIMDs to other waves.  A clone's random numbers are keyed by its slot and
+// event index and its outputs are written by slot, so the results are those
+// of k_step bit for bit.
+// ---------------------------------------------------------------------------
+template <int W>
+struct Pack {
+    uint64_t x[W][kTile];
+    uint64_t K[kTile];
+    double tau[kTile], A[kTile];
+    uint32_t k[kTile], kb[kTile], t[kTile];
+};
+
+template <int W>
+__global__ __launch_bounds__(kTile) void k_step_c(const InstDev* __restrict__ insts,
+                                                  const TileDesc* __restrict__ tiles,
+                                                  int tile_base, int src, int use_anc,
+                                                  int first16)
+{
+    __shared__ double s_invr[64 * W + 1];     // r <= L <= 64 W
+    __shared__ double s_log[kLogRows * 4];
+    __shared__ double s_ell[kTile];
+    __shared__ uint32_t s_kb[kTile];
+    __shared__ int s_wc[kTile / 64];
+    __shared__ Pack<W> P;
+
+    const TileDesc td = tiles[tile_base + blockIdx.x];
+    const InstDev& I = insts[td.inst];
+    const int L = I.L;
+    for (int i = threadIdx.x; i < kLogRows * 4; i += kTile) s_log[i] = gptr(I.log_tab)[i];
+    for (int i = threadIdx.x; i <= 64 * W; i += kTile) s_invr[i] = gptr(I.inv_count)[i];
+
+    StepConst C;
+    C.invr = s_invr; C.logt = s_log; C.inv_scale = I.inv_scale;
+    C.dt = I.dt; C.ln2_hi = I.ln2_hi; C.ln2_lo = I.ln2_lo;
+    C.beta = (uint32_t)(I.ctl->beta + 1); C.c3 = TAG_DYN | I.tag_hi;
+    C.key0 = I.key0; C.key1 = I.key1; C.L = L; C.lb = (L - 1) & 63;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t Nc = I.Nc;
+    const int dst = src ^ 1;
+    const bool directw = I.mode != MODE_MODIFIED;
+
+    bool active = tid < td.count;
+    uint32_t t = (uint32_t)tid;
+    uint64_t x[W], m[W], Kfrom = 0;
+    int r = 0;
+    double tau = 0.0, A = 0.0;
+    uint32_t k = 0, kb = 0;
+    if (active) {
+        const int64_t j = td.first + tid;
+        const int64_t from = use_anc ? (int64_t)gptr(I.anc)[j] : j;
+#pragma unroll
+        for (int w = 0; w < W; ++w) x[w] = gptr(I.state[src])[w * Nc + from];
+        Kfrom = gptr(I.K[src])[from];
+        if (I.origin[0]) gptr(I.origin[dst])[j] = gptr(I.origin[src])[from];
+        bond_mask<W>(x, C.lb, m);
+        r = popcount_words<W>(m);
+    } else {
+#pragma unroll
+        for (int w = 0; w < W; ++w) x[w] = m[w] = 0;
+        s_ell[tid] = -INFINITY;
+        s_kb[tid] = 0;
+    }
+    // expected events per clone: (rate of one hop) x (mean allowed bonds) x dt, + 1;
+    // the first round runs first16/16 of it, later rounds 0.15 of that
+    const double rbar = L > 1 ? 2.0 * I.N * (double)(L - I.N) / (double)(L - 1) : 0.0;
+    const double ev = (rbar * C.dt / C.inv_scale + 1.0) * (double)first16 * (1.0 / 16.0);
+    int budget = max(1, (int)fmin(ev + 1.0, 1.0e6));
+    const int later = max(2, (int)fmin(0.15 * ev + 1.0, 1.0e6));
+    __syncthreads();
+
+    for (;;) {
+        for (int it = 0; active && it < budget; ++it) {
+            if (one_event<W>(C, (uint32_t)(td.first + t), x, m, r, tau, A, k, kb)) {
+                const int64_t j = td.first + t;
+                const double ell = directw ? -I.s * (double)kb : -I.c * A;
+#pragma unroll
+                for (int w = 0; w < W; ++w) gptr(I.state[dst])[w * Nc + j] = x[w];
+                gptr(I.K[dst])[j] = Kfrom + kb;
+                gptr(I.Kb)[j] = kb;
+                gptr(I.A)[j] = A;
+                gptr(I.ell)[j] = ell;
+                s_ell[t] = ell;
+                s_kb[t] = kb;
+                active = false;
+            }
+        }
+        // rank of each unfinished clone among the block's unfinished clones
+        const uint64_t bal = __ballot(active);
+        if (lane == 0) s_wc[wave] = __popcll(bal);
+        __syncthreads();
+        int before = 0, total = 0;
+#pragma unroll
+        for (int v = 0; v < kTile / 64; ++v) {
+            before += v < wave ? s_wc[v] : 0;
+            total += s_wc[v];
+        }
+        if (total == 0) break;
+        if (active) {
+            const int p = before + __popcll(bal & ((1ull << lane) - 1ull));
+#pragma unroll
+            for (int w = 0; w < W; ++w) P.x[w][p] = x[w];
+            P.K[p] = Kfrom; P.tau[p] = tau; P.A[p] = A;
+            P.k[p] = k; P.kb[p] = kb; P.t[p] = t;
+        }
+        __syncthreads();
+        active = tid < total;
+        if (active) {
+#pragma unroll
+            for (int w = 0; w < W; ++w) x[w] = P.x[w][tid];
+            Kfrom = P.K[tid]; tau = P.tau[tid]; A = P.A[tid];
+            k = P.k[tid]; kb = P.kb[tid]; t = P.t[tid];
+            bond_mask<W>(x, C.lb, m);
+            r = popcount_words<W>(m);
+        }
+        __syncthreads();
+        budget = later;
+    }
+    if (tid < 64) {
+        uint64_t h = 0;
+        for (int i = tid; i < td.count; i += 64) h += s_kb[i];
+        tile_aggregate(I, td.tile, s_ell, td.count, h);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Dynamical stage, persistent queued waves.  Each wave takes tiles from the
 // launch's counter; within a tile every lane runs one clone at a time and,
 // once `refill` lanes have finished theirs, all finished lanes take the next
@@ -633,6 +766,14 @@ hipError_t launch_step(const StepLaunch& s, const InstDev* insts, const TileDesc
         break;
         PD_W_SWITCH(s.W, PD_CASE)
 #undef PD_CASE
+    } else if (s.variant == 4) {
+#define PD_CASE(w)                                                                            \
+    case w:                                                                                   \
+        hipLaunchKernelGGL(k_step_c<w>, dim3(s.count), dim3(kTile), 0, st, insts, tiles,      \
+                           s.base, src, use_anc, s.refill);                                   \
+        break;
+        PD_W_SWITCH(s.W, PD_CASE)
+#undef PD_CASE
     } else if (s.variant == 1) {
 #define PD_CASE(w)                                                                            \
     case w:                                                                                   \
@@ -668,6 +809,13 @@ hipError_t step_occupancy(int W, int variant, int* blocks_per_cu)
 #define PD_CASE(w)                                                                            \
     case w:                                                                                   \
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_step<w>, kTile, 0);
+        PD_W_SWITCH(W, PD_CASE)
+#undef PD_CASE
+    }
+    if (variant == 4) {
+#define PD_CASE(w)                                                                            \
+    case w:                                                                                   \
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_step_c<w>, kTile, 0);
         PD_W_SWITCH(W, PD_CASE)
 #undef PD_CASE
     }

@@ -328,16 +328,35 @@ def test_origin_tracking_composes_ancestor_maps():
     assert np.bincount(S.origin(), minlength=Nc).sum() == Nc
 
 
+def test_compacting_variant_carries_origins():
+    """Variant 4 (compaction between rounds) carries origin ids exactly as
+    variant 0 does."""
+    out = []
+    for variant in (0, 4):
+        p = pd.make_params(100, 50, 0.01, 3000, 5.0, 0.5, seed=91, track_origin=1)
+        S = pd.Sampler(p)
+        S.set_tuning(variant, 8, 16)
+        S.run(2)
+        S.reset_origin()
+        S.run(8)
+        out.append((S.origin(), S.get_population(), S.estimates()))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1][0], out[1][1][0]) and out[0][2] == out[1][2]
+
+
 def test_launch_variants_bit_identical():
     """Neither kernel variant nor refill threshold nor graph length changes any
     result: every random number is keyed by clone slot."""
-    specs = [(10, 5, 0.3, 1000, 0.1), (100, 50, 0.002, 3000, 0.5), (400, 200, 1e-4, 700, 1.0),
-             (65, 32, -0.05, 257, 0.5), (512, 256, 0.0, 300, 0.2)]
+    specs = [(10, 5, 0.3, 1000, 0.1, MOD), (100, 50, 0.002, 3000, 0.5, MOD),
+             (400, 200, 1e-4, 700, 1.0, MOD), (65, 32, -0.05, 257, 0.5, DIR),
+             (512, 256, 0.0, 300, 0.2, MOD), (30, 0, 0.1, 100, 0.5, MOD),
+             (200, 100, 5e-4, 2000, 2.0, DIR)]
     M = 10
-    params = [pd.make_params(L, N, s, Nc, M * dt, dt, seed=70 + i, instance=i)
-              for i, (L, N, s, Nc, dt) in enumerate(specs)]
+    params = [pd.make_params(L, N, s, Nc, M * dt, dt, seed=70 + i, instance=i, weight_mode=wm)
+              for i, (L, N, s, Nc, dt, wm) in enumerate(specs)]
     ref = None
-    for variant, refill, graph in [(0, 8, 16), (1, 1, 16), (1, 8, 0), (1, 32, 4), (1, 64, 2)]:
+    for variant, refill, graph in [(0, 8, 16), (1, 1, 16), (1, 8, 0), (1, 32, 4), (1, 64, 2),
+                                   (4, 8, 16), (4, 8, 0), (2, 8, 2), (3, 16, 16)]:
         S = pd.Sampler(params)
         S.set_tuning(variant, refill, graph)
         S.run(M)
@@ -355,7 +374,7 @@ def test_autotune_leaves_the_run_unchanged():
     A = pd.Sampler(p)
     A.run(10)
     best = A.autotune(2)
-    assert best["step_variant"] in (0, 1)
+    assert best["step_variant"] in (0, 1, 2, 3, 4)
     A.run(20)
     B = pd.Sampler(p)
     B.run(30)
