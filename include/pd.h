@@ -173,6 +173,21 @@ pd_status pd_get_ancestors(pd_ctx* ctx, int32_t inst, int32_t* anc);
 pd_status pd_reset_origin(pd_ctx* ctx, int32_t inst);
 pd_status pd_get_origin(pd_ctx* ctx, int32_t inst, int32_t* origin);
 
+/* Observables (Secs. 2.4, 3.3).  pd_density_mode queues, for every clone j of
+ * instance `inst` (slot order), d_out[j] = |delta rho_n|^2 with
+ * delta rho_n = L^{-1/2} sum over the occupied sites X of e^{-2 pi i n X / L}
+ * (eq. fourdens); d_out is a caller-owned device array of Nc doubles.
+ * pd_mean returns (1/Nc) sum_j v_j for a caller-owned device array d_values of
+ * Nc doubles: v_j = d_values[j] (ancestral = 0: the end-time distribution of
+ * the current population) or v_j = d_values[origin_j] (ancestral = 1, needs
+ * track_origin: d_values holds a quantity recorded per slot at the last
+ * pd_reset_origin, averaged over the ancestors of the current clones, the
+ * ancestral distribution of eq. Opave).  pd_mean synchronises.  Both return
+ * PD_ESTATE between pd_step and pd_resample. */
+pd_status pd_density_mode(pd_ctx* ctx, int32_t inst, int32_t n, double* d_out);
+pd_status pd_mean(pd_ctx* ctx, int32_t inst, const double* d_values, int32_t ancestral,
+                  double* mean);
+
 /* Per-interval log of instance `inst` (params.log_cycles > 0): for interval
  * beta = 1..n_rows, lbeta[beta-1] = ln((1/Nc) sum_i Upsilon_i^beta) and
  * mean_kb[beta-1] = population mean of K^beta before cloning.  Synchronises. */

@@ -9,7 +9,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpd.so")
-SOURCES = ["pd_kernels.hip", "pd_guided.hip", "pd_api.cpp", "pd_guide.hip", "pd_guide_api.cpp"]
+SOURCES = ["pd_kernels.hip", "pd_guided.hip", "pd_observables.hip", "pd_api.cpp", "pd_guide.hip",
+           "pd_guide_api.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -812,6 +812,40 @@ pd_status pd_get_origin(pd_ctx* ctx, int32_t inst, int32_t* origin)
     return PD_OK;
 }
 
+pd_status pd_density_mode(pd_ctx* ctx, int32_t inst, int32_t n, double* d_out)
+{
+    pd_status st = check_inst(ctx, inst);
+    if (st != PD_OK) return st;
+    if (!d_out) return fail(ctx, PD_EINVAL, "null output");
+    if (ctx->stepped) return fail(ctx, PD_ESTATE, "observable between pd_step and pd_resample");
+    st = materialise(ctx);
+    if (st != PD_OK) return st;
+    const pd_params& p = ctx->params[inst];
+    PD_HIP(launch_density_mode(words_of(p.L), ctx->d_insts, inst, p.Nc, ctx->cur, n, d_out,
+                               ctx->stream));
+    return PD_OK;
+}
+
+pd_status pd_mean(pd_ctx* ctx, int32_t inst, const double* d_values, int32_t ancestral,
+                  double* mean)
+{
+    pd_status st = check_inst(ctx, inst);
+    if (st != PD_OK) return st;
+    if (!d_values || !mean) return fail(ctx, PD_EINVAL, "null argument");
+    if (ancestral != 0 && ancestral != 1) return fail(ctx, PD_EINVAL, "ancestral must be 0 or 1");
+    if (ancestral && !ctx->dev[inst].origin[0])
+        return fail(ctx, PD_ESTATE, "instance does not track origins");
+    if (ctx->stepped) return fail(ctx, PD_ESTATE, "observable between pd_step and pd_resample");
+    st = materialise(ctx);
+    if (st != PD_OK) return st;
+    const InstDev& d = ctx->dev[inst];
+    PD_HIP(launch_mean(ctx->d_insts, inst, ctx->params[inst].Nc, ctx->cur, d_values, ancestral,
+                       ctx->stream));
+    PD_HIP(hipMemcpyAsync(mean, d.tile_off, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    PD_HIP(hipStreamSynchronize(ctx->stream));
+    return PD_OK;
+}
+
 pd_status pd_get_tuning(pd_ctx* ctx, pd_tuning* out)
 {
     if (!ctx || !out) return PD_EINVAL;

@@ -25,6 +25,10 @@ hipError_t launch_step(const StepLaunch& s, const InstDev* insts, const TileDesc
 hipError_t launch_step_guided(int W, int count, const InstDev* insts, const TileDesc* tiles,
                               int base, int src, int use_anc, hipStream_t st);
 hipError_t step_occupancy(int W, int variant, int* blocks_per_cu);
+hipError_t launch_density_mode(int W, const InstDev* insts, int inst, int64_t Nc, int cur, int n,
+                               double* out, hipStream_t st);
+hipError_t launch_mean(const InstDev* insts, int inst, int64_t Nc, int cur, const double* values,
+                       int ancestral, hipStream_t st);
 hipError_t launch_prefix(const InstDev* insts, int n_inst, hipStream_t st);
 hipError_t launch_resample(const InstDev* insts, const TileDesc* tiles, int ntiles,
                            hipStream_t st);

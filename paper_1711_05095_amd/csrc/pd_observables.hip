@@ -1,0 +1,108 @@
+// Observables over a population (arXiv:1711.05095, Secs. 2.4 and 3.3): the
+// squared modulus of a Fourier mode of the density (eq. fourdens) per clone,
+// and the mean of a per-clone quantity over the current population (the
+// end-time distribution) or over the ancestors of the current population at
+// the last origin reset (the ancestral distribution, eq. Opave).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "pd_device.hpp"
+#include "pd_internal.hpp"
+#include "pd_launch.hpp"
+
+namespace pd {
+
+// out[j] = |L^{-1/2} sum_{occupied i} e^{-2 pi i n i / L}|^2 for the clones
+// of instance `inst`, population in state[cur] in slot order.
+template <int W>
+__global__ __launch_bounds__(kTile) void k_density_mode(const InstDev* __restrict__ insts,
+                                                        int inst, int cur, int n,
+                                                        double* __restrict__ out)
+{
+    __shared__ double s_cos[kMaxSites], s_sin[kMaxSites];
+    const InstDev& I = insts[inst];
+    const int L = I.L;
+    for (int i = threadIdx.x; i < L; i += kTile) {
+        // the phase n i / L taken mod 1 exactly in integers
+        int64_t m = ((int64_t)n * i) % L;
+        if (m < 0) m += L;
+        double sv, cv;
+        sincospi(2.0 * (double)m / (double)L, &sv, &cv);
+        s_cos[i] = cv;
+        s_sin[i] = sv;
+    }
+    __syncthreads();
+    const int64_t j = (int64_t)blockIdx.x * kTile + threadIdx.x;
+    const int64_t Nc = I.Nc;
+    if (j >= Nc) return;
+    double re = 0.0, im = 0.0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        uint64_t bits = gptr(I.state[cur])[w * Nc + j];
+        while (bits) {
+            const int i = w * 64 + __builtin_ctzll(bits);
+            bits &= bits - 1;
+            re += s_cos[i];
+            im -= s_sin[i];
+        }
+    }
+    out[j] = (re * re + im * im) / (double)L;
+}
+
+// Per-block sums of v_j = values[j] (or values[origin[j]] when ancestral),
+// written to the instance's tile_sum (one entry per 256 clones).
+__global__ __launch_bounds__(kTile) void k_mean_partial(const InstDev* __restrict__ insts, int inst,
+                                                        int cur, const double* __restrict__ values,
+                                                        int ancestral)
+{
+    __shared__ double s_red[kTile / 64];
+    const InstDev& I = insts[inst];
+    const int64_t j = (int64_t)blockIdx.x * kTile + threadIdx.x;
+    double v = 0.0;
+    if (j < I.Nc) v = values[ancestral ? (int64_t)gptr(I.origin[cur])[j] : j];
+    v = block_reduce(v, OpSum(), s_red);
+    if (threadIdx.x == 0) gptr(I.tile_sum)[blockIdx.x] = v;
+}
+
+// mean = (sum of the partials in block order) / Nc, into tile_off[0].
+__global__ __launch_bounds__(kTile) void k_mean_final(const InstDev* __restrict__ insts, int inst,
+                                                      int nb)
+{
+    __shared__ double s_red[kTile / 64];
+    const InstDev& I = insts[inst];
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kTile) v += gptr(I.tile_sum)[b];
+    v = block_reduce(v, OpSum(), s_red);
+    if (threadIdx.x == 0) gptr(I.tile_off)[0] = v / (double)I.Nc;
+}
+
+hipError_t launch_density_mode(int W, const InstDev* insts, int inst, int64_t Nc, int cur, int n,
+                               double* out, hipStream_t st)
+{
+    const dim3 grid((unsigned)((Nc + kTile - 1) / kTile));
+    switch (W) {
+#define PD_CASE(w)                                                                            \
+    case w:                                                                                   \
+        hipLaunchKernelGGL(k_density_mode<w>, grid, dim3(kTile), 0, st, insts, inst, cur, n,  \
+                           out);                                                              \
+        break;
+        PD_CASE(1) PD_CASE(2) PD_CASE(3) PD_CASE(4) PD_CASE(5) PD_CASE(6) PD_CASE(7)
+        PD_CASE(8)
+#undef PD_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_mean(const InstDev* insts, int inst, int64_t Nc, int cur, const double* values,
+                       int ancestral, hipStream_t st)
+{
+    const int nb = (int)((Nc + kTile - 1) / kTile);
+    hipLaunchKernelGGL(k_mean_partial, dim3(nb), dim3(kTile), 0, st, insts, inst, cur, values,
+                       ancestral);
+    hipLaunchKernelGGL(k_mean_final, dim3(1), dim3(kTile), 0, st, insts, inst, nb);
+    return hipGetLastError();
+}
+
+}  // namespace pd

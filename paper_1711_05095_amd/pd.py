@@ -23,7 +23,8 @@ PD_MAX_L = 512
 EXPORTS = ["pd_workspace_bytes", "pd_create", "pd_destroy", "pd_step", "pd_resample", "pd_run",
            "pd_scgf", "pd_estimates_get", "pd_population_bytes", "pd_get_population",
            "pd_set_population", "pd_get_step_outputs", "pd_get_ancestors", "pd_get_log",
-           "pd_save_bytes", "pd_save", "pd_load", "pd_set_guide", "pd_reset_origin", "pd_get_origin", "pd_get_tuning",
+           "pd_save_bytes", "pd_save", "pd_load", "pd_set_guide", "pd_reset_origin",
+           "pd_get_origin", "pd_density_mode", "pd_mean", "pd_get_tuning",
            "pd_set_tuning", "pd_autotune", "pd_last_error", "pd_status_str"]
 
 
@@ -87,6 +88,8 @@ def lib():
             "pd_set_guide": [vp, vp, c.c_size_t],
             "pd_reset_origin": [vp, c.c_int32],
             "pd_get_origin": [vp, c.c_int32, vp],
+            "pd_density_mode": [vp, c.c_int32, c.c_int32, vp],
+            "pd_mean": [vp, c.c_int32, vp, c.c_int32, P(c.c_double)],
             "pd_get_tuning": [vp, P(PdTuning)],
             "pd_set_tuning": [vp, P(PdTuning)],
             "pd_autotune": [vp, c.c_int32, P(PdTuning)],
@@ -234,6 +237,17 @@ def pd_get_origin(ctx, inst, Nc):
     return out
 
 
+def pd_density_mode(ctx, inst, n, out_ptr):
+    _check(lib().pd_density_mode(ctx, inst, int(n), ctypes.c_void_p(out_ptr)), ctx)
+
+
+def pd_mean(ctx, inst, values_ptr, ancestral):
+    m = ctypes.c_double()
+    _check(lib().pd_mean(ctx, inst, ctypes.c_void_p(values_ptr), int(ancestral),
+                         ctypes.byref(m)), ctx)
+    return m.value
+
+
 def _tuning_dict(t):
     return dict(step_variant=t.step_variant, refill=t.refill, graph_cycles=t.graph_cycles)
 
@@ -340,6 +354,26 @@ class Sampler:
 
     def origin(self, inst=0):
         return pd_get_origin(self.ctx, inst, self.params[inst].Nc)
+
+    def density_mode(self, n, inst=0):
+        """|delta rho_n|^2 of every clone (slot order) as a float64 CUDA tensor."""
+        import torch
+        out = torch.empty(self.params[inst].Nc, dtype=torch.float64, device=self.workspace.device)
+        torch.cuda.current_stream().synchronize()   # the allocation is ordered on torch's stream
+        pd_density_mode(self.ctx, inst, n, out.data_ptr())
+        self.stream.synchronize()                   # written on the sampler's stream
+        return out
+
+    def mean(self, values, ancestral=False, inst=0):
+        """(1/Nc) sum_j values[j], or values[origin_j] when ancestral; values is
+        a float64 CUDA tensor of Nc entries."""
+        import torch
+        if values.dtype != torch.float64 or not values.is_cuda or not values.is_contiguous() \
+                or values.numel() < self.params[inst].Nc:
+            raise TypeError("values must be a contiguous float64 CUDA tensor of Nc entries")
+        # the library reads values on its own stream
+        torch.cuda.current_stream().synchronize()
+        return pd_mean(self.ctx, inst, values.data_ptr(), 1 if ancestral else 0)
 
     def tuning(self):
         return pd_get_tuning(self.ctx)

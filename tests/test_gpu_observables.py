@@ -1,0 +1,73 @@
+"""Observables over the population through the C ABI (pd_density_mode,
+pd_mean) against the plain definitions in oracle/observables.py, and two
+physical checks of the density mode (eq. fourdens): its exact mean over the
+uniform distribution at s = 0, and the phase separation of Sec. 3.3 at
+lambda = 50 > lambda_c = 2 pi^2."""
+import numpy as np
+import pytest
+import torch
+
+from layout import unpack
+from oracle import observables as ob
+from paper_1711_05095_amd import inputs, pd
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pd.lib()
+
+
+@pytest.mark.parametrize("L,N,s,Nc,n", [(13, 6, 0.2, 700, 1), (100, 50, 0.002, 3000, 1),
+                                        (100, 50, 0.002, 3000, -3), (400, 200, 1e-4, 1025, 2)])
+def test_density_mode_and_means_match_oracle(L, N, s, Nc, n):
+    p = pd.make_params(L, N, s, Nc, 20.0, 0.5, seed=5, track_origin=1)
+    S = pd.Sampler(p)
+    S.run(3)
+    S.reset_origin()
+    rho0 = S.density_mode(n)
+    words, _ = S.get_population()
+    want0 = ob.density_mode(unpack(words, L), n)
+    assert np.allclose(rho0.cpu().numpy(), want0, rtol=1e-12, atol=1e-13)
+    assert S.mean(rho0) == pytest.approx(ob.population_mean(want0), rel=1e-12)
+    S.run(7)
+    origin = S.origin()
+    assert S.mean(rho0, ancestral=True) == pytest.approx(ob.ancestral_mean(want0, origin),
+                                                         rel=1e-12)
+    rho1 = S.density_mode(n)
+    words, _ = S.get_population()
+    assert np.allclose(rho1.cpu().numpy(), ob.density_mode(unpack(words, L), n), rtol=1e-12,
+                       atol=1e-13)
+
+
+def test_mean_needs_origins_and_rejects_mid_cycle():
+    p = pd.make_params(20, 10, 0.1, 100, 5.0, 0.5, seed=1)
+    S = pd.Sampler(p)
+    v = torch.zeros(100, dtype=torch.float64, device="cuda")
+    with pytest.raises(pd.PdError) as e:
+        S.mean(v, ancestral=True)
+    assert e.value.status == pd.PD_ESTATE
+    S.step()
+    with pytest.raises(pd.PdError) as e:
+        S.mean(v)
+    assert e.value.status == pd.PD_ESTATE
+    S.resample()
+    assert S.mean(v) == 0.0
+
+
+def test_density_mode_physics():
+    L, N, Nc = 50, 25, 100_000
+    # s = 0: the population stays uniform over C(L, N), where the mean is exact
+    S = pd.Sampler(pd.make_params(L, N, 0.0, Nc, 50.0, 0.5, seed=3))
+    S.run(20)
+    r = S.density_mode(1)
+    exact = N * (L - N) / (L * (L - 1))
+    se = r.std().item() / np.sqrt(Nc)
+    assert abs(S.mean(r) - exact) <= 5 * se
+    # lambda = 50: the biased population phase-separates (Sec. 3.3, Fig. dpqGraph)
+    S = pd.Sampler(pd.make_params(L, N, inputs.s_of_lambda(50.0, L), Nc, 3000.0, 10.0, seed=4))
+    S.run(300)
+    assert S.mean(S.density_mode(1)) > 4 * exact
