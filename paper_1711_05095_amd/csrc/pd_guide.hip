@@ -47,275 +47,315 @@ __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c)
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
-struct NetSmem {
-    uint16_t* W2;    // [32][160]  W2[c][c'*5+k]
-    uint16_t* W2T;   // [32][160]  W2T[c'][c*5+k] = W2[c][c'][k]
-    float* W1;       // [160] (bf16 values)
-    float* b1;       // [32]
-    float* b2;       // [32]
-    float* w3s;      // [32]  sum_k W3[c][k] (bf16 values)
-    float* a;        // [LP + 4]  a_{i-2}
-    float* h1;       // [32][LP + 4]  h1[c][i-2] (later dz1)
-    float* h2;       // [32][LP + 4]  h2[c][i-2] (later dz2)
-    float* g;        // partial gradient of the small parameters + loss
+// ---------------------------------------------------------------------------
+// Forward and backward passes, one sample per wave, several waves per block
+// sharing the weights.
+//
+// The layer-2 contraction index is taken tap-major, q = t * 32 + c' (tap t of
+// the kernel, input channel c'), so that four consecutive q of an MFMA operand
+// are four consecutive channels of one position: with the activations stored
+// position-major ([position][channel], bf16) each operand of the forward pass
+// and of the input-gradient pass is one 8-byte LDS read.  The weight-gradient
+// pass contracts over positions and reads the activations position-contiguous
+// ([channel][position]).  Positions carry a circular halo of two sites on each
+// side (row i holds position i - 2).
+//
+// The scalar delta = d loss / d f of a sample is applied after the matrix
+// products (in float32): the products run on g2 = w3s (1 - h2^2) and the
+// results are scaled by delta, so no operand is converted per element.
+// Layer-1 activations in float32 are recomputed where 1 - h1^2 is needed.
+// ---------------------------------------------------------------------------
+constexpr int kNetShared = 2 * CH * Q * 2 + 4 * (Q + 3 * CH);  // bytes
+
+struct NetShared {
+    uint16_t* W2R;   // [c][t * 32 + c']  = W2[c][c'][t]
+    uint16_t* W2T;   // [c'][t * 32 + c]  = W2[c][c'][t]
+    float* W1;       // [c][t] (bf16 values)
+    float* b1;
+    float* b2;
+    float* w3s;      // sum_t W3[c][t] (bf16 values)
 };
 
-// Per-block sums of the small parameters' gradients (g below):
-//   [0,160) W1 | [160,192) b1 | [192,224) b2 | [224,256) S2 = sum_j h2[c][j] of the
-//   current sample | [256,288) sum over samples of delta S2 (the W3 gradient, equal
-//   for the 5 taps) | 288 b3 | 289 c0 | 290 loss
-constexpr int kSmallGrad = 291;
+struct NetWave {
+    float* sa;       // [P] a at row i = position i - 2
+    uint16_t* H1P;   // [P][32] bf16 h1
+    uint16_t* H1C;   // [32][P] bf16 h1
+    uint16_t* G2C;   // [32][LP] bf16 g2 (zero beyond L)
+    uint16_t* G2P;   // [P][32] bf16 g2
+};
 
-__host__ __device__ inline size_t net_smem_bytes(int L)
+__host__ __device__ inline int net_lp(int L) { return (L + 15) / 16 * 16; }
+
+// Bytes of one wave's region: its arrays, and at least the 32 x 160 floats of
+// the end-of-block reduction of the layer-2 weight gradient.
+__host__ __device__ inline size_t net_wave_bytes(int L)
 {
-    const int LP = (L + 15) / 16 * 16;
-    return 2 * (size_t)CH * Q * 2 + sizeof(float) * ((size_t)Q + 3 * CH + (LP + 4) +
-                                                     2 * (size_t)CH * (LP + 4) + kSmallGrad);
+    const size_t LP = net_lp(L), P = LP + 4;
+    const size_t arrays = (4 * P + 15) / 16 * 16 + 2 * P * CH * 2 + 2 * CH * LP + 2 * P * CH;
+    const size_t red = sizeof(float) * CH * Q;
+    return ((arrays > red ? arrays : red) + 15) / 16 * 16;
 }
 
-__device__ NetSmem carve(char* base, int L)
+// Waves per block: as many as fit beside the shared part (at most 4).
+__host__ __device__ inline int net_waves(int L)
 {
-    const int LP = (L + 15) / 16 * 16;
-    NetSmem s;
-    s.W2 = (uint16_t*)base;
-    s.W2T = s.W2 + CH * Q;
-    float* f = (float*)(s.W2T + CH * Q);
-    s.W1 = f; f += Q;
-    s.b1 = f; f += CH;
-    s.b2 = f; f += CH;
-    s.w3s = f; f += CH;
-    s.a = f; f += LP + 4;
-    s.h1 = f; f += CH * (LP + 4);
-    s.h2 = f; f += CH * (LP + 4);
-    s.g = f;
-    return s;
+    const size_t avail = 163840 - kNetShared;
+    const int w = (int)(avail / net_wave_bytes(L));
+    return w < 1 ? 1 : (w > 4 ? 4 : w);
 }
 
-__device__ void load_weights(const float* __restrict__ theta, const NetSmem& s, bool transpose)
+// tanh from one exponential and one reciprocal: 1 - 2 / (e^{2x} + 1), and the
+// odd series x - x^3/3 + 2x^5/15 for |x| < 2^-6 where the difference would
+// cancel.  The error (a few ulp of float) is far below the bfloat16 rounding
+// of the activations that follows.
+__device__ __forceinline__ float tanh_fast(float x)
 {
-    const int t = threadIdx.x;
-    for (int i = t; i < CH * Q; i += blockDim.x) {
-        const int c = i / Q, q = i % Q;              // q = c'*5 + k
-        const uint16_t v = f2bf(theta[OFF_W2 + i]);
-        s.W2[i] = v;
-        if (transpose) {
-            const int cp = q / KS, k = q % KS;
-            s.W2T[cp * Q + c * KS + k] = v;
-        }
-    }
-    for (int i = t; i < Q; i += blockDim.x) s.W1[i] = bfr(theta[OFF_W1 + i]);
-    for (int c = t; c < CH; c += blockDim.x) {
-        s.b1[c] = theta[OFF_B1 + c];
-        s.b2[c] = theta[OFF_B2 + c];
-        float w = 0.0f;
-        for (int k = 0; k < KS; ++k) w += bfr(theta[OFF_W3 + c * KS + k]);
-        s.w3s[c] = w;
-    }
+    const float e = __expf(2.0f * x);
+    const float t = 1.0f - 2.0f * __frcp_rn(e + 1.0f);
+    const float x2 = x * x;
+    const float sers = x * (1.0f + x2 * (-1.0f / 3.0f + x2 * (2.0f / 15.0f)));
+    return fabsf(x) < 0.015625f ? sers : t;
 }
 
-// Circular halo of a [32][LP+4] array holding x[c][i-2] for i in [2, L+2):
-// columns 0,1 <- x[L-2], x[L-1]; L+2, L+3 <- x[0], x[1]; further columns 0.
-__device__ void halo(float* x, int L, int LP)
+__device__ __forceinline__ void wave_sync()
 {
-    const int W = LP + 4;
-    for (int idx = threadIdx.x; idx < CH * (W - L); idx += blockDim.x) {
-        const int c = idx / (W - L), h = idx % (W - L);
-        float* row = x + c * W;
-        if (h == 0) row[0] = row[L];
-        else if (h == 1) row[1] = row[L + 1];
-        else if (h == 2) row[L + 2] = row[2];
-        else if (h == 3) row[L + 3] = row[3];
-        else row[L + h] = 0.0f;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ bf16x4 ld4(const uint16_t* p)
+{
+    return *reinterpret_cast<const bf16x4*>(p);
+}
+
+// Circular halo and zero rows of a position-major [P][32] array holding rows
+// 2 .. L+1: rows 0, 1 <- L, L+1; rows L+2, L+3 <- 2, 3; rows >= L+4 <- 0.
+// For the position-contiguous copy (when C is not null) the same rows.
+__device__ void halo_rows(uint16_t* Pm, uint16_t* Cm, int L, int P, int lane)
+{
+    const int nrow = P - L;
+    for (int idx = lane; idx < CH * nrow; idx += 64) {
+        const int c = idx / nrow, h = idx % nrow;
+        const int i = h < 2 ? h : L + h;
+        uint16_t v = 0;
+        if (i < 2) v = Pm[(L + i) * CH + c];
+        else if (i < L + 4) v = Pm[(i - L) * CH + c];
+        Pm[i * CH + c] = v;
+        if (Cm) Cm[c * P + i] = v;
     }
 }
 
-// Forward pass of one sample (its occupancy bits in words[w * stride]); f is
-// returned to every thread.  Block = one wave.
-__device__ float net_forward(const NetSmem& s, const uint64_t* __restrict__ words, int64_t stride,
-                             int L, float b3)
-{
-    const int LP = (L + 15) / 16 * 16, W = LP + 4;
-    const int lane = threadIdx.x;
-    for (int i = lane; i < W; i += 64) {
-        int site = i - 2;
-        site = site < 0 ? site + L : (site >= L ? site - L : site);
-        float v = 0.0f;
-        if (i < L + 4) v = ((words[(int64_t)(site >> 6) * stride] >> (site & 63)) & 1ull) ? 1.0f : -1.0f;
-        s.a[i] = v;
-    }
-    __syncthreads();
-    for (int idx = lane; idx < CH * L; idx += 64) {
-        const int c = idx / L, j = idx % L;
-        float z = s.b1[c];
-#pragma unroll
-        for (int k = 0; k < KS; ++k) z += s.W1[c * KS + k] * s.a[j + k];
-        s.h1[c * W + j + 2] = tanhf(z);
-    }
-    __syncthreads();
-    halo(s.h1, L, LP);
-    __syncthreads();
-    const int r = lane & 15, g4 = lane >> 4;
-    for (int mt = 0; mt < 2; ++mt)
-        for (int nt = 0; nt < LP / 16; ++nt) {
-            f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-            const int j = nt * 16 + r;
-            for (int kt = 0; kt < Q / 16; ++kt) {
-                const int q0 = kt * 16 + 4 * g4;
-                bf16x4 A, B;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int q = q0 + v;
-                    A[v] = (short)s.W2[(mt * 16 + r) * Q + q];
-                    B[v] = (short)f2bf(s.h1[(q / KS) * W + j + q % KS]);
-                }
-                acc = mfma16(A, B, acc);
-            }
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int c = mt * 16 + 4 * g4 + v;
-                if (j < L) s.h2[c * W + j + 2] = tanhf(acc[v] + s.b2[c]);
-            }
-        }
-    __syncthreads();
-    halo(s.h2, L, LP);
-    __syncthreads();
-    // f = L b3 + sum_c (sum_k W3[c][k]) (sum_j h2[c][j])
-    float part = 0.0f;
-    if (lane < CH) {
-        float S2 = 0.0f;
-        for (int j = 0; j < L; ++j) S2 += s.h2[lane * W + j + 2];
-        part = s.w3s[lane] * S2;
-        s.g[CH * KS + 2 * CH + lane] = S2;     // kept for the W3 gradient
-    }
-    part = wave_reduce(part, OpSum());
-    return (float)L * b3 + part;
-}
-
-// Gradient pass of one sample given delta = d loss / d f; layer-2 weight
-// gradient accumulates into acc (2 x 10 tiles of 16 x 16, MFMA layout).
-__device__ void net_backward(const NetSmem& s, int L, float delta, f32x4 (&acc)[2][10])
-{
-    const int LP = (L + 15) / 16 * 16, W = LP + 4;
-    const int lane = threadIdx.x;
-    const int r = lane & 15, g4 = lane >> 4;
-    // dz2 = delta * w3s[c] * (1 - h2^2), in place of h2
-    for (int idx = lane; idx < CH * L; idx += 64) {
-        const int c = idx / L, j = idx % L;
-        const float h = s.h2[c * W + j + 2];
-        s.h2[c * W + j + 2] = delta * s.w3s[c] * (1.0f - h * h);
-    }
-    __syncthreads();
-    halo(s.h2, L, LP);
-    __syncthreads();
-    // dW2[c][q] += sum_j dz2[c][j] X[q][j],  X[q][j] = h1[q/5][j + q%5 - 2]
-#pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-        for (int qt = 0; qt < Q / 16; ++qt) {
-            const int q = qt * 16 + r;
-            for (int jt = 0; jt < LP / 16; ++jt) {
-                bf16x4 A, B;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int j = jt * 16 + 4 * g4 + v;
-                    const float dz = j < L ? s.h2[(mt * 16 + r) * W + j + 2] : 0.0f;
-                    A[v] = (short)f2bf(dz);
-                    B[v] = (short)f2bf(s.h1[(q / KS) * W + j + q % KS]);
-                }
-                acc[mt][qt] = mfma16(A, B, acc[mt][qt]);
-            }
-        }
-    // small gradients of this sample
-    if (lane < CH) {
-        float db2 = 0.0f;
-        for (int j = 0; j < L; ++j) db2 += s.h2[lane * W + j + 2];
-        s.g[CH * KS + CH + lane] += db2;                       // b2
-    }
-    // dh1[c'][j] = sum_{c,k} W2[c][c'][k] dz2[c][j-k+2]; dz1 = dh1 (1 - h1^2) in place of h1
-    __syncthreads();
-    for (int mt = 0; mt < 2; ++mt)
-        for (int nt = 0; nt < LP / 16; ++nt) {
-            f32x4 d = {0.0f, 0.0f, 0.0f, 0.0f};
-            const int j = nt * 16 + r;
-            for (int kt = 0; kt < Q / 16; ++kt) {
-                const int p0 = kt * 16 + 4 * g4;
-                bf16x4 A, B;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int p = p0 + v;
-                    A[v] = (short)s.W2T[(mt * 16 + r) * Q + p];
-                    B[v] = (short)f2bf(s.h2[(p / KS) * W + j - p % KS + 4]);
-                }
-                d = mfma16(A, B, d);
-            }
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int c = mt * 16 + 4 * g4 + v;
-                if (j < L) {
-                    const float h = s.h1[c * W + j + 2];
-                    s.h1[c * W + j + 2] = d[v] * (1.0f - h * h);
-                }
-            }
-        }
-    __syncthreads();
-    for (int idx = lane; idx < CH * KS; idx += 64) {
-        const int c = idx / KS, k = idx % KS;
-        float acc1 = 0.0f;
-        for (int j = 0; j < L; ++j) acc1 += s.h1[c * W + j + 2] * s.a[j + k];
-        s.g[idx] += acc1;                                      // W1
-    }
-    if (lane < CH) {
-        float db1 = 0.0f;
-        for (int j = 0; j < L; ++j) db1 += s.h1[lane * W + j + 2];
-        s.g[CH * KS + lane] += db1;                            // b1
-    }
-    __syncthreads();
-}
-
-// mode 0: f of every sample; mode 1: loss and gradient partial sums per block.
 template <int MODE>
-__global__ __launch_bounds__(64) void k_net(const float* __restrict__ theta,
-                                            const uint64_t* __restrict__ states,
-                                            const float* __restrict__ counts, int L, int64_t n,
-                                            int64_t ld, float inv_n, float* __restrict__ f_out,
-                                            float* __restrict__ partial)
+__global__ __launch_bounds__(256) void k_net(const float* __restrict__ theta,
+                                             const uint64_t* __restrict__ states,
+                                             const float* __restrict__ counts, int L, int64_t n,
+                                             int64_t ld, float inv_n, float* __restrict__ f_out,
+                                             float* __restrict__ partial)
 {
     extern __shared__ __align__(16) char smem[];
-    const NetSmem s = carve(smem, L);
-    load_weights(theta, s, MODE == 1);
-    const float b3 = theta[OFF_B3];
-    const float c0 = theta[OFF_C0];
-    const int lane = threadIdx.x;
-    for (int i = lane; i < kSmallGrad; i += 64) s.g[i] = 0.0f;
+    const int LP = net_lp(L), P = LP + 4;
+    const int nw = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int r = lane & 15, g4 = lane >> 4;
+
+    NetShared S;
+    S.W2R = (uint16_t*)smem;
+    S.W2T = S.W2R + CH * Q;
+    S.W1 = (float*)(S.W2T + CH * Q);
+    S.b1 = S.W1 + Q;
+    S.b2 = S.b1 + CH;
+    S.w3s = S.b2 + CH;
+    char* wbase = smem + kNetShared + (size_t)wv * net_wave_bytes(L);
+    NetWave V;
+    V.sa = (float*)wbase;
+    V.H1P = (uint16_t*)(wbase + ((4 * P + 15) / 16) * 16);
+    V.H1C = V.H1P + P * CH;
+    V.G2C = V.H1C + CH * P;
+    V.G2P = V.G2C + CH * LP;
+
+    for (int i = threadIdx.x; i < CH * Q; i += blockDim.x) {
+        const int c = i / Q, rest = i % Q, cp = rest / KS, t = rest % KS;   // W2[c][c'][t]
+        const uint16_t v = f2bf(theta[OFF_W2 + i]);
+        S.W2R[c * Q + t * CH + cp] = v;
+        S.W2T[cp * Q + t * CH + c] = v;
+    }
+    for (int i = threadIdx.x; i < Q; i += blockDim.x) S.W1[i] = bfr(theta[OFF_W1 + i]);
+    for (int c = threadIdx.x; c < CH; c += blockDim.x) {
+        S.b1[c] = theta[OFF_B1 + c];
+        S.b2[c] = theta[OFF_B2 + c];
+        float w = 0.0f;
+        for (int t = 0; t < KS; ++t) w += bfr(theta[OFF_W3 + c * KS + t]);
+        S.w3s[c] = w;
+    }
     __syncthreads();
+    const float b3 = theta[OFF_B3], c0 = theta[OFF_C0];
+
+    // per-lane accumulators over the block's samples; the lane's channels are
+    // c = mt * 16 + 4 * g4 + v, its weight-gradient columns q = qt * 16 + r
     f32x4 acc[2][10];
+    float gW1[2][4][KS], gb1[2][4], gW3[2][4], gb2[2][4];
+    float gb3 = 0.0f, gc0 = 0.0f, gloss = 0.0f;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 2; ++a) {
 #pragma unroll
         for (int b = 0; b < 10; ++b) acc[a][b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            gb1[a][v] = gW3[a][v] = gb2[a][v] = 0.0f;
+#pragma unroll
+            for (int t = 0; t < KS; ++t) gW1[a][v][t] = 0.0f;
+        }
+    }
 
-    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
-        const float f = net_forward(s, states + i, ld, L, b3);
+    const int64_t stride = (int64_t)gridDim.x * nw;
+    for (int64_t smp = (int64_t)blockIdx.x * nw + wv; smp < n; smp += stride) {
+        // inputs a = 2 n - 1, circular rows
+        for (int i = lane; i < P; i += 64) {
+            int site = i - 2;
+            site = site < 0 ? site + L : (site >= L ? site - L : site);
+            float v = 0.0f;
+            if (i < L + 4)
+                v = ((states[(int64_t)(site >> 6) * ld + smp] >> (site & 63)) & 1ull) ? 1.0f : -1.0f;
+            V.sa[i] = v;
+        }
+        wave_sync();
+        // layer 1
+        for (int j = lane; j < L; j += 64) {
+            float a5[KS];
+#pragma unroll
+            for (int t = 0; t < KS; ++t) a5[t] = V.sa[j + t];
+            for (int c = 0; c < CH; ++c) {
+                float z = S.b1[c];
+#pragma unroll
+                for (int t = 0; t < KS; ++t) z += S.W1[c * KS + t] * a5[t];
+                const uint16_t hb = f2bf(tanh_fast(z));
+                V.H1P[(j + 2) * CH + c] = hb;
+                V.H1C[c * P + j + 2] = hb;
+            }
+        }
+        wave_sync();
+        halo_rows(V.H1P, V.H1C, L, P, lane);
+        wave_sync();
+        // layer 2 and 3: both channel tiles of a position tile share each B operand
+        float fpart = 0.0f;
+        float s2p[2][4], g2p[2][4];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) s2p[mt][v] = g2p[mt][v] = 0.0f;
+        for (int nt = 0; nt < LP / 16; ++nt) {
+            const int j = nt * 16 + r;
+            f32x4 z[2] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
+#pragma unroll
+            for (int kt = 0; kt < Q / 16; ++kt) {
+                const int t = kt >> 1, cb = (kt & 1) * 16 + 4 * g4;
+                const bf16x4 B = ld4(V.H1P + (j + t) * CH + cb);
+                z[0] = mfma16(ld4(S.W2R + r * Q + kt * 16 + 4 * g4), B, z[0]);
+                z[1] = mfma16(ld4(S.W2R + (16 + r) * Q + kt * 16 + 4 * g4), B, z[1]);
+            }
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int c = mt * 16 + 4 * g4 + v;
+                    uint16_t gb = 0;
+                    if (j < L) {
+                        const float h2 = tanh_fast(z[mt][v] + S.b2[c]);
+                        const float g2 = S.w3s[c] * (1.0f - h2 * h2);
+                        fpart += S.w3s[c] * h2;
+                        s2p[mt][v] += h2;
+                        g2p[mt][v] += g2;
+                        gb = f2bf(g2);
+                        V.G2P[(j + 2) * CH + c] = gb;
+                    }
+                    V.G2C[c * LP + j] = gb;
+                }
+        }
+        const float f = (float)L * b3 + wave_reduce(fpart, OpSum());
         if (MODE == 0) {
-            if (lane == 0) f_out[i] = f;
-            __syncthreads();
+            if (lane == 0) f_out[smp] = f;
+            wave_sync();
             continue;
         }
-        const float cnt = counts[i];
-        const float ez = expf(f + c0);
+        const float cnt = counts[smp];
+        const float zf = f + c0, ez = expf(zf);
         const float delta = (ez - cnt) * inv_n;
-        if (lane < CH) s.g[256 + lane] += delta * s.g[224 + lane];
         if (lane == 0) {
-            s.g[288] += delta * (float)L;
-            s.g[289] += delta;
-            s.g[290] += (ez - cnt * (f + c0)) * inv_n;
+            gb3 += delta * (float)L;
+            gc0 += delta;
+            gloss += (ez - cnt * zf) * inv_n;
         }
-        __syncthreads();
-        net_backward(s, L, delta, acc);
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                gW3[mt][v] += delta * s2p[mt][v];
+                gb2[mt][v] += delta * g2p[mt][v];
+            }
+        wave_sync();
+        halo_rows(V.G2P, nullptr, L, P, lane);
+        wave_sync();
+        // weight gradient of layer 2: sum over positions of g2[c][j] h1[c'][j + t - 2]
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int qt = 0; qt < 10; ++qt) {
+                const int q = qt * 16 + r, t = q >> 5, cp = q & 31;
+                f32x4 d = {0.0f, 0.0f, 0.0f, 0.0f};
+                for (int jt = 0; jt < LP / 16; ++jt) {
+                    const int j0 = jt * 16 + 4 * g4;
+                    const uint16_t* hb = V.H1C + cp * P + j0 + t;
+                    bf16x4 B;
+                    B[0] = (short)hb[0];
+                    B[1] = (short)hb[1];
+                    B[2] = (short)hb[2];
+                    B[3] = (short)hb[3];
+                    d = mfma16(ld4(V.G2C + (mt * 16 + r) * LP + j0), B, d);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[mt][qt][v] += delta * d[v];
+            }
+        // input gradient of layer 2, then layer 1 (both channel tiles per B operand)
+        for (int nt = 0; nt < LP / 16; ++nt) {
+            const int j = nt * 16 + r;
+            f32x4 d[2] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
+#pragma unroll
+            for (int kt = 0; kt < Q / 16; ++kt) {
+                const int t = kt >> 1, cb = (kt & 1) * 16 + 4 * g4;
+                const bf16x4 B = ld4(V.G2P + (j - t + 4) * CH + cb);
+                d[0] = mfma16(ld4(S.W2T + r * Q + kt * 16 + 4 * g4), B, d[0]);
+                d[1] = mfma16(ld4(S.W2T + (16 + r) * Q + kt * 16 + 4 * g4), B, d[1]);
+            }
+            if (j < L) {
+                float a5[KS];
+#pragma unroll
+                for (int t = 0; t < KS; ++t) a5[t] = V.sa[j + t];
+#pragma unroll
+                for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int c = mt * 16 + 4 * g4 + v;
+                        float z = S.b1[c];
+#pragma unroll
+                        for (int t = 0; t < KS; ++t) z += S.W1[c * KS + t] * a5[t];
+                        const float h = tanh_fast(z);
+                        const float dz1 = delta * d[mt][v] * (1.0f - h * h);
+                        gb1[mt][v] += dz1;
+#pragma unroll
+                        for (int t = 0; t < KS; ++t) gW1[mt][v][t] += dz1 * a5[t];
+                    }
+            }
+        }
+        wave_sync();
     }
     if (MODE == 0) return;
-    float* out = partial + (int64_t)blockIdx.x * (kGuideParams + 1);
-    const int r = lane & 15, g4 = lane >> 4;
+
+    // Block sums in a fixed order (no atomics, so the result is reproducible):
+    // first the layer-2 weight gradient, then the small parameters, each
+    // through the per-wave regions.
+    __syncthreads();   // every wave is done with its region
+    float* red = (float*)wbase;   // at least CH * Q floats per wave
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
@@ -323,30 +363,81 @@ __global__ __launch_bounds__(64) void k_net(const float* __restrict__ theta,
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int c = mt * 16 + 4 * g4 + v, q = qt * 16 + r;
-                out[OFF_W2 + c * Q + q] = acc[mt][qt][v];
+                red[c * Q + q] = acc[mt][qt][v];
             }
-    for (int i = lane; i < CH * KS; i += 64) out[OFF_W1 + i] = s.g[i];
-    for (int c = lane; c < CH; c += 64) {
-        out[OFF_B1 + c] = s.g[160 + c];
-        out[OFF_B2 + c] = s.g[192 + c];
-        for (int k = 0; k < KS; ++k) out[OFF_W3 + c * KS + k] = s.g[256 + c];
+    __syncthreads();
+    float* out = partial + (int64_t)blockIdx.x * (kGuideParams + 1);
+    for (int i = threadIdx.x; i < CH * Q; i += blockDim.x) {
+        const int c = i / Q, q = i % Q, t = q >> 5, cp = q & 31;
+        float sum = 0.0f;
+        for (int w = 0; w < nw; ++w)
+            sum += ((const float*)(smem + kNetShared + (size_t)w * net_wave_bytes(L)))[i];
+        out[OFF_W2 + c * Q + cp * KS + t] = sum;
     }
-    if (lane == 0) {
-        out[OFF_B3] = s.g[288];
-        out[OFF_C0] = s.g[289];
-        out[kGuideParams] = s.g[290];
+    __syncthreads();
+    // small parameters: lane l of a wave writes its 8 channels x 8 slots
+    // (5 taps of W1, b1, b2, W3) at red[l * 64 + (mt * 4 + v) * 8 + slot] and
+    // its scalars at red[4096 + l * 3 + k]
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            float* o = red + lane * 64 + (mt * 4 + v) * 8;
+#pragma unroll
+            for (int t = 0; t < KS; ++t) o[t] = gW1[mt][v][t];
+            o[5] = gb1[mt][v];
+            o[6] = gb2[mt][v];
+            o[7] = gW3[mt][v];
+        }
+    red[4096 + lane * 3 + 0] = gb3;
+    red[4096 + lane * 3 + 1] = gc0;
+    red[4096 + lane * 3 + 2] = gloss;
+    __syncthreads();
+    // channel c = mt * 16 + 4 * g4 + v lives in lanes g4 * 16 + r, r = 0..15
+    for (int i = threadIdx.x; i < CH * 8; i += blockDim.x) {
+        const int c = i >> 3, slot = i & 7;
+        const int mt = c >> 4, g = (c >> 2) & 3, v = c & 3;
+        float sum = 0.0f;
+        for (int w = 0; w < nw; ++w) {
+            const float* R = (const float*)(smem + kNetShared + (size_t)w * net_wave_bytes(L));
+            for (int rr = 0; rr < 16; ++rr) sum += R[(g * 16 + rr) * 64 + (mt * 4 + v) * 8 + slot];
+        }
+        if (slot < KS) out[OFF_W1 + c * KS + slot] = sum;
+        else if (slot == 5) out[OFF_B1 + c] = sum;
+        else if (slot == 6) out[OFF_B2 + c] = sum;
+        else for (int t = 0; t < KS; ++t) out[OFF_W3 + c * KS + t] = sum;
+    }
+    if (threadIdx.x < 3) {
+        float sum = 0.0f;
+        for (int w = 0; w < nw; ++w) {
+            const float* R = (const float*)(smem + kNetShared + (size_t)w * net_wave_bytes(L));
+            sum += R[4096 + threadIdx.x];   // lane 0 of each wave holds the scalars
+        }
+        out[threadIdx.x == 0 ? OFF_B3 : (threadIdx.x == 1 ? OFF_C0 : kGuideParams)] = sum;
     }
 }
 
-__global__ void k_net_reduce(const float* __restrict__ partial, int blocks,
-                             float* __restrict__ grad, float* __restrict__ loss)
+// Sum of the per-block partials: 16 parameters per block, 16 lanes per
+// parameter each summing every 16th block in double precision, then the 16
+// lane sums combined in a fixed order.
+__global__ __launch_bounds__(256) void k_net_reduce(const float* __restrict__ partial, int blocks,
+                                                    float* __restrict__ grad,
+                                                    float* __restrict__ loss)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p > kGuideParams) return;
+    __shared__ double s[16][17];
+    const int pl = threadIdx.x & 15, part = threadIdx.x >> 4;
+    const int p = blockIdx.x * 16 + pl;
     double acc = 0.0;
-    for (int b = 0; b < blocks; ++b) acc += partial[(int64_t)b * (kGuideParams + 1) + p];
-    if (p < kGuideParams) grad[p] = (float)acc;
-    else if (loss) *loss = (float)acc;
+    if (p <= kGuideParams)
+        for (int b = part; b < blocks; b += 16) acc += partial[(int64_t)b * (kGuideParams + 1) + p];
+    s[pl][part] = acc;
+    __syncthreads();
+    if (part == 0 && p <= kGuideParams) {
+        double t = 0.0;
+        for (int k = 0; k < 16; ++k) t += s[pl][k];
+        if (p < kGuideParams) grad[p] = (float)t;
+        else if (loss) *loss = (float)t;
+    }
 }
 
 __global__ void k_adam(float* __restrict__ theta, float* __restrict__ m, float* __restrict__ v,
@@ -562,37 +653,42 @@ __global__ void k_cond_finish(const double* __restrict__ sums, const uint32_t* _
 // ---------------------------------------------------------------------------
 int guide_blocks(int64_t n) { return (int)(n < kGuideBlocks ? n : kGuideBlocks); }
 
+static size_t net_block_smem(int L) { return kNetShared + net_waves(L) * net_wave_bytes(L); }
+
 hipError_t launch_net(int mode, const float* theta, const uint64_t* states, int64_t ld,
                       const float* counts, int L, int64_t n, float* f_out, float* partial,
                       float* grad, float* loss, hipStream_t st)
 {
-    const int blocks = guide_blocks(n);
-    const size_t sm = net_smem_bytes(L);
+    const int nw = net_waves(L);
+    const int64_t want = (n + nw - 1) / nw;
+    const int blocks = (int)(want < 512 ? want : 512);   // <= guide_blocks(n): fits the workspace
+    const size_t sm = net_block_smem(L);
     if (mode == 0) {
-        hipLaunchKernelGGL(k_net<0>, dim3(blocks), dim3(64), sm, st, theta, states, counts, L, n,
-                           ld, 1.0f / (float)n, f_out, partial);
+        hipLaunchKernelGGL(k_net<0>, dim3(blocks), dim3(64 * nw), sm, st, theta, states, counts,
+                           L, n, ld, 1.0f / (float)n, f_out, partial);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_net<1>, dim3(blocks), dim3(64), sm, st, theta, states, counts, L, n,
+    hipLaunchKernelGGL(k_net<1>, dim3(blocks), dim3(64 * nw), sm, st, theta, states, counts, L, n,
                        ld, 1.0f / (float)n, f_out, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_net_reduce, dim3((kGuideParams + 1 + 255) / 256), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_net_reduce, dim3((kGuideParams + 1 + 15) / 16), dim3(256), 0, st,
                        partial, blocks, grad, loss);
     return hipGetLastError();
 }
 
 hipError_t net_set_smem_limit(int L)
 {
-    const size_t sm = net_smem_bytes(L);
+    (void)L;
+    const int sm = 163840;
     hipError_t e = hipFuncSetAttribute((const void*)k_net<0>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, sm);
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void*)k_net<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)sm);
+                               sm);
 }
 
-size_t net_smem(int L) { return net_smem_bytes(L); }
+size_t net_smem(int L) { return net_block_smem(L); }
 
 hipError_t launch_adam(float* theta, float* m, float* v, const float* grad, int step, float lr,
                        hipStream_t st)
