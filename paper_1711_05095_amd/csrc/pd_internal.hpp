@@ -27,7 +27,8 @@ struct InstCtl {
     double psib_sum, psib_comp;  // ... over intervals beyond burn_in
     uint64_t hops;         // hops performed so far
     uint64_t ksum;         // scratch: sum of K over the population (estimates)
-    uint64_t pad_[4];
+    double d_eq;           // offset d of the [eq] points of interval beta (set by k_prefix)
+    uint64_t pad_[3];
 };
 
 // Per-instance descriptor (written by the host at creation, read-only after).

@@ -521,6 +521,16 @@ __device__ __forceinline__ double tile_weight(const InstDev& I, int b, double M)
     return I.tile_sum[b] * exp(I.tile_max[b] - M);
 }
 
+// Offset d of the [eq] points of interval beta: 52 bits of the RESAMPLE
+// stream plus one half, times 2^-52, strictly inside (0, 1).
+__device__ __forceinline__ double eq_offset(const InstDev& I, uint32_t beta)
+{
+    const uint4 y = philox10(0u, 0u, beta, TAG_RESAMPLE | I.tag_hi, I.key0, I.key1);
+    const double hi = (double)y.x * 1048576.0;   // y.x * 2^20
+    const double lo = (double)(y.y >> 12) + 0.5;
+    return (hi + lo) * 0x1p-52;
+}
+
 __global__ __launch_bounds__(kTile) void k_prefix(const InstDev* __restrict__ insts)
 {
     __shared__ double s_d[kTile / 64];
@@ -581,6 +591,7 @@ __global__ __launch_bounds__(kTile) void k_prefix(const InstDev* __restrict__ in
             I.log[2 * (beta - 1) + 1] = (double)hops / (double)I.Nc;
         }
         c->beta = beta;
+        c->d_eq = eq_offset(I, beta);
     }
 }
 
@@ -599,14 +610,6 @@ __device__ __forceinline__ int64_t count_points_below(double y, double d, int64_
     return m;
 }
 
-__device__ __forceinline__ double eq_offset(const InstDev& I, uint32_t beta)
-{
-    const uint4 y = philox10(0u, 0u, beta, TAG_RESAMPLE | I.tag_hi, I.key0, I.key1);
-    const double hi = (double)y.x * 1048576.0;   // y.x * 2^20
-    const double lo = (double)(y.y >> 12) + 0.5;
-    return (hi + lo) * 0x1p-52;
-}
-
 __global__ __launch_bounds__(kTile) void k_resample(const InstDev* __restrict__ insts,
                                                     const TileDesc* __restrict__ tiles)
 {
@@ -620,13 +623,12 @@ __global__ __launch_bounds__(kTile) void k_resample(const InstDev* __restrict__ 
     const int64_t k = td.first + tid;
     const int64_t Nc = I.Nc;
     const double Ncd = (double)Nc;
-    const uint32_t beta = (uint32_t)I.ctl->beta;   // k_prefix has completed the interval
     const double M = I.ctl->lmax;
     const int b = td.tile;
     const double off0 = I.tile_off[b];
     const double off1 = I.tile_off[b + 1];
     const double T = I.tile_off[I.ntiles];
-    const double d = eq_offset(I, beta);
+    const double d = I.ctl->d_eq;   // k_prefix drew it for this interval
 
     const double w = valid ? exp(gptr(I.ell)[k] - M) : 0.0;
     double tot;
