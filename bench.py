@@ -15,7 +15,7 @@ By default W + K = 4000 so that the run covers exactly t_obs = 2000.
 
 --workload batch: 64 uneven instances in one context against 64 sequential
 contexts.  --workload guided-rate: guided against plain throughput at L=100,
-lambda=15.  --workload guide: wall time to |delta psi| <= 1e-3, guided
+lambda=15.  --workload large: the L=400, Nc=1e6 workload, plain and guided.  --workload guide: wall time to |delta psi| <= 1e-3, guided
 against plain, at L=100 (lambda = 5, 10, 15, 20, Delta t = 0.5) and at the
 paper's phase-separated state point L=50, lambda=50 (Delta t = 10,
 t_obs = 1e4); see bench_guide.
@@ -43,6 +43,7 @@ PEAK_HBM_GBS = 8000.0
 # event for every variant: the compacting variant's loop adds 8 instructions of
 # round bookkeeping, which count as overhead.
 VALU_PER_EVENT_W2 = 215
+VALU_PER_EVENT_W7 = 344   # the same loop for 400-site states (7 words)
 # HBM bytes the cloning stage must move per clone: ln Ups read (8) by the
 # resample scan, ancestor written (4); the gather of the states is fused into
 # the next dynamical stage's load.
@@ -73,7 +74,7 @@ def parse():
                     help="step kernel variant (default: chosen by the autotuner)")
     ap.add_argument("--refill", type=int, default=13,
                     help="variants 1-3: refill threshold; variant 4: first round in 16ths")
-    ap.add_argument("--workload", choices=["sweep", "batch", "guide", "guided-rate"],
+    ap.add_argument("--workload", choices=["sweep", "batch", "guide", "guided-rate", "large"],
                     default="sweep",
                     help="sweep: the L=100 transition sweep (default); batch: 64 uneven "
                          "instances in one context against 64 sequential contexts")
@@ -264,6 +265,90 @@ def bench_guided_rate(a):
             "guided_over_plain": out["guided"]["hops_per_second"] / out["plain"]["hops_per_second"]}
 
 
+def _timed_cycles(S, steps, res_bytes):
+    """Runs `steps` cycles with HIP events around every stage on the sampler's
+    stream; returns (hops/s, mean step ms, mean resample ms, resample GB/s)."""
+    import torch
+    st = S.stream
+    torch.cuda.synchronize()
+    h0 = sum(S.estimates(i)["hops"] for i in range(S.n))
+    ev = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev[k][0].record(st)
+        S.step()
+        ev[k][1].record(st)
+        S.resample()
+        ev[k][2].record(st)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    h = sum(S.estimates(i)["hops"] for i in range(S.n)) - h0
+    step_ms = float(np.mean([a.elapsed_time(b) for a, b, _ in ev]))
+    res_ms = float(np.mean([b.elapsed_time(c) for _, b, c in ev]))
+    return h / el, step_ms, res_ms, res_bytes / (res_ms / 1e3) / 1e9, h / steps
+
+
+def bench_large(a):
+    """The L=400 workload: N=200, Nc=1e6 clones with 400-bit states (7 words),
+    dt=1, lambda in {0, 10, 20}.  Per lambda: plain throughput over a.steps
+    cycles (default 100, after 8, autotuned), the step kernel against the ALU
+    roofline (events x the 7-word event loop's VALU count / step time) and the
+    cloning stage's HBM rate; then guided throughput with a guide trained at
+    L=100 (lambda=20) and fine-tuned on L=400 populations."""
+    import torch
+    from paper_1711_05095_amd import guide
+    L, N, Nc, dt = 400, 200, 1_000_000, 1.0
+    steps = min(a.steps, 100)
+    rows = []
+    g100 = guide.train_guide(100, 50, inputs.s_of_lambda(20.0, 100), Nc=100_000, dt=0.5,
+                             lag_cycles=100, snapshots=10, burn_cycles=400, epochs=10, lr=1e-3,
+                             decay=0.8, gmax=1.0, seed=9)
+    for lam in inputs.LARGE["lambdas"]:
+        s = inputs.s_of_lambda(lam, L)
+        row = {"lambda": lam}
+        P = pd.make_params(L, N, s, Nc, (steps + 8) * dt, dt, seed=5000 + int(lam))
+        S = pd.Sampler(P)
+        tuning = S.autotune(3)
+        S.run(8)
+        hs, sm, rm, gbs, hpc = _timed_cycles(S, steps, RESAMPLE_BYTES_PER_CLONE * Nc)
+        ach = (hpc + Nc) * VALU_PER_EVENT_W7 / (sm / 1e3)
+        row["plain"] = {"hops_per_second": hs, "step_ms": sm, "resample_ms": rm,
+                        "resample_GBps": gbs, "hops_per_cycle": hpc, "tuning": tuning,
+                        "roofline": {"bound": "alu", "achieved": ach / 1e12,
+                                     "peak": PEAK_VALU_LANE_OPS / 1e12,
+                                     "unit": "T VALU lane-instr/s",
+                                     "frac": ach / PEAK_VALU_LANE_OPS,
+                                     "per_unit": "%d VALU instr per event" % VALU_PER_EVENT_W7}}
+        S.close()
+        # fine-tune the L=100 guide on L=400 populations (1e5 clones, 4 snapshots)
+        states, counts = guide.collect(L, N, s, 100_000, dt, 20, 4, 50, seed=77)
+        Sd, Cd = guide.Trainer.upload(states, counts, seed=1)
+        tr = guide.Trainer(L, theta0=g100["trainer"].theta.cpu().numpy(), lr=5e-4)
+        t0 = time.perf_counter()
+        for e in range(3):
+            tr.epoch(Sd, Cd, 5e-4 * 0.8 ** e)
+        _, eg, _ = tr.tables_cond(Sd, 4, 1.0)
+        row["finetune_seconds"] = time.perf_counter() - t0
+        P = pd.make_params(L, N, s, Nc, (steps + 8) * dt, dt, seed=5000 + int(lam),
+                           weight_mode=pd.PD_W_GUIDED)
+        S = pd.Sampler(P)
+        S.set_guide(eg)
+        S.run(8)
+        hs, sm, rm, gbs, hpc = _timed_cycles(S, steps, RESAMPLE_BYTES_PER_CLONE * Nc)
+        row["guided"] = {"hops_per_second": hs, "step_ms": sm, "resample_ms": rm,
+                         "resample_GBps": gbs, "hops_per_cycle": hpc}
+        S.close()
+        print(json.dumps(row), file=sys.stderr, flush=True)
+        rows.append(row)
+    return {"metric": "clone-hops/s", "unit": "clone-hops/s", "n_gpus": 1, "dtype": "f64",
+            "data": "synthetic", "vs_baseline": None, "higher_is_better": True,
+            "value": float(np.mean([r["plain"]["hops_per_second"] for r in rows])),
+            "steps": steps, "warmup": 8,
+            "config": {"workload": "L=400 N=200 Nc=1e6 dt=1, lambda 0/10/20, one instance each; "
+                                   "guide trained at L=100 lambda=20, fine-tuned at L=400"},
+            "resample_peak_GBps": PEAK_HBM_GBS, "points": rows}
+
+
 def cpu_baseline(nc, cycles):
     """The test oracle (plain single-threaded C) on a bounded sample of the
     same workload: instance lambda = 20, Nc clones, `cycles` intervals."""
@@ -296,6 +381,9 @@ def main():
         return
     if a.workload == "guided-rate":
         print(json.dumps(bench_guided_rate(a)), flush=True)
+        return
+    if a.workload == "large":
+        print(json.dumps(bench_large(a)), flush=True)
         return
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"

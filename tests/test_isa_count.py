@@ -13,3 +13,4 @@ from paper_1711_05095_amd import isa_count
                     reason="hipcc not available")
 def test_bench_valu_count_matches_assembly():
     assert isa_count.count() == bench.VALU_PER_EVENT_W2
+    assert isa_count.count("_ZN2pd6k_stepILi7E") == bench.VALU_PER_EVENT_W7
