@@ -58,7 +58,7 @@ typedef enum {
     PD_ENOMEM = -2,       /* workspace or host buffer too small */
     PD_EDEVICE = -3,      /* a HIP call failed; see pd_last_error */
     PD_ESTATE = -4,       /* call out of order (e.g. two dynamical stages in a row) */
-    PD_EUNSUPPORTED = -5  /* parameter combination not supported by this build */
+    PD_EUNSUPPORTED = -5  /* parameter combination not supported by this library */
 } pd_status;
 
 typedef enum {
