@@ -74,6 +74,8 @@ def parse():
                     help="step kernel variant (default: chosen by the autotuner)")
     ap.add_argument("--refill", type=int, default=13,
                     help="variants 1-3: refill threshold; variant 4: first round in 16ths")
+    ap.add_argument("--scan-tiles", type=int, default=1,
+                    help="tiles of 256 clones per cloning-stage block (with --variant)")
     ap.add_argument("--workload", choices=["sweep", "batch", "guide", "guided-rate", "large"],
                     default="sweep",
                     help="sweep: the L=100 transition sweep (default); batch: 64 uneven "
@@ -121,7 +123,8 @@ def bench_batch(a):
     hops_b = sum(B.estimates(i)["hops"] for i in range(B.n))
     singles = [pd.Sampler(q) for q in params]
     for S in singles:
-        S.set_tuning(tuning["step_variant"], tuning["refill"], tuning["graph_cycles"])
+        S.set_tuning(tuning["step_variant"], tuning["refill"], tuning["graph_cycles"],
+                     tuning["scan_tiles"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for S in singles:
@@ -399,7 +402,7 @@ def main():
     if a.variant is None:
         tuning = S.autotune(8)           # restores the population afterwards
     else:
-        S.set_tuning(a.variant, a.refill, 16)
+        S.set_tuning(a.variant, a.refill, 16, a.scan_tiles)
         tuning = S.tuning()
     for _ in range(a.warmup):
         S.step()

@@ -230,10 +230,13 @@ typedef struct {
                              events in sixteenths of the expected number per
                              clone (later rounds: 0.15 of it) */
     int32_t graph_cycles; /* cycles per captured graph in pd_run (even, 0: no graph) */
-    int32_t reserved;
+    int32_t scan_tiles;   /* tiles of 256 clones per block of the cloning stage: 1, 2, 4
+                             or 8 (0 means 1) */
 } pd_tuning;
 
-/* A new context starts with {step_variant 4, refill 13, graph_cycles 16}. */
+/* A new context starts with {step_variant 4, refill 13, graph_cycles 16, scan_tiles 1}.
+ * pd_autotune times the dynamical stage's configurations first and then the
+ * scan tilings with the best of them. */
 pd_status pd_get_tuning(pd_ctx* ctx, pd_tuning* out);
 pd_status pd_set_tuning(pd_ctx* ctx, const pd_tuning* tuning);
 

@@ -41,7 +41,7 @@ pd_tuning default_tuning()
     t.step_variant = 4;
     t.refill = 13;
     t.graph_cycles = 16;
-    t.reserved = 0;
+    t.scan_tiles = 1;
     return t;
 }
 
@@ -213,7 +213,8 @@ pd_status fail(pd_ctx* ctx, pd_status st, const std::string& msg)
 // Cloning stage of every instance.
 pd_status enqueue_resample(pd_ctx* ctx)
 {
-    PD_HIP(launch_resample(ctx->d_insts, ctx->d_tiles, (int)ctx->tiles.size(), ctx->stream));
+    PD_HIP(launch_resample(ctx->d_insts, ctx->d_tiles, (int)ctx->tiles.size(),
+                           std::max(1, ctx->tuning.scan_tiles), ctx->stream));
     if (ctx->any_iid)
         PD_HIP(launch_select_iid(ctx->d_insts, ctx->d_tiles, (int)ctx->tiles.size(), ctx->stream));
     return PD_OK;
@@ -239,7 +240,9 @@ pd_status enqueue_cycle(pd_ctx* ctx, int use_anc, int src)
 pd_status apply_tuning(pd_ctx* ctx, const pd_tuning& t)
 {
     if (t.step_variant < 0 || t.step_variant > 4 || t.refill < 1 || t.refill > 64 ||
-        t.graph_cycles < 0 || (t.graph_cycles & 1))
+        t.graph_cycles < 0 || (t.graph_cycles & 1) ||
+        !(t.scan_tiles == 0 || t.scan_tiles == 1 || t.scan_tiles == 2 || t.scan_tiles == 4 ||
+          t.scan_tiles == 8))
         return fail(ctx, PD_EINVAL, "invalid tuning");
     int dev = 0, cus = 0;
     PD_HIP(hipGetDevice(&dev));
@@ -259,7 +262,8 @@ pd_status apply_tuning(pd_ctx* ctx, const pd_tuning& t)
         for (auto& gx : ctx->graph)
             if (gx) { (void)hipGraphExecDestroy(gx); gx = nullptr; }
     // captured graphs hold the launch configuration: recapture on change
-    if (t.step_variant != ctx->tuning.step_variant || t.refill != ctx->tuning.refill)
+    if (t.step_variant != ctx->tuning.step_variant || t.refill != ctx->tuning.refill ||
+        t.scan_tiles != ctx->tuning.scan_tiles)
         for (auto& gx : ctx->graph)
             if (gx) { (void)hipGraphExecDestroy(gx); gx = nullptr; }
     ctx->tuning = t;
@@ -892,29 +896,41 @@ pd_status pd_autotune(pd_ctx* ctx, int32_t trial_cycles, pd_tuning* best)
     hipEvent_t e0 = nullptr, e1 = nullptr;
     PD_HIP(hipEventCreate(&e0));
     PD_HIP(hipEventCreate(&e1));
-    float best_ms = 1e30f;
-    pd_tuning chosen = start;
-    for (const auto& c : cands) {
-        st = apply_tuning(ctx, c);
-        if (st != PD_OK) break;
-        // one untimed cycle, then the timed ones (single launches, no graph)
-        for (int rep = 0; rep <= trial_cycles && st == PD_OK; ++rep) {
-            if (rep == 1) {
-                if (hipEventRecord(e0, ctx->stream) != hipSuccess) { st = PD_EDEVICE; break; }
-            }
-            st = enqueue_cycle(ctx, ctx->perm ? 1 : 0, ctx->cur);
-            if (st != PD_OK) break;
+    // one untimed cycle, then the timed ones (single launches, no graph)
+    auto time_one = [&](const pd_tuning& c, float* ms) -> pd_status {
+        pd_status s2 = apply_tuning(ctx, c);
+        for (int rep = 0; rep <= trial_cycles && s2 == PD_OK; ++rep) {
+            if (rep == 1 && hipEventRecord(e0, ctx->stream) != hipSuccess) return PD_EDEVICE;
+            s2 = enqueue_cycle(ctx, ctx->perm ? 1 : 0, ctx->cur);
+            if (s2 != PD_OK) break;
             ctx->cur ^= 1;
             ctx->perm = true;
         }
-        if (st != PD_OK) break;
-        if (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-            st = PD_EDEVICE;
-            break;
-        }
+        if (s2 != PD_OK) return s2;
+        if (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+            return PD_EDEVICE;
+        if (hipEventElapsedTime(ms, e0, e1) != hipSuccess) return PD_EDEVICE;
+        return PD_OK;
+    };
+    float best_ms = 1e30f;
+    pd_tuning chosen = start;
+    // the dynamical stage's launch configuration, then the cloning stage's scan tiling
+    for (const auto& c : cands) {
         float ms = 0.0f;
-        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { st = PD_EDEVICE; break; }
+        st = time_one(c, &ms);
+        if (st != PD_OK) break;
         if (ms < best_ms) { best_ms = ms; chosen = c; }
+    }
+    if (st == PD_OK) {
+        const pd_tuning step_best = chosen;
+        for (int tpb : {1, 2, 4, 8}) {
+            pd_tuning c = step_best;
+            c.scan_tiles = tpb;
+            float ms = 0.0f;
+            st = time_one(c, &ms);
+            if (st != PD_OK) break;
+            if (ms < best_ms) { best_ms = ms; chosen = c; }
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

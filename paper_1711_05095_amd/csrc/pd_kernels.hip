@@ -610,13 +610,22 @@ __device__ __forceinline__ int64_t count_points_below(double y, double d, int64_
     return m;
 }
 
+// Each block takes TPB consecutive tiles of the step order, one after the
+// other (the scan tiling the autotuner chooses; the per-tile arithmetic and so
+// every result is the same for any TPB).
+template <int TPB>
 __global__ __launch_bounds__(kTile) void k_resample(const InstDev* __restrict__ insts,
-                                                    const TileDesc* __restrict__ tiles)
+                                                    const TileDesc* __restrict__ tiles,
+                                                    int ntiles)
 {
     __shared__ double s_d[kTile / 64];
     __shared__ int64_t s_hi[kTile];
 
-    const TileDesc td = tiles[blockIdx.x];
+#pragma unroll
+    for (int tb = 0; tb < TPB; ++tb) {
+    const int tix = blockIdx.x * TPB + tb;
+    if (TPB > 1 && tix >= ntiles) break;
+    const TileDesc td = tiles[tix];
     const InstDev& I = insts[td.inst];
     const int tid = threadIdx.x;
     const bool valid = tid < td.count;
@@ -648,6 +657,8 @@ __global__ __launch_bounds__(kTile) void k_resample(const InstDev* __restrict__ 
             const auto anc = gptr(I.anc);
             for (int64_t jj = lo; jj < hi; ++jj) anc[jj] = (int32_t)k;
         }
+    }
+    if (TPB > 1) __syncthreads();   // s_hi and s_d are reused by the next tile
     }
 }
 
@@ -841,9 +852,17 @@ hipError_t launch_prefix(const InstDev* insts, int n_inst, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_resample(const InstDev* insts, const TileDesc* tiles, int ntiles, hipStream_t st)
+hipError_t launch_resample(const InstDev* insts, const TileDesc* tiles, int ntiles, int tpb,
+                           hipStream_t st)
 {
-    hipLaunchKernelGGL(k_resample, dim3(ntiles), dim3(kTile), 0, st, insts, tiles);
+    const int blocks = (ntiles + tpb - 1) / tpb;
+    switch (tpb) {
+        case 1: hipLaunchKernelGGL(k_resample<1>, dim3(blocks), dim3(kTile), 0, st, insts, tiles, ntiles); break;
+        case 2: hipLaunchKernelGGL(k_resample<2>, dim3(blocks), dim3(kTile), 0, st, insts, tiles, ntiles); break;
+        case 4: hipLaunchKernelGGL(k_resample<4>, dim3(blocks), dim3(kTile), 0, st, insts, tiles, ntiles); break;
+        case 8: hipLaunchKernelGGL(k_resample<8>, dim3(blocks), dim3(kTile), 0, st, insts, tiles, ntiles); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -45,7 +45,7 @@ class PdEstimates(ctypes.Structure):
 
 class PdTuning(ctypes.Structure):
     _fields_ = [("step_variant", ctypes.c_int32), ("refill", ctypes.c_int32),
-                ("graph_cycles", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("graph_cycles", ctypes.c_int32), ("scan_tiles", ctypes.c_int32)]
 
 
 class PdError(RuntimeError):
@@ -249,7 +249,8 @@ def pd_mean(ctx, inst, values_ptr, ancestral):
 
 
 def _tuning_dict(t):
-    return dict(step_variant=t.step_variant, refill=t.refill, graph_cycles=t.graph_cycles)
+    return dict(step_variant=t.step_variant, refill=t.refill, graph_cycles=t.graph_cycles,
+                scan_tiles=t.scan_tiles)
 
 
 def pd_get_tuning(ctx):
@@ -258,8 +259,9 @@ def pd_get_tuning(ctx):
     return _tuning_dict(t)
 
 
-def pd_set_tuning(ctx, step_variant, refill, graph_cycles):
-    t = PdTuning(step_variant=step_variant, refill=refill, graph_cycles=graph_cycles, reserved=0)
+def pd_set_tuning(ctx, step_variant, refill, graph_cycles, scan_tiles=1):
+    t = PdTuning(step_variant=step_variant, refill=refill, graph_cycles=graph_cycles,
+                 scan_tiles=scan_tiles)
     _check(lib().pd_set_tuning(ctx, ctypes.byref(t)), ctx)
 
 
@@ -378,8 +380,8 @@ class Sampler:
     def tuning(self):
         return pd_get_tuning(self.ctx)
 
-    def set_tuning(self, step_variant, refill=8, graph_cycles=16):
-        pd_set_tuning(self.ctx, step_variant, refill, graph_cycles)
+    def set_tuning(self, step_variant, refill=13, graph_cycles=16, scan_tiles=1):
+        pd_set_tuning(self.ctx, step_variant, refill, graph_cycles, scan_tiles)
 
     def autotune(self, trial_cycles=3):
         return pd_autotune(self.ctx, trial_cycles)

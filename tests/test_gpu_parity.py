@@ -345,8 +345,9 @@ def test_compacting_variant_carries_origins():
 
 
 def test_launch_variants_bit_identical():
-    """Neither kernel variant nor refill threshold nor graph length changes any
-    result: every random number is keyed by clone slot."""
+    """Neither kernel variant nor refill threshold nor graph length nor scan
+    tiling changes any result: every random number is keyed by clone slot, and
+    every tile is scanned the same way."""
     specs = [(10, 5, 0.3, 1000, 0.1, MOD), (100, 50, 0.002, 3000, 0.5, MOD),
              (400, 200, 1e-4, 700, 1.0, MOD), (65, 32, -0.05, 257, 0.5, DIR),
              (512, 256, 0.0, 300, 0.2, MOD), (30, 0, 0.1, 100, 0.5, MOD),
@@ -355,10 +356,11 @@ def test_launch_variants_bit_identical():
     params = [pd.make_params(L, N, s, Nc, M * dt, dt, seed=70 + i, instance=i, weight_mode=wm)
               for i, (L, N, s, Nc, dt, wm) in enumerate(specs)]
     ref = None
-    for variant, refill, graph in [(0, 8, 16), (1, 1, 16), (1, 8, 0), (1, 32, 4), (1, 64, 2),
-                                   (4, 8, 16), (4, 8, 0), (2, 8, 2), (3, 16, 16)]:
+    for variant, refill, graph, tpb in [(0, 8, 16, 1), (1, 1, 16, 1), (1, 8, 0, 2), (1, 32, 4, 1),
+                                        (1, 64, 2, 4), (4, 8, 16, 8), (4, 8, 0, 1), (2, 8, 2, 1),
+                                        (3, 16, 16, 2)]:
         S = pd.Sampler(params)
-        S.set_tuning(variant, refill, graph)
+        S.set_tuning(variant, refill, graph, tpb)
         S.run(M)
         out = [(S.estimates(i), S.get_population(i)) for i in range(len(params))]
         if ref is None:
