@@ -169,7 +169,8 @@ def bench_guide(a):
 
     For each state point and each form (plain: modified dynamics; guided: the
     learned guide, trained on the GPU from plain populations at Nc = 1e5 and
-    distilled on them), the cheapest (Nc, t_obs) of a grid whose RMS error over
+    distilled on them; at L = 400 the L = 100 guide fine-tuned on L = 400
+    populations), the cheapest (Nc, t_obs) of a grid whose RMS error over
     8 seeds against psi_ref is <= 1e-3; psi_ref = mean of plain runs at
     Nc = 1e6 with the same t_obs (psi-hat's large-Nc limit depends on t_obs).
     The reported time is one run at that grid point (median of 3).  Guide
@@ -182,22 +183,41 @@ def bench_guide(a):
     points.append(dict(L=50, N=25, lam=50.0, dt=10.0, t_grid=[10000.0],
                        nc_grid=[1000, 3000, 10000, 30000, 100000], lag=5, snapshots=10,
                        burn=100))
+    # L=400: the guide of the L=100, lambda=20 point, fine-tuned on L=400 populations
+    points.append(dict(L=400, N=200, lam=20.0, dt=1.0, t_grid=[100.0, 500.0],
+                       nc_grid=[100, 1000, 10000], lag=20, snapshots=4, burn=50,
+                       finetune_from=(100, 20.0)))
     out = []
+    trained = {}
     tol, reps = 1e-3, 8
     for P in points:
         L, N, lam, dt = P["L"], P["N"], P["lam"], P["dt"]
         t0 = time.perf_counter()
-        g = guide.train_guide(L, N, inputs.s_of_lambda(lam, L), Nc=100_000, dt=dt,
-                              lag_cycles=P["lag"], snapshots=P["snapshots"],
-                              burn_cycles=P["burn"], epochs=10, lr=1e-3, decay=0.8, gmax=1.0,
-                              seed=9)
+        if "finetune_from" in P:
+            base = trained[P["finetune_from"]]
+            states, counts = guide.collect(L, N, inputs.s_of_lambda(lam, L), 100_000, dt,
+                                           P["lag"], P["snapshots"], P["burn"], seed=77)
+            Sd, Cd = guide.Trainer.upload(states, counts, seed=1)
+            tr = guide.Trainer(L, theta0=base.theta.cpu().numpy(), lr=5e-4)
+            for e in range(3):
+                tr.epoch(Sd, Cd, 5e-4 * 0.8 ** e)
+            _, eg, _ = tr.tables_cond(Sd, 4, 1.0)
+            g = {"trainer": tr, "eg": eg}
+        else:
+            g = guide.train_guide(L, N, inputs.s_of_lambda(lam, L), Nc=100_000, dt=dt,
+                                  lag_cycles=P["lag"], snapshots=P["snapshots"],
+                                  burn_cycles=P["burn"], epochs=10, lr=1e-3, decay=0.8,
+                                  gmax=1.0, seed=9)
+        trained[(L, lam)] = g["trainer"]
         t_train = time.perf_counter() - t0
         refs = {}
         for t_obs in P["t_grid"]:
             psi, _ = _estimates(L, N, lam, 1_000_000, t_obs, dt, 2, pd.PD_W_MODIFIED, seed=1,
                                 inst0=100)
             refs[t_obs] = float(psi.mean())
-        row = {"L": L, "lambda": lam, "dt": dt, "train_seconds": t_train, "psi_ref": refs}
+        row = {"L": L, "lambda": lam, "dt": dt, "train_seconds": t_train, "psi_ref": refs,
+               "guide": "fine-tuned from L=%d" % P["finetune_from"][0] if "finetune_from" in P
+               else "trained at this point"}
         grid = sorted(((nc, t) for nc in P["nc_grid"] for t in P["t_grid"]),
                       key=lambda q: q[0] * q[1])
         for name, mode, eg in (("plain", pd.PD_W_MODIFIED, None),
@@ -225,7 +245,8 @@ def bench_guide(a):
             "higher_is_better": True, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
             "vs_baseline": None,
             "config": {"workload": "guided vs plain: L=100 lambda 5..20 dt=0.5; L=50 lambda=50 "
-                                   "dt=10 t_obs=1e4; RMS over 8 seeds vs plain Nc=1e6"},
+                                   "dt=10 t_obs=1e4; L=400 lambda=20 dt=1 (guide fine-tuned "
+                                   "from L=100); RMS over 8 seeds vs plain Nc=1e6"},
             "points": out}
 
 
