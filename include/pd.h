@@ -151,7 +151,8 @@ pd_status pd_get_population(pd_ctx* ctx, int32_t inst, void* host, size_t bytes)
 
 /* Replaces the current population of instance `inst` (synchronises).
  * Every clone must hold exactly N particles in its first L bits (PD_EINVAL
- * otherwise).  Clears a pending dynamical stage. */
+ * otherwise).  Clears a pending dynamical stage.  Carried origins are left as
+ * they were and mean nothing for the new clones until pd_reset_origin. */
 pd_status pd_set_population(pd_ctx* ctx, int32_t inst, const void* host, size_t bytes);
 
 /* Per-clone outputs of the last dynamical stage of instance `inst`, indexed
@@ -193,10 +194,11 @@ pd_status pd_mean(pd_ctx* ctx, int32_t inst, const double* d_values, int32_t anc
  * mean_kb[beta-1] = population mean of K^beta before cloning.  Synchronises. */
 pd_status pd_get_log(pd_ctx* ctx, int32_t inst, double* lbeta, double* mean_kb, int32_t n_rows);
 
-/* Checkpoint of the whole context (all instances: populations and estimator
- * sums) into a host buffer of pd_save_bytes() bytes, and its restore into a
- * context created with the same parameters.  A restored run continues
- * bit-identically. Both synchronise. */
+/* Checkpoint of the whole context (all instances: populations, estimator sums
+ * and, for instances with track_origin, the carried origins) into a host
+ * buffer of pd_save_bytes() bytes, and its restore into a context created
+ * with the same parameters.  A restored run continues bit-identically.  Both
+ * synchronise. */
 pd_status pd_save_bytes(pd_ctx* ctx, size_t* bytes);
 pd_status pd_save(pd_ctx* ctx, void* host, size_t bytes);
 pd_status pd_load(pd_ctx* ctx, const void* host, size_t bytes);

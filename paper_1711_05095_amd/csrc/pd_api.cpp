@@ -687,8 +687,10 @@ pd_status pd_save_bytes(pd_ctx* ctx, size_t* bytes)
 {
     if (!ctx || !bytes) return PD_EINVAL;
     size_t b = 3 * 8;
-    for (const auto& p : ctx->params)
+    for (const auto& p : ctx->params) {
         b += sizeof(InstCtl) + 8 * (size_t)p.Nc * (size_t)(words_of(p.L) + 1);
+        if (p.track_origin) b += (4 * (size_t)p.Nc + 7) / 8 * 8;
+    }
     *bytes = b;
     return PD_OK;
 }
@@ -716,6 +718,11 @@ pd_status pd_save(pd_ctx* ctx, void* host, size_t bytes)
         at += 8 * Nc * W;
         PD_HIP(hipMemcpyAsync(at, d.K[ctx->cur], 8 * Nc, hipMemcpyDeviceToHost, ctx->stream));
         at += 8 * Nc;
+        if (d.origin[0]) {
+            PD_HIP(hipMemcpyAsync(at, d.origin[ctx->cur], 4 * Nc, hipMemcpyDeviceToHost,
+                                  ctx->stream));
+            at += (4 * Nc + 7) / 8 * 8;
+        }
     }
     PD_HIP(hipStreamSynchronize(ctx->stream));
     return PD_OK;
@@ -740,6 +747,11 @@ pd_status pd_load(pd_ctx* ctx, const void* host, size_t bytes)
         at += 8 * Nc * W;
         PD_HIP(hipMemcpyAsync(d.K[ctx->cur], at, 8 * Nc, hipMemcpyHostToDevice, ctx->stream));
         at += 8 * Nc;
+        if (d.origin[0]) {
+            PD_HIP(hipMemcpyAsync(d.origin[ctx->cur], at, 4 * Nc, hipMemcpyHostToDevice,
+                                  ctx->stream));
+            at += (4 * Nc + 7) / 8 * 8;
+        }
     }
     PD_HIP(hipStreamSynchronize(ctx->stream));
     ctx->beta = (int64_t)h[2];

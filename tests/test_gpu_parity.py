@@ -328,6 +328,31 @@ def test_origin_tracking_composes_ancestor_maps():
     assert np.bincount(S.origin(), minlength=Nc).sum() == Nc
 
 
+def test_checkpoint_and_autotune_keep_origins():
+    """Carried origins survive a checkpoint round trip, and the autotuner (which
+    runs trial cycles and restores the context) leaves them as an uninterrupted
+    run has them."""
+    p = pd.make_params(60, 30, 0.01, 2000, 10.0, 0.5, seed=93, track_origin=1)
+    A = pd.Sampler(p)
+    A.run(3)
+    A.reset_origin()
+    A.run(5)
+    blob = A.save()
+    A.run(4)
+    want = A.origin()
+    A.load(blob)
+    A.run(4)
+    assert np.array_equal(A.origin(), want)
+    B = pd.Sampler(p)
+    B.run(3)
+    B.reset_origin()
+    B.run(5)
+    B.autotune(2)
+    B.run(4)
+    assert np.array_equal(B.origin(), want)
+    assert B.estimates() == A.estimates()
+
+
 def test_compacting_variant_carries_origins():
     """Variant 4 (compaction between rounds) carries origin ids exactly as
     variant 0 does."""
