@@ -220,30 +220,18 @@ static int window13(const uint8_t* n, int L, int c)
  * and the compensating factor of the interval is
  *     ln Ups = -sum_jumps g - int (r(C) - e^{-s} S(C) 2^-16) dt,
  * which makes the weighted guided trajectories unbiased for ANY table.
- * Random words of a clone come from one stream per interval: block n of the
- * GUIDE stream of (slot, beta) gives words 2n and 2n+1.  Each event uses one
- * word for the waiting time; each proposal of the hop uses one word for the
- * uniform allowed bond and one for its acceptance with probability
- * eg[u_b] / eg_max (exact 64-bit Bernoulli), repeated until accepted. */
-enum { ORC_TAG_GUIDE = 5 };
+ * The hop is chosen by rejection: a uniform allowed bond (64-bit word w,
+ * index floor(w r / 2^64)) is accepted with probability eg[u_b] / eg_max
+ * (64-bit word a, accepted iff floor(a eg_max / 2^64) < eg[u_b]), repeated
+ * until accepted.  Random numbers of a clone in interval beta: event k (its
+ * waiting times counted from 0) takes block (k, slot, beta, GUIDE): the
+ * waiting time from words 0, 1 as in the plain dynamics, the first proposal's
+ * bond word from words 2, 3; proposal p (counted over the interval from 0)
+ * takes block (p, slot, beta, GUIDE_PROP): its acceptance word from words
+ * 0, 1 and, if it is rejected, the next proposal's bond word from words 2, 3. */
+enum { ORC_TAG_GUIDE = 5, ORC_TAG_GUIDE_PROP = 6 };
 
-typedef struct {
-    const orc_params* p;
-    uint32_t beta, slot, block, half;
-    uint32_t x[4];
-} word_stream;
-
-static uint64_t next_word(word_stream* ws)
-{
-    if (ws->half == 0) {
-        draw(ws->p, ORC_TAG_GUIDE, ws->block, ws->slot, ws->beta, ws->x);
-        ws->block++;
-        ws->half = 1;
-        return ((uint64_t)ws->x[0] << 32) | ws->x[1];
-    }
-    ws->half = 0;
-    return ((uint64_t)ws->x[2] << 32) | ws->x[3];
-}
+static uint64_t word_of(uint32_t hi, uint32_t lo) { return ((uint64_t)hi << 32) | lo; }
 
 static uint64_t guided_total(const orc_params* p, const uint8_t* n)
 {
@@ -266,13 +254,15 @@ static uint32_t step_clone_guided(const orc_params* p, double es, uint32_t egmax
 {
     const int L = p->L;
     const double dt = p->dt;
-    word_stream ws = { p, beta, (uint32_t)j, 0u, 0u, {0, 0, 0, 0} };
     double tau = 0.0, A = 0.0, AS = 0.0, G = 0.0;
-    uint32_t kb = 0;
+    uint32_t kb = 0, k = 0, prop = 0;
     int r = escape_count(n, L);
     uint64_t S = guided_total(p, n);
     while (r > 0) {
-        double u = (double)((next_word(&ws) >> 11) + 1) * 0x1p-53;
+        uint32_t x[4];
+        draw(p, ORC_TAG_GUIDE, k, (uint32_t)j, beta, x);
+        ++k;
+        double u = (double)((word_of(x[0], x[1]) >> 11) + 1) * 0x1p-53;
         double E = -log(u);
         double R = es * ((double)S * 0x1p-16);
         double w = E / R;
@@ -284,12 +274,17 @@ static uint32_t step_clone_guided(const orc_params* p, double es, uint32_t egmax
         A = fma((double)r, w, A);
         AS = fma((double)S, w, AS);
         tau = tau + w;
+        uint64_t bond_word = word_of(x[2], x[3]);
         int bond = -1;
         uint32_t e = 0;
-        for (int proposal = 0; proposal < (1 << 20); ++proposal) {
-            bond = qth_active_bond(n, L, (int)mulhi64(next_word(&ws), (uint64_t)r));
+        for (;;) {
+            bond = qth_active_bond(n, L, (int)mulhi64(bond_word, (uint64_t)r));
             e = p->guide[window13(n, L, bond)];
-            if (mulhi64(next_word(&ws), (uint64_t)egmax) < (uint64_t)e) break;
+            uint32_t y[4];
+            draw(p, ORC_TAG_GUIDE_PROP, prop, (uint32_t)j, beta, y);
+            ++prop;
+            if (mulhi64(word_of(y[0], y[1]), (uint64_t)egmax) < (uint64_t)e) break;
+            bond_word = word_of(y[2], y[3]);
         }
         G += log((double)e * 0x1p-16);
         uint8_t t = n[bond];

@@ -23,31 +23,18 @@ namespace pd {
 // the hop is chosen by proposing a uniform allowed bond and accepting it with
 // probability eg / eg_max (exact 64-bit Bernoulli), and the compensating
 // factor is ln Ups = -sum_jumps ln(eg 2^-16) - int (r - e^{-s} S 2^-16) dt.
-// Random words come from one GUIDE stream per (slot, interval): block n gives
-// words 2n, 2n+1; an event uses one word for its waiting time and each
-// proposal one word for the bond and one for the acceptance.
+// Random numbers of a clone in interval beta: event k (its waiting times
+// counted from 0) takes Philox block (k, slot, beta, GUIDE): the waiting time
+// from words 0, 1 and the first proposal's bond word from words 2, 3; proposal
+// p (counted over the interval from 0) takes block (p, slot, beta, GUIDE_PROP):
+// its acceptance word from words 0, 1 and, if it is rejected, the next
+// proposal's bond word from words 2, 3.  Every call site draws one block per
+// pass of its loop, so no lane of a wave waits on another lane's refill.
 // In LDS the table keeps only the 4096 neighbourhoods of allowed bonds (bit 7
 // is the complement of bit 6 there, so it is dropped), and sum_jumps ln eg is
 // formed as the logarithm of the running product of the eg, kept in [0.5, 1)
 // by frexp with the binary exponents summed separately.
 // ---------------------------------------------------------------------------
-struct WordStream {
-    uint32_t block, half;
-    uint4 y;
-};
-
-__device__ __forceinline__ uint64_t next_word(WordStream& ws, uint32_t slot, uint32_t beta,
-                                              uint32_t c3, uint32_t k0, uint32_t k1)
-{
-    if (ws.half == 0) {
-        ws.y = philox10(ws.block, slot, beta, c3, k0, k1);
-        ws.block++;
-        ws.half = 1;
-        return ((uint64_t)ws.y.x << 32) | ws.y.y;
-    }
-    ws.half = 0;
-    return ((uint64_t)ws.y.z << 32) | ws.y.w;
-}
 
 // i mod L in [0, L) for i >= -L * 8.
 __device__ __forceinline__ int ring_mod(int i, int L)
@@ -107,7 +94,7 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
     const int64_t j = td.first + tid;
     const int64_t Nc = I.Nc;
     const uint32_t beta = (uint32_t)(I.ctl->beta + 1);
-    const uint32_t c3 = TAG_GUIDE | I.tag_hi;
+    const uint32_t c3 = TAG_GUIDE | I.tag_hi, cp = TAG_GUIDE_PROP | I.tag_hi;
     const double es = I.es, dt = I.dt;
     const uint64_t egmax = I.guide_max;
 
@@ -123,15 +110,15 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
         bond_mask<W>(x, lb, m);
         int r = popcount_words<W>(m);
         uint64_t S = guided_total<W>(x, m, L, s_eg);
-        WordStream ws = {0u, 0u, make_uint4(0, 0, 0, 0)};
+        uint32_t k = 0, prop = 0;
         double tau = 0.0, A = 0.0, AS = 0.0, P = 1.0;
         int pexp = 0;
         int events = 0;
         while (r > 0 && events < (1 << 30)) {
             ++events;
-            const uint64_t wu = next_word(ws, (uint32_t)j, beta, c3, I.key0, I.key1);
-            const double E = -log_unit(unit_open0((uint32_t)(wu >> 32), (uint32_t)wu), s_log,
-                                       I.ln2_hi, I.ln2_lo);
+            const uint4 y = philox10(k, (uint32_t)j, beta, c3, I.key0, I.key1);
+            ++k;
+            const double E = -log_unit(unit_open0(y.x, y.y), s_log, I.ln2_hi, I.ln2_lo);
             const double R = es * ((double)S * 0x1p-16);
             const double w = E / R;
             if (tau + w >= dt) {
@@ -144,13 +131,15 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
             tau = tau + w;
             int b = 0;
             uint32_t e = 0;
-            for (int prop = 0; prop < (1 << 20); ++prop) {
-                const uint64_t wq = next_word(ws, (uint32_t)j, beta, c3, I.key0, I.key1);
-                b = select_bit<W>(m, mulhi64_small((uint32_t)(wq >> 32), (uint32_t)wq,
-                                                   (uint32_t)r));
+            uint32_t qh = y.z, ql = y.w;   // bond word of the first proposal
+            for (int tries = 0; tries < (1 << 20); ++tries) {
+                b = select_bit<W>(m, mulhi64_small(qh, ql, (uint32_t)r));
                 e = s_eg[gidx(ring_bits<W>(x, L, ring_mod(b - 6, L), 13))];
-                const uint64_t wa = next_word(ws, (uint32_t)j, beta, c3, I.key0, I.key1);
-                if (__umul64hi(wa, egmax) < (uint64_t)e) break;
+                const uint4 a = philox10(prop, (uint32_t)j, beta, cp, I.key0, I.key1);
+                ++prop;
+                if (__umul64hi(((uint64_t)a.x << 32) | a.y, egmax) < (uint64_t)e) break;
+                qh = a.z;
+                ql = a.w;
             }
             P *= (double)e;
             pexp += __builtin_amdgcn_frexp_exp(P);

@@ -11,7 +11,8 @@ constexpr int kMaxWords = 8;        // 64-site words per state
 constexpr int kMaxSites = 512;      // L <= kMaxSites
 constexpr int kLogRows = 96;        // rows of the logarithm table
 
-enum : uint32_t { TAG_INIT = 1, TAG_DYN = 2, TAG_RESAMPLE = 3, TAG_IID = 4, TAG_GUIDE = 5 };
+enum : uint32_t { TAG_INIT = 1, TAG_DYN = 2, TAG_RESAMPLE = 3, TAG_IID = 4, TAG_GUIDE = 5,
+                  TAG_GUIDE_PROP = 6 };
 constexpr int kGuideEntries = 8192; // 13-site bond neighbourhoods
 enum : int32_t { MODE_MODIFIED = 0, MODE_DIRECT = 1, MODE_GUIDED = 2 };
 enum : int32_t { SEL_EQ = 0, SEL_IID = 1 };
