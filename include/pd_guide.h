@@ -78,6 +78,22 @@ pd_status pdg_loss_grad(const float* theta, const uint64_t* states, int64_t ld,
 pd_status pdg_adam(float* theta, float* m, float* v, const float* grad, int32_t step, float lr,
                    void* hip_stream);
 
+/* One epoch of training (Sec. 2.4's regression of descendant counts): the n
+ * samples (states, ld and counts as in pdg_loss_grad) in minibatches of
+ * `batch` columns, [0, batch), [batch, 2 batch), ..., the last one shorter;
+ * for the k-th minibatch (k = 0, 1, ...) the gradient of its mean loss and
+ * one Adam step with step number step0 + k + 1, as pdg_loss_grad followed by
+ * pdg_adam would give them (same results, bit for bit), then its loss added,
+ * as a double, to *loss_sum (device memory) in minibatch order.  Everything
+ * is enqueued on the stream from the library (two launches per minibatch, no
+ * host synchronisation); the caller advances its step count by
+ * ceil(n / batch).  work: pdg_workspace_bytes(min(batch, n)) bytes, 256-byte
+ * aligned.  batch >= 1, step0 >= 0, lr > 0. */
+pd_status pdg_train_epoch(float* theta, float* m, float* v, const uint64_t* states, int64_t ld,
+                          const float* counts, int32_t L, int64_t n, int64_t batch, int32_t step0,
+                          float lr, double* loss_sum, void* work, size_t work_bytes,
+                          void* hip_stream);
+
 /* table[w] = h(w) for the 8192 windows w of 13 sites (site j-6 in bit 0 ...
  * site j+6 in bit 12): the net on the window alone, so f(C) = sum_j h(w_j). */
 pd_status pdg_window_table(const float* theta, float* table, void* hip_stream);

@@ -11,9 +11,10 @@
 //   o_j  = b3 + sum_{c',k} W3[c'][k] h2[c'][j+k-2]                 (32 -> 1)
 //
 // Weights enter the arithmetic rounded to bfloat16 (the FP32 master copy is
-// what Adam updates); the 32 x 160 x L contractions of layer 2 (forward, the
-// weight gradient and the input gradient) run on MFMA 16x16x16 bf16 with FP32
-// accumulation; the small layers 1 and 3 run on the vector ALU in FP32.
+// what Adam updates, biases stay FP32); the 32 x 160 x L contractions of
+// layer 2 (forward, the weight gradient and the input gradient) and layer 1
+// (exact: its inputs are +-1) run on the matrix cores in bf16 with FP32
+// accumulation; layer 3 and the activations run on the vector ALU in FP32.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -25,7 +26,11 @@
 namespace pd {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 constexpr int CH = 32, KS = 5, Q = CH * KS;
 constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + CH * KS, OFF_W2 = OFF_B1 + CH,
@@ -46,52 +51,46 @@ __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
+__device__ __forceinline__ f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
 
-// ---------------------------------------------------------------------------
-// Forward and backward passes, one sample per wave, several waves per block
-// sharing the weights.
-//
-// The layer-2 contraction index is taken tap-major, q = t * 32 + c' (tap t of
-// the kernel, input channel c'), so that four consecutive q of an MFMA operand
-// are four consecutive channels of one position: with the activations stored
-// position-major ([position][channel], bf16) each operand of the forward pass
-// and of the input-gradient pass is one 8-byte LDS read.  The weight-gradient
-// pass contracts over positions and reads the activations position-contiguous
-// ([channel][position]).  Positions carry a circular halo of two sites on each
-// side (row i holds position i - 2).
-//
-// The scalar delta = d loss / d f of a sample is applied after the matrix
-// products (in float32): the products run on g2 = w3s (1 - h2^2) and the
-// results are scaled by delta, so no operand is converted per element.
-// Layer-1 activations in float32 are recomputed where 1 - h1^2 is needed.
-// ---------------------------------------------------------------------------
-constexpr int kNetShared = 2 * CH * Q * 2 + 4 * (Q + 3 * CH);  // bytes
+// Row strides chosen so that the operand reads of a wave spread over all LDS
+// banks: W2R / W2T rows of WS halves (336 bytes) and position-major rows of RS
+// halves (80 bytes) put 8 consecutive rows of a 16-byte read on 8 disjoint
+// 16-byte bank groups; channel-major rows of P = LP + 4 halves (2 x odd
+// dwords) do the same for the 8-byte reads of the weight-gradient pass.
+constexpr int WS = 168, RS = 40;
+constexpr int kNetShared = 2 * CH * WS * 2 + 4 * (3 * CH);  // bytes
 
 struct NetShared {
-    uint16_t* W2R;   // [c][t * 32 + c']  = W2[c][c'][t]
-    uint16_t* W2T;   // [c'][t * 32 + c]  = W2[c][c'][t]
-    float* W1;       // [c][t] (bf16 values)
+    uint16_t* W2R;   // [c][t * 32 + c']  = W2[c][c'][t]   (row stride WS)
+    uint16_t* W2T;   // [c'][t * 32 + c]  = W2[c][c'][t]   (row stride WS)
     float* b1;
     float* b2;
     float* w3s;      // sum_t W3[c][t] (bf16 values)
 };
 
-struct NetWave {
-    float* sa;       // [P] a at row i = position i - 2
-    uint16_t* H1P;   // [P][32] bf16 h1
-    uint16_t* H1C;   // [32][P] bf16 h1
-    uint16_t* G2C;   // [32][LP] bf16 g2 (zero beyond L)
-    uint16_t* G2P;   // [P][32] bf16 g2
-};
-
 __host__ __device__ inline int net_lp(int L) { return (L + 15) / 16 * 16; }
 
-// Bytes of one wave's region: its arrays, and at least the 32 x 160 floats of
-// the end-of-block reduction of the layer-2 weight gradient.
+// The inputs a = 2 n - 1 of a sample as a circular bit string: bit i is
+// site (i - 4) mod L, so that the 5-site window of layer 1 at row R (site
+// R - 2) is bits R .. R + 4.  Rows up to LP + 1 are evaluated, each reading
+// the 32-bit window at its row.
+__host__ __device__ inline int net_ext_words(int L)
+{
+    return (32 * (((net_lp(L) + 13) >> 5) + 2) + 63) / 64;
+}
+__host__ __device__ inline size_t net_ext_bytes(int L) { return (8 * net_ext_words(L) + 15) / 16 * 16; }
+
+// Bytes of one wave's region: the bit string, the position-major array (h1,
+// then g2 once the forward pass is past a row), the channel-major h1 and g2,
+// and at least the 32 x 160 floats of the end-of-block reduction.
 __host__ __device__ inline size_t net_wave_bytes(int L)
 {
     const size_t LP = net_lp(L), P = LP + 4;
-    const size_t arrays = (4 * P + 15) / 16 * 16 + 2 * P * CH * 2 + 2 * CH * LP + 2 * P * CH;
+    const size_t arrays = net_ext_bytes(L) + P * RS * 2 + 2 * CH * P * 2;
     const size_t red = sizeof(float) * CH * Q;
     return ((arrays > red ? arrays : red) + 15) / 16 * 16;
 }
@@ -104,17 +103,15 @@ __host__ __device__ inline int net_waves(int L)
     return w < 1 ? 1 : (w > 4 ? 4 : w);
 }
 
-// tanh from one exponential and one reciprocal: 1 - 2 / (e^{2x} + 1), and the
-// odd series x - x^3/3 + 2x^5/15 for |x| < 2^-6 where the difference would
-// cancel.  The error (a few ulp of float) is far below the bfloat16 rounding
-// of the activations that follows.
+// tanh(x) = 1 - 2 / (e^{2x} + 1) from the hardware base-2 exponential and
+// reciprocal (each within about 1 ulp): absolute error a few 1e-7 for every
+// x, saturating to +-1 for large |x|.  Near 0 the relative error grows, but
+// the absolute one stays far below the bfloat16 quantum of the activations
+// and below what float32 accumulation of the network's sums adds.
 __device__ __forceinline__ float tanh_fast(float x)
 {
-    const float e = __expf(2.0f * x);
-    const float t = 1.0f - 2.0f * __frcp_rn(e + 1.0f);
-    const float x2 = x * x;
-    const float sers = x * (1.0f + x2 * (-1.0f / 3.0f + x2 * (2.0f / 15.0f)));
-    return fabsf(x) < 0.015625f ? sers : t;
+    const float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);   // e^{2x}
+    return fmaf(-2.0f, __builtin_amdgcn_rcpf(e + 1.0f), 1.0f);
 }
 
 __device__ __forceinline__ void wave_sync()
@@ -128,24 +125,87 @@ __device__ __forceinline__ bf16x4 ld4(const uint16_t* p)
 {
     return *reinterpret_cast<const bf16x4*>(p);
 }
-
-// Circular halo and zero rows of a position-major [P][32] array holding rows
-// 2 .. L+1: rows 0, 1 <- L, L+1; rows L+2, L+3 <- 2, 3; rows >= L+4 <- 0.
-// For the position-contiguous copy (when C is not null) the same rows.
-__device__ void halo_rows(uint16_t* Pm, uint16_t* Cm, int L, int P, int lane)
+__device__ __forceinline__ bf16x8 ld8(const uint16_t* p)
 {
-    const int nrow = P - L;
-    for (int idx = lane; idx < CH * nrow; idx += 64) {
-        const int c = idx / nrow, h = idx % nrow;
-        const int i = h < 2 ? h : L + h;
-        uint16_t v = 0;
-        if (i < 2) v = Pm[(L + i) * CH + c];
-        else if (i < L + 4) v = Pm[(i - L) * CH + c];
-        Pm[i * CH + c] = v;
-        if (Cm) Cm[c * P + i] = v;
+    return *reinterpret_cast<const bf16x8*>(p);
+}
+__device__ __forceinline__ bf16x4 as_bf16x4(uint32_t lo, uint32_t hi)
+{
+    return __builtin_bit_cast(bf16x4, u32x2{lo, hi});
+}
+
+// Two floats to a pair of bfloat16 (round to nearest even), low half first.
+__device__ __forceinline__ uint32_t pk_bf16(float lo, float hi)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{lo, hi}, bf16x2));
+}
+
+// The 32 bits of the circular input string starting at bit R.
+__device__ __forceinline__ uint32_t ext_window(const uint32_t* ext32, int R)
+{
+    return __builtin_amdgcn_alignbit(ext32[(R >> 5) + 1], ext32[R >> 5], (uint32_t)(R & 31));
+}
+
+// B operand of layer 1 (16x16x16, k = 4 g4 + i): the inputs a_k = +-1 of the
+// window bits k < 5 as bfloat16 (0x3F80 / 0xBF80), zero for k >= 5; m0, m1
+// are the lane's masks of valid halves.
+__device__ __forceinline__ bf16x4 l1_operand(uint32_t x, int g4, uint32_t m0, uint32_t m1)
+{
+    const uint32_t y = x >> (4 * g4);
+    const uint32_t d0 = 0xBF80BF80u ^ (((y & 1u) << 15) | ((y & 2u) << 30));
+    const uint32_t d1 = 0xBF80BF80u ^ (((y & 4u) << 13) | ((y & 8u) << 28));
+    return as_bf16x4(d0 & m0, d1 & m1);
+}
+
+// Positions of one wave's sample, one lane per bit: lane k < W holds word k of
+// the sample; bit i = w * 64 + lane of the string is site p (advanced by 64
+// per word, modulo L).
+__device__ __forceinline__ void build_ext(uint64_t* ext, uint64_t word_of_lane, int p0, int L,
+                                          int next, int lane)
+{
+    int p = p0;
+    for (int w = 0; w < next; ++w) {
+        const int src = p >> 6;
+        const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)word_of_lane, src);
+        const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(word_of_lane >> 32), src);
+        const uint32_t wbits = (p & 32) ? hi : lo;
+        const uint64_t m = __ballot((wbits >> (p & 31)) & 1u);
+        if (lane == 0) ext[w] = m;
+        p += 64;
+        while (p >= L) p -= L;
     }
 }
 
+// Circular halo rows of the position-major h1 and its channel-major copy:
+// rows 0, 1 and LP + 2, LP + 3 copied from the rows of their sites; for g2
+// (position-major only) rows 0, 1 and L + 2, L + 3 copied, rows LP + 2 and
+// LP + 3 zero where they are not those.  dst / src rows per lane slot are
+// precomputed (src < 0: zero).
+struct HaloSlots {
+    int dst[3], src[3];
+};
+
+// ---------------------------------------------------------------------------
+// Forward and backward passes, one sample per wave, several waves per block
+// sharing the weights.
+//
+// Layer 1 (1 -> 32, K = 5 padded to 16) and layer 2 (32 -> 32, K = 160) run
+// on the matrix cores, channels as the rows of the product and positions as
+// its columns: each lane ends with 4 consecutive channels of one position.
+// The layer-2 contraction index is taken tap-major, q = t * 32 + c', so that
+// one 16x16x32 step covers one tap: its B operand is 8 consecutive channels
+// of one position, a 16-byte read of the position-major array.  The
+// weight-gradient pass contracts over positions (16x16x16) and reads the
+// channel-major copies; the tap shift of its B operand is taken from two
+// aligned 8-byte reads with byte alignment, all five taps from one pair.
+//
+// The position-major array holds h1 during the forward pass and g2 after it:
+// the g2 of a position tile is written one tile late, once the next tile has
+// read the h1 rows they share.  The scalar delta = d loss / d f of a sample is
+// applied after the matrix products (in float32): the products run on
+// g2 = w3s (1 - h2^2) and the results are scaled by delta.  Layer-1
+// activations are recomputed on the matrix cores where 1 - h1^2 is needed.
+// ---------------------------------------------------------------------------
 template <int MODE>
 __global__ __launch_bounds__(256) void k_net(const float* __restrict__ theta,
                                              const uint64_t* __restrict__ states,
@@ -153,34 +213,35 @@ __global__ __launch_bounds__(256) void k_net(const float* __restrict__ theta,
                                              int64_t ld, float inv_n, float* __restrict__ f_out,
                                              float* __restrict__ partial)
 {
+    // products and sums may fuse here: the results are compared statistically
+#pragma clang fp contract(fast)
     extern __shared__ __align__(16) char smem[];
-    const int LP = net_lp(L), P = LP + 4;
+    const int LP = net_lp(L), P = LP + 4, NT = LP / 16;
+    const int W = (L + 63) >> 6, next = net_ext_words(L);
     const int nw = blockDim.x >> 6;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int r = lane & 15, g4 = lane >> 4;
 
     NetShared S;
     S.W2R = (uint16_t*)smem;
-    S.W2T = S.W2R + CH * Q;
-    S.W1 = (float*)(S.W2T + CH * Q);
-    S.b1 = S.W1 + Q;
+    S.W2T = S.W2R + CH * WS;
+    S.b1 = (float*)(S.W2T + CH * WS);
     S.b2 = S.b1 + CH;
     S.w3s = S.b2 + CH;
     char* wbase = smem + kNetShared + (size_t)wv * net_wave_bytes(L);
-    NetWave V;
-    V.sa = (float*)wbase;
-    V.H1P = (uint16_t*)(wbase + ((4 * P + 15) / 16) * 16);
-    V.H1C = V.H1P + P * CH;
-    V.G2C = V.H1C + CH * P;
-    V.G2P = V.G2C + CH * LP;
+    uint64_t* ext = (uint64_t*)wbase;
+    const uint32_t* ext32 = (const uint32_t*)wbase;
+    uint16_t* HP = (uint16_t*)(wbase + net_ext_bytes(L));   // [P][RS]: h1, then g2
+    uint16_t* H1C = HP + P * RS;                              // [32][P]
+    uint16_t* G2C = H1C + CH * P;                             // [32][P], zero beyond L
 
     for (int i = threadIdx.x; i < CH * Q; i += blockDim.x) {
         const int c = i / Q, rest = i % Q, cp = rest / KS, t = rest % KS;   // W2[c][c'][t]
         const uint16_t v = f2bf(theta[OFF_W2 + i]);
-        S.W2R[c * Q + t * CH + cp] = v;
-        S.W2T[cp * Q + t * CH + c] = v;
+        S.W2R[c * WS + t * CH + cp] = v;
+        S.W2T[cp * WS + t * CH + c] = v;
     }
-    for (int i = threadIdx.x; i < Q; i += blockDim.x) S.W1[i] = bfr(theta[OFF_W1 + i]);
     for (int c = threadIdx.x; c < CH; c += blockDim.x) {
         S.b1[c] = theta[OFF_B1 + c];
         S.b2[c] = theta[OFF_B2 + c];
@@ -188,95 +249,159 @@ __global__ __launch_bounds__(256) void k_net(const float* __restrict__ theta,
         for (int t = 0; t < KS; ++t) w += bfr(theta[OFF_W3 + c * KS + t]);
         S.w3s[c] = w;
     }
+    // layer-1 B operand: W1[mt * 16 + r][k], k = 4 g4 + i < 5
+    bf16x4 W1op[2];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+        uint16_t h[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = 4 * g4 + i;
+            h[i] = k < KS ? f2bf(theta[OFF_W1 + (mt * 16 + r) * KS + k]) : (uint16_t)0;
+        }
+        W1op[mt] = as_bf16x4(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16));
+    }
+    const uint32_t m0 = g4 == 0 ? 0xFFFFFFFFu : (g4 == 1 ? 0x0000FFFFu : 0u);
+    const uint32_t m1 = g4 == 0 ? 0xFFFFFFFFu : 0u;
+    const uint32_t ma = r < KS ? 0xFFFFFFFFu : 0u;
+    // halo slots: idx = lane + 64 s over 4 rows (h1) / 6 rows (g2) of 32 channels
+    HaloSlots H1s, G2s;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        const int idx = lane + 64 * s, k = idx >> 5;
+        H1s.dst[s] = H1s.src[s] = -1;
+        if (k < 4) {
+            const int R = k < 2 ? k : LP + k;   // 0, 1, LP + 2, LP + 3
+            H1s.dst[s] = R;
+            H1s.src[s] = (R - 2 + 2 * L) % L + 2;
+        }
+        const int RG = k == 0 ? 0 : k == 1 ? 1 : k == 2 ? LP + 2 : k == 3 ? LP + 3 : L + k - 2;
+        G2s.dst[s] = RG;
+        G2s.src[s] = RG < 2 ? RG + L : (RG == L + 2 || RG == L + 3) ? RG - L : -1;
+    }
+    const int p0 = (lane - 4 + L) % L;
     __syncthreads();
     const float b3 = theta[OFF_B3], c0 = theta[OFF_C0];
+    // the lane's channels c = mt * 16 + r
+    float b1s[2], b2s[2], w3c[2];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+        b1s[mt] = S.b1[mt * 16 + r];
+        b2s[mt] = S.b2[mt * 16 + r];
+        w3c[mt] = S.w3s[mt * 16 + r];
+    }
 
-    // per-lane accumulators over the block's samples; the lane's channels are
-    // c = mt * 16 + 4 * g4 + v, its weight-gradient columns q = qt * 16 + r
-    f32x4 acc[2][10];
-    float gW1[2][4][KS], gb1[2][4], gW3[2][4], gb2[2][4];
+    // per-lane accumulators over the block's samples: the layer-2 weight
+    // gradient for c = mt * 16 + 4 g4 + v and q = qt * 16 + r, the layer-1
+    // weight gradient for c = mt * 16 + 4 g4 + v and tap r < 5, and per-channel
+    // sums for c = mt * 16 + r
+    f32x4 acc[2][10], gW1[2];
+    float gb1[2], gW3[2], gb2[2];
     float gb3 = 0.0f, gc0 = 0.0f, gloss = 0.0f;
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
 #pragma unroll
         for (int b = 0; b < 10; ++b) acc[a][b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            gb1[a][v] = gW3[a][v] = gb2[a][v] = 0.0f;
-#pragma unroll
-            for (int t = 0; t < KS; ++t) gW1[a][v][t] = 0.0f;
-        }
+        gW1[a] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        gb1[a] = gW3[a] = gb2[a] = 0.0f;
     }
 
     const int64_t stride = (int64_t)gridDim.x * nw;
-    for (int64_t smp = (int64_t)blockIdx.x * nw + wv; smp < n; smp += stride) {
-        // inputs a = 2 n - 1, circular rows
-        for (int i = lane; i < P; i += 64) {
-            int site = i - 2;
-            site = site < 0 ? site + L : (site >= L ? site - L : site);
-            float v = 0.0f;
-            if (i < L + 4)
-                v = ((states[(int64_t)(site >> 6) * ld + smp] >> (site & 63)) & 1ull) ? 1.0f : -1.0f;
-            V.sa[i] = v;
-        }
+    int64_t smp = (int64_t)blockIdx.x * nw + wv;
+    uint64_t word = (lane < W && smp < n) ? states[(int64_t)lane * ld + smp] : 0ull;
+    for (; smp < n; smp += stride) {
+        const uint64_t word_next =
+            (lane < W && smp + stride < n) ? states[(int64_t)lane * ld + smp + stride] : 0ull;
+        build_ext(ext, word, p0, L, next, lane);
+        word = word_next;
         wave_sync();
-        // layer 1
-        for (int j = lane; j < L; j += 64) {
-            float a5[KS];
+        // layer 1, positions as rows: the lane reads the window of position
+        // nt * 16 + r and ends with channel mt * 16 + r at rows R0 .. R0 + 3
+        for (int nt = 0; nt < NT; ++nt) {
+            const bf16x4 Aa = l1_operand(ext_window(ext32, nt * 16 + 2 + r), g4, m0, m1);
+            const int R0 = nt * 16 + 2 + 4 * g4;
 #pragma unroll
-            for (int t = 0; t < KS; ++t) a5[t] = V.sa[j + t];
-            for (int c = 0; c < CH; ++c) {
-                float z = S.b1[c];
-#pragma unroll
-                for (int t = 0; t < KS; ++t) z += S.W1[c * KS + t] * a5[t];
-                const uint16_t hb = f2bf(tanh_fast(z));
-                V.H1P[(j + 2) * CH + c] = hb;
-                V.H1C[c * P + j + 2] = hb;
+            for (int mt = 0; mt < 2; ++mt) {
+                const int c = mt * 16 + r;
+                const f32x4 z = mfma16(Aa, W1op[mt], f32x4{b1s[mt], b1s[mt], b1s[mt], b1s[mt]});
+                const uint32_t lo = pk_bf16(tanh_fast(z[0]), tanh_fast(z[1]));
+                const uint32_t hi = pk_bf16(tanh_fast(z[2]), tanh_fast(z[3]));
+                *reinterpret_cast<uint32_t*>(H1C + c * P + R0) = lo;
+                *reinterpret_cast<uint32_t*>(H1C + c * P + R0 + 2) = hi;
+                HP[R0 * RS + c] = (uint16_t)lo;
+                HP[(R0 + 1) * RS + c] = (uint16_t)(lo >> 16);
+                HP[(R0 + 2) * RS + c] = (uint16_t)hi;
+                HP[(R0 + 3) * RS + c] = (uint16_t)(hi >> 16);
             }
         }
         wave_sync();
-        halo_rows(V.H1P, V.H1C, L, P, lane);
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            if (H1s.dst[s] >= 0) {
+                const int c = (lane + 64 * s) & 31;
+                const uint16_t v = HP[H1s.src[s] * RS + c];
+                HP[H1s.dst[s] * RS + c] = v;
+                H1C[c * P + H1s.dst[s]] = v;
+            }
+        }
         wave_sync();
-        // layer 2 and 3: both channel tiles of a position tile share each B operand
-        float fpart = 0.0f;
-        float s2p[2][4], g2p[2][4];
+        // layers 2 and 3, positions as rows: one A operand (8 channels of h1 at
+        // one position) serves both channel tiles
+        float fpart = 0.0f, s2p[2] = {0.0f, 0.0f}, g2p[2] = {0.0f, 0.0f};
+        u32x2 lag[2] = {{0u, 0u}, {0u, 0u}};
+        for (int nt = 0; nt < NT; ++nt) {
+            const int j = nt * 16 + r, jo = nt * 16 + 4 * g4;
+            float vm[4];   // 1 for positions of the ring, 0 for the padding
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
+            for (int v = 0; v < 4; ++v) vm[v] = jo + v < L ? 1.0f : 0.0f;
+            f32x4 z[2] = {{b2s[0], b2s[0], b2s[0], b2s[0]}, {b2s[1], b2s[1], b2s[1], b2s[1]}};
 #pragma unroll
-            for (int v = 0; v < 4; ++v) s2p[mt][v] = g2p[mt][v] = 0.0f;
-        for (int nt = 0; nt < LP / 16; ++nt) {
-            const int j = nt * 16 + r;
-            f32x4 z[2] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
+            for (int t = 0; t < KS; ++t) {
+                const bf16x8 Ah = ld8(HP + (j + t) * RS + 8 * g4);
+                z[0] = mfma32(Ah, ld8(S.W2R + r * WS + t * 32 + 8 * g4), z[0]);
+                z[1] = mfma32(Ah, ld8(S.W2R + (16 + r) * WS + t * 32 + 8 * g4), z[1]);
+            }
+            if (MODE == 1 && nt > 0) {
 #pragma unroll
-            for (int kt = 0; kt < Q / 16; ++kt) {
-                const int t = kt >> 1, cb = (kt & 1) * 16 + 4 * g4;
-                const bf16x4 B = ld4(V.H1P + (j + t) * CH + cb);
-                z[0] = mfma16(ld4(S.W2R + r * Q + kt * 16 + 4 * g4), B, z[0]);
-                z[1] = mfma16(ld4(S.W2R + (16 + r) * Q + kt * 16 + 4 * g4), B, z[1]);
+                for (int mt = 0; mt < 2; ++mt) {
+                    uint16_t* hp = HP + (jo - 14) * RS + mt * 16 + r;
+                    hp[0] = (uint16_t)lag[mt][0];
+                    hp[RS] = (uint16_t)(lag[mt][0] >> 16);
+                    hp[2 * RS] = (uint16_t)lag[mt][1];
+                    hp[3 * RS] = (uint16_t)(lag[mt][1] >> 16);
+                }
             }
 #pragma unroll
-            for (int mt = 0; mt < 2; ++mt)
+            for (int mt = 0; mt < 2; ++mt) {
+                float g2[4];
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int c = mt * 16 + 4 * g4 + v;
-                    uint16_t gb = 0;
-                    if (j < L) {
-                        const float h2 = tanh_fast(z[mt][v] + S.b2[c]);
-                        const float g2 = S.w3s[c] * (1.0f - h2 * h2);
-                        fpart += S.w3s[c] * h2;
-                        s2p[mt][v] += h2;
-                        g2p[mt][v] += g2;
-                        gb = f2bf(g2);
-                        V.G2P[(j + 2) * CH + c] = gb;
-                    }
-                    V.G2C[c * LP + j] = gb;
+                    const float h2 = tanh_fast(z[mt][v]);
+                    const float hv = vm[v] * h2;
+                    g2[v] = vm[v] * w3c[mt] * (1.0f - h2 * h2);
+                    s2p[mt] += hv;
+                    g2p[mt] += g2[v];
                 }
+                if (MODE == 1) {
+                    lag[mt] = u32x2{pk_bf16(g2[0], g2[1]), pk_bf16(g2[2], g2[3])};
+                    *reinterpret_cast<u32x2*>(G2C + (mt * 16 + r) * P + jo) = lag[mt];
+                }
+            }
         }
+        fpart = w3c[0] * s2p[0] + w3c[1] * s2p[1];
         const float f = (float)L * b3 + wave_reduce(fpart, OpSum());
         if (MODE == 0) {
             if (lane == 0) f_out[smp] = f;
             wave_sync();
             continue;
+        }
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+            uint16_t* hp = HP + ((NT - 1) * 16 + 2 + 4 * g4) * RS + mt * 16 + r;
+            hp[0] = (uint16_t)lag[mt][0];
+            hp[RS] = (uint16_t)(lag[mt][0] >> 16);
+            hp[2 * RS] = (uint16_t)lag[mt][1];
+            hp[3 * RS] = (uint16_t)(lag[mt][1] >> 16);
         }
         const float cnt = counts[smp];
         const float zf = f + c0, ez = expf(zf);
@@ -287,64 +412,76 @@ __global__ __launch_bounds__(256) void k_net(const float* __restrict__ theta,
             gloss += (ez - cnt * zf) * inv_n;
         }
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                gW3[mt][v] += delta * s2p[mt][v];
-                gb2[mt][v] += delta * g2p[mt][v];
-            }
+        for (int mt = 0; mt < 2; ++mt) {
+            gW3[mt] += delta * s2p[mt];
+            gb2[mt] += delta * g2p[mt];
+        }
         wave_sync();
-        halo_rows(V.G2P, nullptr, L, P, lane);
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const int c = (lane + 64 * s) & 31;
+            const uint16_t v = G2s.src[s] >= 0 ? HP[G2s.src[s] * RS + c] : (uint16_t)0;
+            HP[G2s.dst[s] * RS + c] = v;
+        }
         wave_sync();
         // weight gradient of layer 2: sum over positions of g2[c][j] h1[c'][j + t - 2]
+        // for c = mt * 16 + 4 g4 + v and c' = h * 16 + r; the five taps of B from one
+        // aligned pair of 8-byte reads
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
+        for (int hm = 0; hm < 4; ++hm) {
+            const int h = hm >> 1, mt = hm & 1;
+            f32x4 d[KS];
 #pragma unroll
-            for (int qt = 0; qt < 10; ++qt) {
-                const int q = qt * 16 + r, t = q >> 5, cp = q & 31;
-                f32x4 d = {0.0f, 0.0f, 0.0f, 0.0f};
-                for (int jt = 0; jt < LP / 16; ++jt) {
-                    const int j0 = jt * 16 + 4 * g4;
-                    const uint16_t* hb = V.H1C + cp * P + j0 + t;
-                    bf16x4 B;
-                    B[0] = (short)hb[0];
-                    B[1] = (short)hb[1];
-                    B[2] = (short)hb[2];
-                    B[3] = (short)hb[3];
-                    d = mfma16(ld4(V.G2C + (mt * 16 + r) * LP + j0), B, d);
-                }
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[mt][qt][v] += delta * d[v];
+            for (int t = 0; t < KS; ++t) d[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            const uint16_t* hrow = H1C + (h * 16 + r) * P + 4 * g4;
+            const uint16_t* grow = G2C + (mt * 16 + r) * P + 4 * g4;
+            for (int jt = 0; jt < NT; ++jt) {
+                const bf16x4 A = ld4(grow + jt * 16);
+                const u32x2 lo = *reinterpret_cast<const u32x2*>(hrow + jt * 16);
+                const u32x2 hi = *reinterpret_cast<const u32x2*>(hrow + jt * 16 + 4);
+                d[0] = mfma16(A, as_bf16x4(lo[0], lo[1]), d[0]);
+                d[1] = mfma16(A, as_bf16x4(__builtin_amdgcn_alignbit(lo[1], lo[0], 16),
+                                           __builtin_amdgcn_alignbit(hi[0], lo[1], 16)), d[1]);
+                d[2] = mfma16(A, as_bf16x4(lo[1], hi[0]), d[2]);
+                d[3] = mfma16(A, as_bf16x4(__builtin_amdgcn_alignbit(hi[0], lo[1], 16),
+                                           __builtin_amdgcn_alignbit(hi[1], hi[0], 16)), d[3]);
+                d[4] = mfma16(A, as_bf16x4(hi[0], hi[1]), d[4]);
             }
-        // input gradient of layer 2, then layer 1 (both channel tiles per B operand)
-        for (int nt = 0; nt < LP / 16; ++nt) {
-            const int j = nt * 16 + r;
+#pragma unroll
+            for (int t = 0; t < KS; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[mt][2 * t + h][v] += delta * d[t][v];
+        }
+        // input gradient of layer 2 and the layer-1 backward, positions as rows
+        for (int nt = 0; nt < NT; ++nt) {
+            const int j = nt * 16 + r, jo = nt * 16 + 4 * g4;
+            float vm[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) vm[v] = jo + v < L ? delta : 0.0f;
             f32x4 d[2] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
 #pragma unroll
-            for (int kt = 0; kt < Q / 16; ++kt) {
-                const int t = kt >> 1, cb = (kt & 1) * 16 + 4 * g4;
-                const bf16x4 B = ld4(V.G2P + (j - t + 4) * CH + cb);
-                d[0] = mfma16(ld4(S.W2T + r * Q + kt * 16 + 4 * g4), B, d[0]);
-                d[1] = mfma16(ld4(S.W2T + (16 + r) * Q + kt * 16 + 4 * g4), B, d[1]);
+            for (int t = 0; t < KS; ++t) {
+                const bf16x8 Ag = ld8(HP + (j - t + 4) * RS + 8 * g4);
+                d[0] = mfma32(Ag, ld8(S.W2T + r * WS + t * 32 + 8 * g4), d[0]);
+                d[1] = mfma32(Ag, ld8(S.W2T + (16 + r) * WS + t * 32 + 8 * g4), d[1]);
             }
-            if (j < L) {
-                float a5[KS];
+            const bf16x4 Aa = l1_operand(ext_window(ext32, j + 2), g4, m0, m1);
+            // inputs a at positions jo + i + t - 2 for tap t = r (B of the W1 gradient)
+            const uint32_t xa = ext_window(ext32, jo + r + 2);
+            const bf16x4 Ba = as_bf16x4((0xBF80BF80u ^ (((xa & 1u) << 15) | ((xa & 2u) << 30))) & ma,
+                                        (0xBF80BF80u ^ (((xa & 4u) << 13) | ((xa & 8u) << 28))) & ma);
 #pragma unroll
-                for (int t = 0; t < KS; ++t) a5[t] = V.sa[j + t];
+            for (int mt = 0; mt < 2; ++mt) {
+                const f32x4 z1 = mfma16(Aa, W1op[mt], f32x4{b1s[mt], b1s[mt], b1s[mt], b1s[mt]});
+                float dz[4];
 #pragma unroll
-                for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int c = mt * 16 + 4 * g4 + v;
-                        float z = S.b1[c];
-#pragma unroll
-                        for (int t = 0; t < KS; ++t) z += S.W1[c * KS + t] * a5[t];
-                        const float h = tanh_fast(z);
-                        const float dz1 = delta * d[mt][v] * (1.0f - h * h);
-                        gb1[mt][v] += dz1;
-#pragma unroll
-                        for (int t = 0; t < KS; ++t) gW1[mt][v][t] += dz1 * a5[t];
-                    }
+                for (int v = 0; v < 4; ++v) {
+                    const float h = tanh_fast(z1[v]);
+                    dz[v] = vm[v] * d[mt][v] * (1.0f - h * h);
+                    gb1[mt] += dz[v];
+                }
+                gW1[mt] = mfma16(as_bf16x4(pk_bf16(dz[0], dz[1]), pk_bf16(dz[2], dz[3])), Ba,
+                                 gW1[mt]);
             }
         }
         wave_sync();
@@ -375,54 +512,79 @@ __global__ __launch_bounds__(256) void k_net(const float* __restrict__ theta,
         out[OFF_W2 + c * Q + cp * KS + t] = sum;
     }
     __syncthreads();
-    // small parameters: lane l of a wave writes its 8 channels x 8 slots
-    // (5 taps of W1, b1, b2, W3) at red[l * 64 + (mt * 4 + v) * 8 + slot] and
-    // its scalars at red[4096 + l * 3 + k]
+    // small parameters: the W1 gradient at red[c * 5 + t] (lanes r < 5), the
+    // per-channel partials of b1, b2 and W3 at red[160 + (k * 4 + g4) * 32 + c]
+    // and the scalars at red[544 + k]
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
+    for (int mt = 0; mt < 2; ++mt) {
+        if (r < KS) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            float* o = red + lane * 64 + (mt * 4 + v) * 8;
-#pragma unroll
-            for (int t = 0; t < KS; ++t) o[t] = gW1[mt][v][t];
-            o[5] = gb1[mt][v];
-            o[6] = gb2[mt][v];
-            o[7] = gW3[mt][v];
+            for (int v = 0; v < 4; ++v) red[(mt * 16 + 4 * g4 + v) * KS + r] = gW1[mt][v];
         }
-    red[4096 + lane * 3 + 0] = gb3;
-    red[4096 + lane * 3 + 1] = gc0;
-    red[4096 + lane * 3 + 2] = gloss;
+        const int c = mt * 16 + r;
+        red[160 + (0 * 4 + g4) * 32 + c] = gb1[mt];
+        red[160 + (1 * 4 + g4) * 32 + c] = gb2[mt];
+        red[160 + (2 * 4 + g4) * 32 + c] = gW3[mt];
+    }
+    if (lane == 0) {
+        red[544] = gb3;
+        red[545] = gc0;
+        red[546] = gloss;
+    }
     __syncthreads();
-    // channel c = mt * 16 + 4 * g4 + v lives in lanes g4 * 16 + r, r = 0..15
-    for (int i = threadIdx.x; i < CH * 8; i += blockDim.x) {
-        const int c = i >> 3, slot = i & 7;
-        const int mt = c >> 4, g = (c >> 2) & 3, v = c & 3;
+    for (int i = threadIdx.x; i < CH * KS + 3 * CH + 3; i += blockDim.x) {
         float sum = 0.0f;
         for (int w = 0; w < nw; ++w) {
             const float* R = (const float*)(smem + kNetShared + (size_t)w * net_wave_bytes(L));
-            for (int rr = 0; rr < 16; ++rr) sum += R[(g * 16 + rr) * 64 + (mt * 4 + v) * 8 + slot];
+            if (i < CH * KS) {
+                sum += R[i];
+            } else if (i < CH * KS + 3 * CH) {
+                const int k = (i - CH * KS) >> 5, c = (i - CH * KS) & 31;
+#pragma unroll
+                for (int g = 0; g < 4; ++g) sum += R[160 + (k * 4 + g) * 32 + c];
+            } else {
+                sum += R[544 + (i - CH * KS - 3 * CH)];
+            }
         }
-        if (slot < KS) out[OFF_W1 + c * KS + slot] = sum;
-        else if (slot == 5) out[OFF_B1 + c] = sum;
-        else if (slot == 6) out[OFF_B2 + c] = sum;
-        else for (int t = 0; t < KS; ++t) out[OFF_W3 + c * KS + t] = sum;
-    }
-    if (threadIdx.x < 3) {
-        float sum = 0.0f;
-        for (int w = 0; w < nw; ++w) {
-            const float* R = (const float*)(smem + kNetShared + (size_t)w * net_wave_bytes(L));
-            sum += R[4096 + threadIdx.x];   // lane 0 of each wave holds the scalars
+        if (i < CH * KS) {
+            out[OFF_W1 + i] = sum;
+        } else if (i < CH * KS + 3 * CH) {
+            const int k = (i - CH * KS) >> 5, c = (i - CH * KS) & 31;
+            if (k == 0) out[OFF_B1 + c] = sum;
+            else if (k == 1) out[OFF_B2 + c] = sum;
+            else
+                for (int t = 0; t < KS; ++t) out[OFF_W3 + c * KS + t] = sum;
+        } else {
+            const int k = i - CH * KS - 3 * CH;
+            out[k == 0 ? OFF_B3 : (k == 1 ? OFF_C0 : kGuideParams)] = sum;
         }
-        out[threadIdx.x == 0 ? OFF_B3 : (threadIdx.x == 1 ? OFF_C0 : kGuideParams)] = sum;
     }
+}
+
+// Adam (Kingma and Ba; beta1 0.9, beta2 0.999, eps 1e-8) on parameter p with
+// gradient g; bc1, bc2 are the bias corrections 1 - beta^step.
+__device__ __forceinline__ void adam_update(float* __restrict__ theta, float* __restrict__ m,
+                                            float* __restrict__ v, int p, float g, float lr,
+                                            float bc1, float bc2)
+{
+    const float mm = 0.9f * m[p] + 0.1f * g;
+    const float vv = 0.999f * v[p] + 0.001f * g * g;
+    m[p] = mm;
+    v[p] = vv;
+    theta[p] -= lr * (mm / bc1) / (sqrtf(vv / bc2) + 1e-8f);
 }
 
 // Sum of the per-block partials: 16 parameters per block, 16 lanes per
 // parameter each summing every 16th block in double precision, then the 16
-// lane sums combined in a fixed order.
+// lane sums combined in a fixed order.  The float gradient then goes to grad
+// (if not null) and, when theta is not null, straight into one Adam step; the
+// loss to `loss` (if not null) and, as a double, added to *loss_sum (if not
+// null) by the one thread that owns it.
 __global__ __launch_bounds__(256) void k_net_reduce(const float* __restrict__ partial, int blocks,
                                                     float* __restrict__ grad,
-                                                    float* __restrict__ loss)
+                                                    float* __restrict__ loss, float* theta,
+                                                    float* m, float* v, float lr, float bc1,
+                                                    float bc2, double* __restrict__ loss_sum)
 {
     __shared__ double s[16][17];
     const int pl = threadIdx.x & 15, part = threadIdx.x >> 4;
@@ -435,8 +597,14 @@ __global__ __launch_bounds__(256) void k_net_reduce(const float* __restrict__ pa
     if (part == 0 && p <= kGuideParams) {
         double t = 0.0;
         for (int k = 0; k < 16; ++k) t += s[pl][k];
-        if (p < kGuideParams) grad[p] = (float)t;
-        else if (loss) *loss = (float)t;
+        const float tf = (float)t;
+        if (p < kGuideParams) {
+            if (grad) grad[p] = tf;
+            if (theta) adam_update(theta, m, v, p, tf, lr, bc1, bc2);
+        } else {
+            if (loss) *loss = tf;
+            if (loss_sum) *loss_sum += (double)tf;
+        }
     }
 }
 
@@ -445,12 +613,7 @@ __global__ void k_adam(float* __restrict__ theta, float* __restrict__ m, float* 
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= kGuideParams) return;
-    const float g = grad[p];
-    const float mm = 0.9f * m[p] + 0.1f * g;
-    const float vv = 0.999f * v[p] + 0.001f * g * g;
-    m[p] = mm;
-    v[p] = vv;
-    theta[p] -= lr * (mm / bc1) / (sqrtf(vv / bc2) + 1e-8f);
+    adam_update(theta, m, v, p, grad[p], lr, bc1, bc2);
 }
 
 // ---------------------------------------------------------------------------
@@ -655,26 +818,66 @@ int guide_blocks(int64_t n) { return (int)(n < kGuideBlocks ? n : kGuideBlocks);
 
 static size_t net_block_smem(int L) { return kNetShared + net_waves(L) * net_wave_bytes(L); }
 
-hipError_t launch_net(int mode, const float* theta, const uint64_t* states, int64_t ld,
-                      const float* counts, int L, int64_t n, float* f_out, float* partial,
-                      float* grad, float* loss, hipStream_t st)
+static void adam_corrections(int step, float* bc1, float* bc2)
+{
+    *bc1 = 1.0f - powf(0.9f, (float)step);
+    *bc2 = 1.0f - powf(0.999f, (float)step);
+}
+
+// Forward (mode 0) or the per-block partial gradients (mode 1); returns the
+// grid used through *blocks_out.
+static hipError_t launch_net_pass(int mode, const float* theta, const uint64_t* states, int64_t ld,
+                                  const float* counts, int L, int64_t n, float* f_out,
+                                  float* partial, int* blocks_out, hipStream_t st)
 {
     const int nw = net_waves(L);
     const int64_t want = (n + nw - 1) / nw;
     const int blocks = (int)(want < 512 ? want : 512);   // <= guide_blocks(n): fits the workspace
     const size_t sm = net_block_smem(L);
-    if (mode == 0) {
+    if (blocks_out) *blocks_out = blocks;
+    if (mode == 0)
         hipLaunchKernelGGL(k_net<0>, dim3(blocks), dim3(64 * nw), sm, st, theta, states, counts,
                            L, n, ld, 1.0f / (float)n, f_out, partial);
-        return hipGetLastError();
-    }
-    hipLaunchKernelGGL(k_net<1>, dim3(blocks), dim3(64 * nw), sm, st, theta, states, counts, L, n,
-                       ld, 1.0f / (float)n, f_out, partial);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_net_reduce, dim3((kGuideParams + 1 + 15) / 16), dim3(256), 0, st,
-                       partial, blocks, grad, loss);
+    else
+        hipLaunchKernelGGL(k_net<1>, dim3(blocks), dim3(64 * nw), sm, st, theta, states, counts,
+                           L, n, ld, 1.0f / (float)n, f_out, partial);
     return hipGetLastError();
+}
+
+static constexpr int kReduceBlocks = (kGuideParams + 1 + 15) / 16;
+
+hipError_t launch_net(int mode, const float* theta, const uint64_t* states, int64_t ld,
+                      const float* counts, int L, int64_t n, float* f_out, float* partial,
+                      float* grad, float* loss, hipStream_t st)
+{
+    int blocks = 0;
+    hipError_t e = launch_net_pass(mode, theta, states, ld, counts, L, n, f_out, partial, &blocks, st);
+    if (e != hipSuccess || mode == 0) return e;
+    hipLaunchKernelGGL(k_net_reduce, dim3(kReduceBlocks), dim3(256), 0, st, partial, blocks, grad,
+                       loss, nullptr, nullptr, nullptr, 0.0f, 1.0f, 1.0f, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_train_epoch(float* theta, float* m, float* v, const uint64_t* states,
+                              int64_t ld, const float* counts, int L, int64_t n, int64_t batch,
+                              int step0, float lr, double* loss_sum, float* partial,
+                              hipStream_t st)
+{
+    int k = 0;
+    for (int64_t a = 0; a < n; a += batch, ++k) {
+        const int64_t nb = (n - a < batch) ? n - a : batch;
+        int blocks = 0;
+        hipError_t e = launch_net_pass(1, theta, states + a, ld, counts + a, L, nb, nullptr,
+                                       partial, &blocks, st);
+        if (e != hipSuccess) return e;
+        float bc1, bc2;
+        adam_corrections(step0 + k + 1, &bc1, &bc2);
+        hipLaunchKernelGGL(k_net_reduce, dim3(kReduceBlocks), dim3(256), 0, st, partial, blocks,
+                           nullptr, nullptr, theta, m, v, lr, bc1, bc2, loss_sum);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t net_set_smem_limit(int L)
@@ -693,8 +896,8 @@ size_t net_smem(int L) { return net_block_smem(L); }
 hipError_t launch_adam(float* theta, float* m, float* v, const float* grad, int step, float lr,
                        hipStream_t st)
 {
-    const float bc1 = 1.0f - powf(0.9f, (float)step);
-    const float bc2 = 1.0f - powf(0.999f, (float)step);
+    float bc1, bc2;
+    adam_corrections(step, &bc1, &bc2);
     hipLaunchKernelGGL(k_adam, dim3((kGuideParams + 255) / 256), dim3(256), 0, st, theta, m, v,
                        grad, lr, bc1, bc2);
     return hipGetLastError();

@@ -21,6 +21,13 @@ hipError_t launch_net(int mode, const float* theta, const uint64_t* states, int6
                       float* grad, float* loss, hipStream_t st);
 hipError_t launch_adam(float* theta, float* m, float* v, const float* grad, int step, float lr,
                        hipStream_t st);
+// minibatches [a, a + batch) of n samples: partial gradients, then reduction
+// fused with Adam (step numbers step0 + 1, ...), minibatch losses added to
+// *loss_sum (partial: guide_blocks(batch) * (kGuideParams + 1) floats)
+hipError_t launch_train_epoch(float* theta, float* m, float* v, const uint64_t* states,
+                              int64_t ld, const float* counts, int L, int64_t n, int64_t batch,
+                              int step0, float lr, double* loss_sum, float* partial,
+                              hipStream_t st);
 hipError_t launch_window_table(const float* theta, float* table, hipStream_t st);
 hipError_t launch_bond_table(const float* H, double gmax, uint32_t* eg, double* G,
                              hipStream_t st);

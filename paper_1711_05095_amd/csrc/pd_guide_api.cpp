@@ -103,6 +103,29 @@ pd_status pdg_adam(float* theta, float* m, float* v, const float* grad, int32_t 
     return gdev(launch_adam(theta, m, v, grad, step, lr, (hipStream_t)hip_stream), "adam launch");
 }
 
+pd_status pdg_train_epoch(float* theta, float* m, float* v, const uint64_t* states, int64_t ld,
+                          const float* counts, int32_t L, int64_t n, int64_t batch, int32_t step0,
+                          float lr, double* loss_sum, void* work, size_t work_bytes,
+                          void* hip_stream)
+{
+    std::string msg = check_batch(states, ld, L, n);
+    if (!msg.empty()) return gfail(PD_EINVAL, msg);
+    if (!theta || !m || !v || !counts || !loss_sum || !work) return gfail(PD_EINVAL, "null pointer");
+    if (batch < 1) return gfail(PD_EINVAL, "batch < 1");
+    if (step0 < 0 || (int64_t)step0 + (n + batch - 1) / batch > INT32_MAX)
+        return gfail(PD_EINVAL, "step0 < 0 or step numbers overflow");
+    if (!(lr > 0.0f) || !std::isfinite(lr)) return gfail(PD_EINVAL, "lr <= 0");
+    if (!aligned256(work)) return gfail(PD_EINVAL, "workspace must be 256-byte aligned");
+    size_t need = 0;
+    pdg_workspace_bytes(batch < n ? batch : n, &need);
+    if (work_bytes < need) return gfail(PD_ENOMEM, "workspace too small");
+    pd_status st = smem_limit(L);
+    if (st != PD_OK) return st;
+    return gdev(launch_train_epoch(theta, m, v, states, ld, counts, L, n, batch, step0, lr,
+                                   loss_sum, (float*)work, (hipStream_t)hip_stream),
+                "training launch");
+}
+
 pd_status pdg_window_table(const float* theta, float* table, void* hip_stream)
 {
     if (!theta || !table) return gfail(PD_EINVAL, "null pointer");

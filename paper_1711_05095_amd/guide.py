@@ -79,19 +79,13 @@ class Trainer:
 
     def epoch(self, states, counts, lr=None):
         """One pass over the samples in minibatches (learning rate `lr`, default
-        the trainer's); returns the mean minibatch loss (synchronises)."""
+        the trainer's), enqueued by the library in one call; returns the mean
+        minibatch loss (synchronises)."""
         lr = self.lr if lr is None else lr
-        n = states.shape[1]
-        total = torch.zeros((), dtype=torch.float64, device=self.theta.device)
-        k = 0
-        for a in range(0, n, self.batch):
-            b = min(n, a + self.batch)
-            gnet.loss_grad(self.theta, states[:, a:b], counts[a:b], self.L, self.grad, self.loss,
-                           self.work)
-            self.steps += 1
-            gnet.adam(self.theta, self.m, self.v, self.grad, self.steps, lr)
-            total += self.loss[0].double()
-            k += 1
+        total = torch.zeros(1, dtype=torch.float64, device=self.theta.device)
+        k = gnet.train_epoch(self.theta, self.m, self.v, states, counts, self.L, self.batch,
+                             self.steps, lr, total, self.work)
+        self.steps += k
         return float(total.item()) / k
 
     def evaluate(self, states, counts):

@@ -15,7 +15,7 @@ PDG_MAX_GMAX = 3.45
 PDG_COND_MIN_L = 26
 PDG_COND_WORK_BYTES = 163840
 
-EXPORTS = ["pdg_workspace_bytes", "pdg_forward", "pdg_loss_grad", "pdg_adam",
+EXPORTS = ["pdg_workspace_bytes", "pdg_forward", "pdg_loss_grad", "pdg_adam", "pdg_train_epoch",
            "pdg_window_table", "pdg_bond_table", "pdg_bond_table_cond", "pdg_last_error"]
 
 _bound = False
@@ -33,6 +33,8 @@ def lib():
             "pdg_loss_grad": [vp, vp, c.c_int64, vp, c.c_int32, c.c_int64, vp, vp, vp, c.c_size_t,
                               vp],
             "pdg_adam": [vp, vp, vp, vp, c.c_int32, c.c_float, vp],
+            "pdg_train_epoch": [vp, vp, vp, vp, c.c_int64, vp, c.c_int32, c.c_int64, c.c_int64,
+                                c.c_int32, c.c_float, vp, vp, c.c_size_t, vp],
             "pdg_window_table": [vp, vp, vp],
             "pdg_bond_table": [vp, c.c_double, vp, vp, vp],
             "pdg_bond_table_cond": [vp, vp, c.c_int64, c.c_int32, c.c_int64, c.c_int32, c.c_double,
@@ -123,6 +125,23 @@ def adam(theta, m, v, grad, step, lr, stream=None):
         _dev(t, torch.float32, PDG_PARAMS, nm)
     _check(lib().pdg_adam(_p(theta), _p(m), _p(v), _p(grad), int(step), float(lr),
                           _stream(stream)))
+
+
+def train_epoch(theta, m, v, states, counts, L, batch, step0, lr, loss_sum, work, stream=None):
+    """Minibatches of `batch` columns, one Adam step each (step numbers
+    step0 + 1, ...); minibatch losses added to loss_sum (float64 CUDA tensor,
+    one entry).  Returns the number of minibatches (steps taken)."""
+    import torch
+    n, ld = _states(states, L)
+    for t, nm in ((theta, "theta"), (m, "m"), (v, "v")):
+        _dev(t, torch.float32, PDG_PARAMS, nm)
+    _dev(counts, torch.float32, n, "counts")
+    _dev(loss_sum, torch.float64, 1, "loss_sum")
+    _dev(work, torch.uint8, None, "work")
+    _check(lib().pdg_train_epoch(_p(theta), _p(m), _p(v), _p(states), ld, _p(counts), L, n,
+                                 int(batch), int(step0), float(lr), _p(loss_sum), _p(work),
+                                 work.numel(), _stream(stream)))
+    return (n + int(batch) - 1) // int(batch)
 
 
 def window_table(theta, table, stream=None):

@@ -61,6 +61,24 @@ def test_guide_host_validation():
     assert b"too small" in lib.pdg_last_error()
     assert lib.pdg_adam(fake, fake, fake, fake, 0, 1e-3, None) == pd.PD_EINVAL
     assert lib.pdg_adam(fake, fake, fake, fake, 1, -1.0, None) == pd.PD_EINVAL
+    W = 1 << 30
+    te = lib.pdg_train_epoch
+    assert te(fake, fake, fake, fake, 10, fake, 20, 10, 0, 0, 1e-3, fake, fake, W,
+              None) == pd.PD_EINVAL                                            # batch < 1
+    assert te(fake, fake, fake, fake, 10, fake, 20, 10, 4, -1, 1e-3, fake, fake, W,
+              None) == pd.PD_EINVAL                                            # step0 < 0
+    assert te(fake, fake, fake, fake, 10, fake, 20, 10, 4, 0, 0.0, fake, fake, W,
+              None) == pd.PD_EINVAL                                            # lr <= 0
+    assert te(fake, fake, fake, fake, 10, fake, 20, 10, 4, 0, 1e-3, None, fake, W,
+              None) == pd.PD_EINVAL                                            # loss_sum
+    assert te(fake, fake, fake, fake, 10, fake, 20, 10, 4, 0, 1e-3, fake, vp(4097), W,
+              None) == pd.PD_EINVAL                                            # misaligned
+    assert te(fake, fake, fake, fake, 10, fake, 4, 10, 4, 0, 1e-3, fake, fake, W,
+              None) == pd.PD_EINVAL                                            # L < 5
+    need = ctypes.c_size_t()
+    assert lib.pdg_workspace_bytes(4, ctypes.byref(need)) == pd.PD_OK
+    assert te(fake, fake, fake, fake, 10, fake, 20, 10, 4, 0, 1e-3, fake, fake,
+              need.value - 1, None) == pd.PD_ENOMEM                            # min(batch, n)
     assert lib.pdg_bond_table(fake, 3.5, fake, None, None) == pd.PD_EINVAL
     assert lib.pdg_bond_table(fake, float("nan"), fake, None, None) == pd.PD_EINVAL
     assert lib.pdg_window_table(None, fake, None) == pd.PD_EINVAL

@@ -191,6 +191,42 @@ def test_gradient_is_additive_over_batches():
     assert np.allclose(out[0], comb, rtol=1e-4, atol=1e-5 * np.max(np.abs(out[0])))
 
 
+def test_train_epoch_equals_gradient_and_adam_steps():
+    """pdg_train_epoch (minibatches enqueued by the library, reduction fused
+    with Adam) gives the same parameters, moments and summed loss, bit for
+    bit, as pdg_loss_grad + pdg_adam called per minibatch, including a short
+    last minibatch and a nonzero starting step."""
+    L, n, batch, step0, lr = 37, 2500, 1024, 5, 3e-3
+    th = theta_for(21)
+    occ = inputs.random_population(L, 15, n, seed=22)
+    counts = np.random.default_rng(23).poisson(1.2, n).astype(np.float32)
+    S, C = states_dev(occ), dev(counts)
+    rng = np.random.default_rng(24)
+    m0 = (rng.standard_normal(gn.PDG_PARAMS) * 1e-3).astype(np.float32)
+    v0 = (rng.random(gn.PDG_PARAMS) * 1e-6).astype(np.float32)
+    work = torch.empty(gn.workspace_bytes(batch), dtype=torch.uint8, device="cuda")
+
+    t1, m1, v1 = dev(th), dev(m0), dev(v0)
+    total = torch.zeros(1, dtype=torch.float64, device="cuda")
+    k = gn.train_epoch(t1, m1, v1, S, C, L, batch, step0, lr, total, work)
+    assert k == 3
+
+    t2, m2, v2 = dev(th), dev(m0), dev(v0)
+    grad = torch.empty(gn.PDG_PARAMS, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    want = 0.0
+    for i, a in enumerate(range(0, n, batch)):
+        b = min(n, a + batch)
+        gn.loss_grad(t2, S[:, a:b], C[a:b], L, grad, loss, work)
+        gn.adam(t2, m2, v2, grad, step0 + i + 1, lr)
+        torch.cuda.synchronize()
+        want += float(loss.item())
+    torch.cuda.synchronize()
+    assert torch.equal(t1, t2) and torch.equal(m1, m2) and torch.equal(v1, v2)
+    assert float(total.item()) == want
+    assert not torch.equal(t1, dev(th))
+
+
 def test_adam_matches_reference():
     rng = np.random.default_rng(5)
     th = rng.normal(size=gn.PDG_PARAMS).astype(np.float32)
