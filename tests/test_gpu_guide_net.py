@@ -13,9 +13,10 @@ must agree to 6 sigma_f (plus 1e-4 for float32 rounding elsewhere); the
 worst-case bound (all eps_i aligned) is some 100x looser and would not
 separate a right answer from a wrong one.  The window table is held to the
 same rule with its own sigma.  Gradients pass through bf16-rounded dz2 and h1
-(the W2 gradient) and dz2 (the h1 adjoint): each parameter group must agree
-to 1e-2 in 2-norm and 2e-2 of its largest entry; a CPU emulation of this
-rounding model gives at most 1.2e-3 on these cases.  Adam and the bond table
+(the W2 gradient), dz2 (the h1 adjoint) and dz1 (the W1 gradient, whose other
+factor, the input +-1, is exact): each parameter group must agree to 1e-2 in
+2-norm and 2e-2 of its largest entry; a CPU emulation of this rounding model
+gives at most 1.2e-3 on these cases.  Adam and the bond table
 are float32 / float64 elementwise and agree to rounding.
 """
 import numpy as np
