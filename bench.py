@@ -42,8 +42,8 @@ PEAK_HBM_GBS = 8000.0
 # keeps this constant equal to that count).  It is the algorithmic work of an
 # event for every variant: the compacting variant's loop adds 8 instructions of
 # round bookkeeping, which count as overhead.
-VALU_PER_EVENT_W2 = 215
-VALU_PER_EVENT_W7 = 344   # the same loop for 400-site states (7 words)
+VALU_PER_EVENT_W2 = 164
+VALU_PER_EVENT_W7 = 287   # the same loop for 400-site states (7 words)
 # HBM bytes the cloning stage must move per clone: ln Ups read (8) by the
 # resample scan, ancestor written (4); the gather of the states is fused into
 # the next dynamical stage's load.

@@ -338,6 +338,7 @@ pd_status pd_create(const pd_params* params, int32_t n, void* d_workspace, size_
         InstDev d;
         std::memset(&d, 0, sizeof d);
         d.L = p.L; d.N = p.N; d.W = words_of(p.L); d.mode = p.weight_mode;
+        for (int k = 0; k < 8; ++k) d.log_poly[k] = ((k & 1) ? -1.0 : 1.0) / (double)(9 - k);
         d.selection = p.selection; d.ntiles = o.ntiles; d.log_cycles = p.log_cycles;
         d.key0 = (uint32_t)p.seed; d.key1 = (uint32_t)(p.seed >> 32);
         d.tag_hi = p.instance << 8;

@@ -21,20 +21,22 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* gptr(T* p)
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
 // 32x32->64 multiplies by the published constants, xor with the Weyl key.
+// Each product is one v_mad_u64_u32 and each three-way xor one v_bitop3_b32
+// (truth table 0x96 = a ^ b ^ c).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                           uint32_t k0, uint32_t k1)
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c0;
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo1 = 0xCD9E8D57u * c2;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
-        c0 = hi1 ^ c1 ^ k0;
-        c1 = lo1;
-        c2 = hi0 ^ c3 ^ k1;
-        c3 = lo0;
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96);
+        c0 = n0;
+        c1 = (uint32_t)p1;
+        c2 = n2;
+        c3 = (uint32_t)p0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -57,7 +59,7 @@ __device__ __forceinline__ double unit_open0(uint32_t a, uint32_t b)
 // 2^-7), ln u = e ln2 - ln c + log1p(r); e*ln2_hi - ln c_hi is exact and
 // log1p(r) is its Taylor series to r^9.  The result is within about one ulp.
 __device__ __forceinline__ double log_unit(double u, const double* __restrict__ tab,
-                                           double ln2_hi, double ln2_lo)
+                                           double ln2_hi, double ln2_lo, const double (&pc)[8])
 {
     const int e0 = __builtin_amdgcn_frexp_exp(u);
     const double f = __builtin_amdgcn_frexp_mant(u);   // [0.5, 1)
@@ -69,17 +71,28 @@ __device__ __forceinline__ double log_unit(double u, const double* __restrict__ 
     const double nlc_hi = tab[4 * i + 1];
     const double nlc_lo = tab[4 * i + 2];
     const double r = fma(m, c, -1.0);
-    double p = 1.0 / 9.0;
-    p = fma(p, r, -1.0 / 8.0);
-    p = fma(p, r, 1.0 / 7.0);
-    p = fma(p, r, -1.0 / 6.0);
-    p = fma(p, r, 1.0 / 5.0);
-    p = fma(p, r, -1.0 / 4.0);
-    p = fma(p, r, 1.0 / 3.0);
-    p = fma(p, r, -0.5);
+    double p = pc[0];
+#pragma unroll
+    for (int k = 1; k < 8; ++k) p = fma(p, r, pc[k]);
     const double l1p = fma(r * r, p, r);
     const double t = fma(e, ln2_hi, nlc_hi);            // exact
     return t + (fma(e, ln2_lo, nlc_lo) + l1p);
+}
+
+// The Taylor coefficients of log1p used by log_unit: 1/9, -1/8, ..., -1/2.
+struct Log1pPoly {
+    double c[8];
+    __device__ __forceinline__ Log1pPoly()
+    {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) c[k] = ((k & 1) ? -1.0 : 1.0) / (double)(9 - k);
+    }
+};
+__device__ __forceinline__ double log_unit(double u, const double* __restrict__ tab,
+                                           double ln2_hi, double ln2_lo)
+{
+    const Log1pPoly P;
+    return log_unit(u, tab, ln2_hi, ln2_lo, P.c);
 }
 
 // floor(((a << 32) | b) * r / 2^64) for r < 2^31: a uniform index in [0, r).
@@ -148,6 +161,50 @@ __device__ __forceinline__ int select_bit(const uint64_t (&m)[W], uint32_t q)
     c = v & 1u;
     if (q >= c) { pos += 1; }
     return base + pos;
+}
+
+// Byte table of select_bit_lut: entry b * 8 + q is the position of the q-th
+// set bit (0-based, ascending) of the byte b for q < popcount(b), else 0.
+__device__ __forceinline__ void fill_select_table(uint8_t* t, int tid, int nthr)
+{
+    for (int e = tid; e < 2048; e += nthr) {
+        const uint32_t b = (uint32_t)e >> 3, q = (uint32_t)e & 7u;
+        uint32_t pos = 0, seen = 0;
+        for (uint32_t i = 0; i < 8; ++i)
+            if ((b >> i) & 1u) {
+                if (seen == q) pos = i;
+                ++seen;
+            }
+        t[e] = (uint8_t)pos;
+    }
+}
+
+// select_bit with the last three halvings (byte to bit) replaced by one
+// lookup in the byte table (fill_select_table, in LDS).
+template <int W>
+__device__ __forceinline__ int select_bit_lut(const uint64_t (&m)[W], uint32_t q,
+                                              const uint8_t* __restrict__ sel)
+{
+    uint64_t word = m[W - 1];
+    int base = (W - 1) * 64;
+    bool found = false;
+#pragma unroll
+    for (int w = 0; w < W - 1; ++w) {
+        const uint32_t c = (uint32_t)__popcll(m[w]);
+        const bool here = !found && q < c;
+        if (here) { word = m[w]; base = w * 64; }
+        if (!found && !here) q -= c;
+        found = found || here;
+    }
+    uint32_t v = (uint32_t)word;
+    uint32_t c = (uint32_t)__popc(v);
+    int pos = 0;
+    if (q >= c) { q -= c; v = (uint32_t)(word >> 32); pos = 32; }
+    c = (uint32_t)__popc(v & 0xFFFFu);
+    if (q >= c) { q -= c; v >>= 16; pos += 16; }
+    c = (uint32_t)__popc(v & 0xFFu);
+    if (q >= c) { q -= c; v >>= 8; pos += 8; }
+    return base + pos + sel[((v & 0xFFu) << 3) | (q & 7u)];
 }
 
 // Word i (0 <= i < W) of the register array, i not known at compile time.

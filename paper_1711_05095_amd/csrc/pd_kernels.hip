@@ -101,17 +101,21 @@ __device__ __forceinline__ void neumaier_add(double& sum, double& comp, double x
 // is the hot loop of the whole method.
 // ---------------------------------------------------------------------------
 struct StepConst {
-    const double* invr;    // LDS: 1 / r for r = 0..kMaxSites
+    const double* invr;    // LDS: 1 / r, or inv_scale / r (SCALED), for r = 0..kMaxSites
     const double* logt;    // LDS: logarithm table
+    const uint8_t* sel;    // LDS: byte table of select_bit_lut
     double inv_scale;      // 1 / rate of one allowed hop
     double dt, ln2_hi, ln2_lo;
+    double poly[8];        // log1p coefficients (uniform)
     uint32_t beta, c3, key0, key1;
     int L, lb;
 };
 
 // Draws and performs events until the interval ends.  Returns true when the
-// clone reached the end of the interval; A gets the final sojourn.
-template <int W>
+// clone reached the end of the interval; A gets the final sojourn.  SCALED:
+// the table holds inv_scale / r, the product the unscaled form forms per
+// event (so both give the same rounding).
+template <int W, bool SCALED = false>
 __device__ __forceinline__ bool one_event(const StepConst& C, uint32_t slot, uint64_t (&x)[W],
                                           uint64_t (&m)[W], int& r, double& tau, double& A,
                                           uint32_t& k, uint32_t& kb)
@@ -119,9 +123,9 @@ __device__ __forceinline__ bool one_event(const StepConst& C, uint32_t slot, uin
     if (r == 0) return true;
     const uint4 y = philox10(k, slot, C.beta, C.c3, C.key0, C.key1);
     ++k;
-    const double E = -log_unit(unit_open0(y.x, y.y), C.logt, C.ln2_hi, C.ln2_lo);
+    const double E = -log_unit(unit_open0(y.x, y.y), C.logt, C.ln2_hi, C.ln2_lo, C.poly);
     // waiting time E / R with R = (rate of one hop) * r
-    const double w = E * (C.inv_scale * C.invr[r]);
+    const double w = E * (SCALED ? C.invr[r] : C.inv_scale * C.invr[r]);
     if (tau + w >= C.dt || k >= 0x80000000u) {
         // k < 2^31 always: the host admits at most 2^24 expected hops per
         // interval; the bound only guarantees that the loop ends
@@ -131,18 +135,22 @@ __device__ __forceinline__ bool one_event(const StepConst& C, uint32_t slot, uin
     A = fma((double)r, w, A);
     tau = tau + w;
     const uint32_t q = mulhi64_small(y.z, y.w, (uint32_t)r);
-    hop<W>(x, select_bit<W>(m, q), C.L);
+    hop<W>(x, select_bit_lut<W>(m, q, C.sel), C.L);
     bond_mask<W>(x, C.lb, m);
     r = popcount_words<W>(m);
     ++kb;
     return false;
 }
 
+// The logarithm table and 1 / r (scaled by the instance's inv_scale when
+// `scaled`: one instance per block).
 __device__ __forceinline__ void load_tables(const InstDev& I, double* s_log, double* s_invr,
-                                            int tid, int nthr)
+                                            int tid, int nthr, int rmax, bool scaled)
 {
     for (int i = tid; i < kLogRows * 4; i += nthr) s_log[i] = gptr(I.log_tab)[i];
-    for (int i = tid; i <= kMaxSites; i += nthr) s_invr[i] = gptr(I.inv_count)[i];
+    const double sc = I.inv_scale;
+    for (int i = tid; i <= rmax; i += nthr)
+        s_invr[i] = scaled ? sc * gptr(I.inv_count)[i] : gptr(I.inv_count)[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -157,16 +165,20 @@ __global__ __launch_bounds__(kTile) void k_step(const InstDev* __restrict__ inst
     __shared__ double s_log[kLogRows * 4];
     __shared__ double s_ell[kTile];
     __shared__ uint64_t s_u[kTile];
+    __shared__ uint8_t s_sel[2048];
 
     const TileDesc td = tiles[tile_base + blockIdx.x];
     const InstDev& I = insts[td.inst];
     const int L = I.L;
-    load_tables(I, s_log, s_invr, threadIdx.x, kTile);
+    load_tables(I, s_log, s_invr, threadIdx.x, kTile, kMaxSites, true);
+    fill_select_table(s_sel, threadIdx.x, kTile);
     __syncthreads();
 
     StepConst C;
-    C.invr = s_invr; C.logt = s_log; C.inv_scale = I.inv_scale;
+    C.invr = s_invr; C.logt = s_log; C.sel = s_sel; C.inv_scale = I.inv_scale;
     C.dt = I.dt; C.ln2_hi = I.ln2_hi; C.ln2_lo = I.ln2_lo;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) C.poly[k] = I.log_poly[k];
     C.beta = (uint32_t)(I.ctl->beta + 1); C.c3 = TAG_DYN | I.tag_hi;
     C.key0 = I.key0; C.key1 = I.key1; C.L = L; C.lb = (L - 1) & 63;
 
@@ -187,7 +199,7 @@ __global__ __launch_bounds__(kTile) void k_step(const InstDev* __restrict__ inst
         int r = popcount_words<W>(m);
         double tau = 0.0, A = 0.0;
         uint32_t k = 0;
-        while (!one_event<W>(C, (uint32_t)j, x, m, r, tau, A, k, kb)) {}
+        while (!one_event<W, true>(C, (uint32_t)j, x, m, r, tau, A, k, kb)) {}
         ell = (I.mode == MODE_MODIFIED) ? -I.c * A : -I.s * (double)kb;
         const int dst = src ^ 1;
 #pragma unroll
@@ -239,17 +251,20 @@ __global__ __launch_bounds__(kTile) void k_step_c(const InstDev* __restrict__ in
     __shared__ double s_ell[kTile];
     __shared__ uint32_t s_kb[kTile];
     __shared__ int s_wc[kTile / 64];
+    __shared__ uint8_t s_sel[2048];
     __shared__ Pack<W> P;
 
     const TileDesc td = tiles[tile_base + blockIdx.x];
     const InstDev& I = insts[td.inst];
     const int L = I.L;
-    for (int i = threadIdx.x; i < kLogRows * 4; i += kTile) s_log[i] = gptr(I.log_tab)[i];
-    for (int i = threadIdx.x; i <= 64 * W; i += kTile) s_invr[i] = gptr(I.inv_count)[i];
+    load_tables(I, s_log, s_invr, threadIdx.x, kTile, 64 * W, true);
+    fill_select_table(s_sel, threadIdx.x, kTile);
 
     StepConst C;
-    C.invr = s_invr; C.logt = s_log; C.inv_scale = I.inv_scale;
+    C.invr = s_invr; C.logt = s_log; C.sel = s_sel; C.inv_scale = I.inv_scale;
     C.dt = I.dt; C.ln2_hi = I.ln2_hi; C.ln2_lo = I.ln2_lo;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) C.poly[k] = I.log_poly[k];
     C.beta = (uint32_t)(I.ctl->beta + 1); C.c3 = TAG_DYN | I.tag_hi;
     C.key0 = I.key0; C.key1 = I.key1; C.L = L; C.lb = (L - 1) & 63;
 
@@ -289,7 +304,7 @@ __global__ __launch_bounds__(kTile) void k_step_c(const InstDev* __restrict__ in
 
     for (;;) {
         for (int it = 0; active && it < budget; ++it) {
-            if (one_event<W>(C, (uint32_t)(td.first + t), x, m, r, tau, A, k, kb)) {
+            if (one_event<W, true>(C, (uint32_t)(td.first + t), x, m, r, tau, A, k, kb)) {
                 const int64_t j = td.first + t;
                 const double ell = directw ? -I.s * (double)kb : -I.c * A;
 #pragma unroll
@@ -360,10 +375,12 @@ __global__ __launch_bounds__(64 * kQWaves) __attribute__((amdgpu_waves_per_eu(OC
     __shared__ double s_invr[kMaxSites + 1];
     __shared__ double s_ell[kQWaves][kTile];
     __shared__ int32_t s_from[kQWaves][kTile];
+    __shared__ uint8_t s_sel[2048];
 
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    load_tables(insts[0], s_log, s_invr, threadIdx.x, 64 * kQWaves);
+    load_tables(insts[0], s_log, s_invr, threadIdx.x, 64 * kQWaves, kMaxSites, false);
+    fill_select_table(s_sel, threadIdx.x, 64 * kQWaves);
     __syncthreads();
 
     double* sell = s_ell[wave];
@@ -386,8 +403,12 @@ __global__ __launch_bounds__(64 * kQWaves) __attribute__((amdgpu_waves_per_eu(OC
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
         StepConst C;
-        C.invr = s_invr; C.logt = s_log; C.inv_scale = I.inv_scale;
+        C.invr = s_invr; C.logt = s_log; C.sel = s_sel; C.inv_scale = I.inv_scale;
         C.dt = I.dt; C.ln2_hi = I.ln2_hi; C.ln2_lo = I.ln2_lo;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) C.poly[k] = I.log_poly[k];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) C.poly[k] = I.log_poly[k];
         C.beta = (uint32_t)(I.ctl->beta + 1); C.c3 = TAG_DYN | I.tag_hi;
         C.key0 = I.key0; C.key1 = I.key1; C.L = L; C.lb = (L - 1) & 63;
         const auto st_src = gptr(I.state[src]);

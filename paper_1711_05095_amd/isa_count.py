@@ -4,7 +4,7 @@ gfx950 assembly of this repository's own kernels.
 The count is the per-event work figure of the ALU roofline in bench.py: one
 event (a Philox4x32-10 block, the waiting time, the choice and execution of a
 hop) executes the loop body once.  The loop is the smallest backward-branch
-region of the kernel that contains the Philox multiplies.
+region of the kernel that contains the Philox multiplies (v_mad_u64_u32).
 
     python -m paper_1711_05095_amd.isa_count [kernel-symbol-prefix]
 """
@@ -55,7 +55,7 @@ def event_loop_valu(body):
         if start >= i:
             continue  # not a backward branch
         region = body[start:i + 1]
-        if not any("v_mul_hi_u32" in r for r in region):
+        if sum("v_mad_u64_u32" in r for r in region) < 10:
             continue
         if best is None or len(region) < len(best):
             best = region
