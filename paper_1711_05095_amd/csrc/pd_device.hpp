@@ -57,7 +57,9 @@ __device__ __forceinline__ double unit_open0(uint32_t a, uint32_t b)
 // accurate to the last bit near u = 1), -ln c split into a part that is a
 // multiple of 2^-42 and a remainder.  With r = m c - 1 (one rounding, |r| <=
 // 2^-7), ln u = e ln2 - ln c + log1p(r); e*ln2_hi - ln c_hi is exact and
-// log1p(r) is its Taylor series to r^9.  The result is within about one ulp.
+// log1p(r) is its Taylor series to r^9, coefficients pc = 1/9, -1/8, ..., -1/2
+// (passed in as values uniform over the wave, so the fma take them from
+// scalar registers).  The result is within about one ulp.
 __device__ __forceinline__ double log_unit(double u, const double* __restrict__ tab,
                                            double ln2_hi, double ln2_lo, const double (&pc)[8])
 {
@@ -77,22 +79,6 @@ __device__ __forceinline__ double log_unit(double u, const double* __restrict__ 
     const double l1p = fma(r * r, p, r);
     const double t = fma(e, ln2_hi, nlc_hi);            // exact
     return t + (fma(e, ln2_lo, nlc_lo) + l1p);
-}
-
-// The Taylor coefficients of log1p used by log_unit: 1/9, -1/8, ..., -1/2.
-struct Log1pPoly {
-    double c[8];
-    __device__ __forceinline__ Log1pPoly()
-    {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) c[k] = ((k & 1) ? -1.0 : 1.0) / (double)(9 - k);
-    }
-};
-__device__ __forceinline__ double log_unit(double u, const double* __restrict__ tab,
-                                           double ln2_hi, double ln2_lo)
-{
-    const Log1pPoly P;
-    return log_unit(u, tab, ln2_hi, ln2_lo, P.c);
 }
 
 // floor(((a << 32) | b) * r / 2^64) for r < 2^31: a uniform index in [0, r).
@@ -131,38 +117,6 @@ __device__ __forceinline__ int popcount_words(const uint64_t (&m)[W])
     return r;
 }
 
-// Position of the q-th set bit (0-based, ascending) of the W-word mask.
-template <int W>
-__device__ __forceinline__ int select_bit(const uint64_t (&m)[W], uint32_t q)
-{
-    uint64_t word = m[W - 1];
-    int base = (W - 1) * 64;
-    bool found = false;
-#pragma unroll
-    for (int w = 0; w < W - 1; ++w) {
-        const uint32_t c = (uint32_t)__popcll(m[w]);
-        const bool here = !found && q < c;
-        if (here) { word = m[w]; base = w * 64; }
-        if (!found && !here) q -= c;
-        found = found || here;
-    }
-    uint32_t v = (uint32_t)word;
-    uint32_t c = (uint32_t)__popc(v);
-    int pos = 0;
-    if (q >= c) { q -= c; v = (uint32_t)(word >> 32); pos = 32; }
-    c = (uint32_t)__popc(v & 0xFFFFu);
-    if (q >= c) { q -= c; v >>= 16; pos += 16; }
-    c = (uint32_t)__popc(v & 0xFFu);
-    if (q >= c) { q -= c; v >>= 8; pos += 8; }
-    c = (uint32_t)__popc(v & 0xFu);
-    if (q >= c) { q -= c; v >>= 4; pos += 4; }
-    c = (uint32_t)__popc(v & 0x3u);
-    if (q >= c) { q -= c; v >>= 2; pos += 2; }
-    c = v & 1u;
-    if (q >= c) { pos += 1; }
-    return base + pos;
-}
-
 // Byte table of select_bit_lut: entry b * 8 + q is the position of the q-th
 // set bit (0-based, ascending) of the byte b for q < popcount(b), else 0.
 __device__ __forceinline__ void fill_select_table(uint8_t* t, int tid, int nthr)
@@ -179,8 +133,9 @@ __device__ __forceinline__ void fill_select_table(uint8_t* t, int tid, int nthr)
     }
 }
 
-// select_bit with the last three halvings (byte to bit) replaced by one
-// lookup in the byte table (fill_select_table, in LDS).
+// Position of the q-th set bit (0-based, ascending) of the W-word mask, for
+// q < its popcount: the word, then halvings down to a byte, then one lookup
+// in the byte table (fill_select_table, in LDS).
 template <int W>
 __device__ __forceinline__ int select_bit_lut(const uint64_t (&m)[W], uint32_t q,
                                               const uint8_t* __restrict__ sel)

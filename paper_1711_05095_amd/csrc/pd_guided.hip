@@ -78,11 +78,13 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
     double* s_ell = (double*)s_raw;
     uint64_t* s_u = (uint64_t*)(s_raw + kTile * sizeof(double));
     __shared__ double s_log[kLogRows * 4];
+    __shared__ uint8_t s_sel[2048];
 
     const TileDesc td = tiles[tile_base + blockIdx.x];
     const InstDev& I = insts[td.inst];
     const int L = I.L;
     for (int i = threadIdx.x; i < kLogRows * 4; i += kTile) s_log[i] = gptr(I.log_tab)[i];
+    fill_select_table(s_sel, threadIdx.x, kTile);
     for (int i = threadIdx.x; i < kGuideCompact; i += kTile) {
         const uint32_t b6 = (i >> 6) & 1u;
         s_eg[i] = gptr(I.guide)[(i & 0x7F) | ((b6 ^ 1u) << 7) | ((i >> 7) << 8)];
@@ -97,6 +99,9 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
     const uint32_t c3 = TAG_GUIDE | I.tag_hi, cp = TAG_GUIDE_PROP | I.tag_hi;
     const double es = I.es, dt = I.dt;
     const uint64_t egmax = I.guide_max;
+    double poly[8];   // log1p coefficients as uniform operands
+#pragma unroll
+    for (int q = 0; q < 8; ++q) poly[q] = I.log_poly[q];
 
     uint32_t kb = 0;
     double ell = -INFINITY;
@@ -118,7 +123,7 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
             ++events;
             const uint4 y = philox10(k, (uint32_t)j, beta, c3, I.key0, I.key1);
             ++k;
-            const double E = -log_unit(unit_open0(y.x, y.y), s_log, I.ln2_hi, I.ln2_lo);
+            const double E = -log_unit(unit_open0(y.x, y.y), s_log, I.ln2_hi, I.ln2_lo, poly);
             const double R = es * ((double)S * 0x1p-16);
             const double w = E / R;
             if (tau + w >= dt) {
@@ -133,7 +138,7 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
             uint32_t e = 0;
             uint32_t qh = y.z, ql = y.w;   // bond word of the first proposal
             for (int tries = 0; tries < (1 << 20); ++tries) {
-                b = select_bit<W>(m, mulhi64_small(qh, ql, (uint32_t)r));
+                b = select_bit_lut<W>(m, mulhi64_small(qh, ql, (uint32_t)r), s_sel);
                 e = s_eg[gidx(ring_bits<W>(x, L, ring_mod(b - 6, L), 13))];
                 const uint4 a = philox10(prop, (uint32_t)j, beta, cp, I.key0, I.key1);
                 ++prop;
@@ -169,7 +174,7 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
             ++kb;
         }
         // sum_jumps ln(eg 2^-16) = ln P + (pexp - 16 kb) ln 2
-        const double G = log_unit(P, s_log, I.ln2_hi, I.ln2_lo) +
+        const double G = log_unit(P, s_log, I.ln2_hi, I.ln2_lo, poly) +
                          (double)(pexp - 16 * (int)kb) * (I.ln2_hi + I.ln2_lo);
         ell = -G - (A - (es * 0x1p-16) * AS);
         const int dst = src ^ 1;
