@@ -51,7 +51,7 @@ RESAMPLE_BYTES_PER_CLONE = 12
 # HBM bytes per launch of the step kernel on this workload, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE runs scaled by a plain 1 GiB copy (factors 2 and
 # 1), valid only for the kernel sources they were taken on (STEP_SOURCES).
-STEP_TRAFFIC = {"bytes": 236.6e6, "kernels_sha1": "1a666f2390b5"}
+STEP_TRAFFIC = {"bytes": 236.3e6, "kernels_sha1": "940f6877857a", "kernel": "k_step_c<2>"}
 STEP_SOURCES = ["pd_kernels.hip", "pd_tile.hpp", "pd_device.hpp", "pd_internal.hpp"]
 
 
@@ -455,9 +455,9 @@ def main():
     achieved = events_per_launch * VALU_PER_EVENT_W2 / step_s
 
     sha = step_sources_sha1()
-    traffic = STEP_TRAFFIC["bytes"] if (sha == STEP_TRAFFIC["kernels_sha1"]
-                                        and a.nc == 100_000) else None
     kname = {0: "k_step<2>", 4: "k_step_c<2>"}.get(tuning["step_variant"], "k_step_q<2>")
+    traffic = STEP_TRAFFIC["bytes"] if (sha == STEP_TRAFFIC["kernels_sha1"] and a.nc == 100_000
+                                        and kname == STEP_TRAFFIC["kernel"]) else None
     out = {
         "metric": "clone-hops/s",
         "value": value,
