@@ -69,18 +69,20 @@ def _conv(x, W):
     return out
 
 
-def forward(theta, occ):
-    """f for each configuration in occ (uint8 [B, L]); also the activations."""
+def forward(theta, occ, h1_bf16=False):
+    """f for each configuration in occ (uint8 [B, L]); also the activations.
+    h1_bf16: layer 2 reads h1 rounded to bfloat16 (a precision model of
+    bf16 matrix operands; the returned h1 is the unrounded one)."""
     P = unpack(theta)
     a = (2.0 * occ.astype(np.float64) - 1.0)[:, None, :]
     h1 = np.tanh(_conv(a, P["W1"][:, None, :]) + P["b1"][None, :, None])
-    h2 = np.tanh(_conv(h1, P["W2"]) + P["b2"][None, :, None])
+    h2 = np.tanh(_conv(bf16(h1) if h1_bf16 else h1, P["W2"]) + P["b2"][None, :, None])
     o = _conv(h2, P["W3"][None, :, :])[:, 0, :] + P["b3"]
     return o.sum(axis=1), dict(a=a, h1=h1, h2=h2)
 
 
-def loss(theta, occ, n):
-    f, _ = forward(theta, occ)
+def loss(theta, occ, n, h1_bf16=False):
+    f, _ = forward(theta, occ, h1_bf16)
     z = f + unpack(theta)["c0"]
     return float(np.mean(np.exp(z) - n * z))
 

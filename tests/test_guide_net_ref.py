@@ -6,7 +6,10 @@
   * f is invariant under rotations of the ring;
   * a network with zero weights gives f = L b3;
   * the distilled bond table equals, for L = 13 rings, the exact log-ratio
-    f(C after the hop) - f(C) averaged over the outer sites (brute force).
+    f(C after the hop) - f(C) averaged over the outer sites (brute force);
+  * the option that rounds h1 to bf16 before layer 2 changes nothing when h1
+    is exactly representable, and otherwise moves f by the first-order effect
+    of the roundings (to second order).
 """
 import numpy as np
 import pytest
@@ -144,3 +147,25 @@ def test_conditional_table_is_the_mean_per_neighbourhood():
         else:
             assert G[v] == G_uni[v]
         assert eg[v] == int(np.rint(65536.0 * np.exp(np.clip(G[v], -0.3, 0.3))))
+
+
+def test_h1_rounding_option():
+    occ = inputs.random_population(24, 11, 6, seed=4)
+    th = gn.init_theta(5)
+    # h1 = tanh(b1) = 0.5 exactly representable: W1 = 0, b1 = atanh(0.5)
+    t0 = th.copy()
+    t0[gn.OFF_W1:gn.OFF_B1] = 0.0
+    t0[gn.OFF_B1:gn.OFF_W2] = np.arctanh(0.5)
+    f0, A0 = gn.forward(t0, occ)
+    assert np.all(A0["h1"] == 0.5)
+    f0r, _ = gn.forward(t0, occ, h1_bf16=True)
+    assert np.array_equal(f0, f0r)
+    # general weights: f(rounded) - f = sum_j (bf16(h1) - h1) df/dh1 + O(u^2)
+    P = gn.unpack(th)
+    f, A = gn.forward(th, occ)
+    fr, _ = gn.forward(th, occ, h1_bf16=True)
+    g_z2 = gn._conv_T(np.ones((6, 1, 24)), P["W3"][None]) * (1 - A["h2"] ** 2)
+    dh1 = gn._conv_T(g_z2, P["W2"])
+    lin = ((gn.bf16(A["h1"]) - A["h1"]) * dh1).sum(axis=(1, 2))
+    assert np.all(np.abs(fr - f) > 0)
+    assert np.allclose(fr - f, lin, rtol=0.05, atol=1e-9)
