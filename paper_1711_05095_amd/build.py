@@ -16,6 +16,9 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
     # explicit fma() only: no contraction of a*b+c, so rounding matches the source
     "-ffp-contract=off",
+    # LDS buffers are read and written through different types (bf16 vectors,
+    # 16- and 32-bit words); their order is the program's, not the types'
+    "-fno-strict-aliasing",
     # no packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]

@@ -290,6 +290,17 @@ __global__ __launch_bounds__(256) void k_net(const float* __restrict__ theta,
         b2s[mt] = S.b2[mt * 16 + r];
         w3c[mt] = S.w3s[mt * 16 + r];
     }
+    // the layer-2 B operands of both passes stay in registers: output channel
+    // mt * 16 + r, tap t, input channels 8 g4 .. 8 g4 + 7 (forward), and the
+    // transposed weights for the input gradient
+    bf16x8 Wf[2][KS], Wb[2][KS];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int t = 0; t < KS; ++t) {
+            Wf[mt][t] = ld8(S.W2R + (mt * 16 + r) * WS + t * 32 + 8 * g4);
+            if (MODE == 1) Wb[mt][t] = ld8(S.W2T + (mt * 16 + r) * WS + t * 32 + 8 * g4);
+        }
 
     // per-lane accumulators over the block's samples: the layer-2 weight
     // gradient for c = mt * 16 + 4 g4 + v and q = qt * 16 + r, the layer-1
@@ -346,31 +357,33 @@ __global__ __launch_bounds__(256) void k_net(const float* __restrict__ theta,
         }
         wave_sync();
         // layers 2 and 3, positions as rows: one A operand (8 channels of h1 at
-        // one position) serves both channel tiles
+        // one position) serves both channel tiles.  Software-pipelined: while
+        // the epilogue of tile nt runs, the products of tile nt+1 are in the
+        // matrix cores and the A operands of tile nt+2 are being read (tiles past
+        // the last are clamped to it and their results dropped).  Tile nt writes
+        // its g2 (position-major, over the h1 rows) at the end of its epilogue:
+        // its rows end at row (nt+1)*16 + 1, which only tile nt+1 reads, and that
+        // read was issued before; LDS operations of a wave complete in order.
         float fpart = 0.0f, s2p[2] = {0.0f, 0.0f}, g2p[2] = {0.0f, 0.0f};
-        u32x2 lag[2] = {{0u, 0u}, {0u, 0u}};
-        for (int nt = 0; nt < NT; ++nt) {
-            const int j = nt * 16 + r, jo = nt * 16 + 4 * g4;
+        auto load_h = [&](bf16x8 (&A)[KS], int nt) {
+            const int row = min(nt, NT - 1) * 16 + r;
+#pragma unroll
+            for (int t = 0; t < KS; ++t) A[t] = ld8(HP + (row + t) * RS + 8 * g4);
+        };
+        auto mm_f = [&](const bf16x8 (&A)[KS], f32x4 (&z)[2]) {
+            z[0] = f32x4{b2s[0], b2s[0], b2s[0], b2s[0]};
+            z[1] = f32x4{b2s[1], b2s[1], b2s[1], b2s[1]};
+#pragma unroll
+            for (int t = 0; t < KS; ++t) {
+                z[0] = mfma32(A[t], Wf[0][t], z[0]);
+                z[1] = mfma32(A[t], Wf[1][t], z[1]);
+            }
+        };
+        auto epi_f = [&](const f32x4 (&z)[2], int nt) {
+            const int jo = nt * 16 + 4 * g4;
             float vm[4];   // 1 for positions of the ring, 0 for the padding
 #pragma unroll
             for (int v = 0; v < 4; ++v) vm[v] = jo + v < L ? 1.0f : 0.0f;
-            f32x4 z[2] = {{b2s[0], b2s[0], b2s[0], b2s[0]}, {b2s[1], b2s[1], b2s[1], b2s[1]}};
-#pragma unroll
-            for (int t = 0; t < KS; ++t) {
-                const bf16x8 Ah = ld8(HP + (j + t) * RS + 8 * g4);
-                z[0] = mfma32(Ah, ld8(S.W2R + r * WS + t * 32 + 8 * g4), z[0]);
-                z[1] = mfma32(Ah, ld8(S.W2R + (16 + r) * WS + t * 32 + 8 * g4), z[1]);
-            }
-            if (MODE == 1 && nt > 0) {
-#pragma unroll
-                for (int mt = 0; mt < 2; ++mt) {
-                    uint16_t* hp = HP + (jo - 14) * RS + mt * 16 + r;
-                    hp[0] = (uint16_t)lag[mt][0];
-                    hp[RS] = (uint16_t)(lag[mt][0] >> 16);
-                    hp[2 * RS] = (uint16_t)lag[mt][1];
-                    hp[3 * RS] = (uint16_t)(lag[mt][1] >> 16);
-                }
-            }
 #pragma unroll
             for (int mt = 0; mt < 2; ++mt) {
                 float g2[4];
@@ -383,8 +396,30 @@ __global__ __launch_bounds__(256) void k_net(const float* __restrict__ theta,
                     g2p[mt] += g2[v];
                 }
                 if (MODE == 1) {
-                    lag[mt] = u32x2{pk_bf16(g2[0], g2[1]), pk_bf16(g2[2], g2[3])};
-                    *reinterpret_cast<u32x2*>(G2C + (mt * 16 + r) * P + jo) = lag[mt];
+                    const u32x2 pk{pk_bf16(g2[0], g2[1]), pk_bf16(g2[2], g2[3])};
+                    *reinterpret_cast<u32x2*>(G2C + (mt * 16 + r) * P + jo) = pk;
+                    uint16_t* hp = HP + (jo + 2) * RS + mt * 16 + r;
+                    hp[0] = (uint16_t)pk[0];
+                    hp[RS] = (uint16_t)(pk[0] >> 16);
+                    hp[2 * RS] = (uint16_t)pk[1];
+                    hp[3 * RS] = (uint16_t)(pk[1] >> 16);
+                }
+            }
+        };
+        {
+            bf16x8 A0[KS], A1[KS];
+            f32x4 zc[2], zn[2];
+            load_h(A0, 0);
+            load_h(A1, 1);
+            mm_f(A0, zc);
+            for (int nt = 0; nt < NT; nt += 2) {
+                mm_f(A1, zn);          // tile nt+1
+                load_h(A0, nt + 2);
+                epi_f(zc, nt);
+                if (nt + 1 < NT) {
+                    mm_f(A0, zc);      // tile nt+2
+                    load_h(A1, nt + 3);
+                    epi_f(zn, nt + 1);
                 }
             }
         }
@@ -394,14 +429,6 @@ __global__ __launch_bounds__(256) void k_net(const float* __restrict__ theta,
             if (lane == 0) f_out[smp] = f;
             wave_sync();
             continue;
-        }
-#pragma unroll
-        for (int mt = 0; mt < 2; ++mt) {
-            uint16_t* hp = HP + ((NT - 1) * 16 + 2 + 4 * g4) * RS + mt * 16 + r;
-            hp[0] = (uint16_t)lag[mt][0];
-            hp[RS] = (uint16_t)(lag[mt][0] >> 16);
-            hp[2 * RS] = (uint16_t)lag[mt][1];
-            hp[3 * RS] = (uint16_t)(lag[mt][1] >> 16);
         }
         const float cnt = counts[smp];
         const float zf = f + c0, ez = expf(zf);
@@ -452,36 +479,64 @@ __global__ __launch_bounds__(256) void k_net(const float* __restrict__ theta,
 #pragma unroll
                 for (int v = 0; v < 4; ++v) acc[mt][2 * t + h][v] += delta * d[t][v];
         }
-        // input gradient of layer 2 and the layer-1 backward, positions as rows
-        for (int nt = 0; nt < NT; ++nt) {
-            const int j = nt * 16 + r, jo = nt * 16 + 4 * g4;
+        // input gradient of layer 2 and the layer-1 backward, positions as rows,
+        // pipelined as the forward pass (this pass only reads the arrays)
+        auto load_g = [&](bf16x8 (&A)[KS], int nt) {
+            const int row = min(nt, NT - 1) * 16 + r;
+#pragma unroll
+            for (int t = 0; t < KS; ++t) A[t] = ld8(HP + (row - t + 4) * RS + 8 * g4);
+        };
+        auto mm_b = [&](const bf16x8 (&A)[KS], int nt, f32x4 (&d)[2], f32x4 (&z1)[2]) {
+            d[0] = d[1] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int t = 0; t < KS; ++t) {
+                d[0] = mfma32(A[t], Wb[0][t], d[0]);
+                d[1] = mfma32(A[t], Wb[1][t], d[1]);
+            }
+            // layer-1 pre-activations again, on the matrix cores
+            const int j = min(nt, NT - 1) * 16 + r;
+            const bf16x4 Aa = l1_operand(ext_window(ext32, j + 2), g4, m0, m1);
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt)
+                z1[mt] = mfma16(Aa, W1op[mt], f32x4{b1s[mt], b1s[mt], b1s[mt], b1s[mt]});
+        };
+        auto epi_b = [&](const f32x4 (&d)[2], const f32x4 (&z1)[2], int nt) {
+            const int jo = nt * 16 + 4 * g4;
             float vm[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) vm[v] = jo + v < L ? delta : 0.0f;
-            f32x4 d[2] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
-#pragma unroll
-            for (int t = 0; t < KS; ++t) {
-                const bf16x8 Ag = ld8(HP + (j - t + 4) * RS + 8 * g4);
-                d[0] = mfma32(Ag, ld8(S.W2T + r * WS + t * 32 + 8 * g4), d[0]);
-                d[1] = mfma32(Ag, ld8(S.W2T + (16 + r) * WS + t * 32 + 8 * g4), d[1]);
-            }
-            const bf16x4 Aa = l1_operand(ext_window(ext32, j + 2), g4, m0, m1);
             // inputs a at positions jo + i + t - 2 for tap t = r (B of the W1 gradient)
             const uint32_t xa = ext_window(ext32, jo + r + 2);
             const bf16x4 Ba = as_bf16x4((0xBF80BF80u ^ (((xa & 1u) << 15) | ((xa & 2u) << 30))) & ma,
                                         (0xBF80BF80u ^ (((xa & 4u) << 13) | ((xa & 8u) << 28))) & ma);
 #pragma unroll
             for (int mt = 0; mt < 2; ++mt) {
-                const f32x4 z1 = mfma16(Aa, W1op[mt], f32x4{b1s[mt], b1s[mt], b1s[mt], b1s[mt]});
                 float dz[4];
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const float h = tanh_fast(z1[v]);
+                    const float h = tanh_fast(z1[mt][v]);
                     dz[v] = vm[v] * d[mt][v] * (1.0f - h * h);
                     gb1[mt] += dz[v];
                 }
                 gW1[mt] = mfma16(as_bf16x4(pk_bf16(dz[0], dz[1]), pk_bf16(dz[2], dz[3])), Ba,
                                  gW1[mt]);
+            }
+        };
+        {
+            bf16x8 A0[KS], A1[KS];
+            f32x4 dc[2], dn[2], zc[2], zn[2];
+            load_g(A0, 0);
+            load_g(A1, 1);
+            mm_b(A0, 0, dc, zc);
+            for (int nt = 0; nt < NT; nt += 2) {
+                mm_b(A1, nt + 1, dn, zn);      // tile nt+1
+                load_g(A0, nt + 2);
+                epi_b(dc, zc, nt);
+                if (nt + 1 < NT) {
+                    mm_b(A0, nt + 2, dc, zc);  // tile nt+2
+                    load_g(A1, nt + 3);
+                    epi_b(dn, zn, nt + 1);
+                }
             }
         }
         wave_sync();
