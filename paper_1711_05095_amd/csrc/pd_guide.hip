@@ -77,7 +77,8 @@ __host__ __device__ inline int net_lp(int L) { return (L + 15) / 16 * 16; }
 // The inputs a = 2 n - 1 of a sample as a circular bit string: bit i is
 // site (i - 4) mod L, so that the 5-site window of layer 1 at row R (site
 // R - 2) is bits R .. R + 4.  Rows up to LP + 1 are evaluated, each reading
-// the 32-bit window at its row.
+// the 32-bit window at its row, and the W1 gradient reads windows from rows up
+// to LP + 13 (two 32-bit words from word R / 32).
 __host__ __device__ inline int net_ext_words(int L)
 {
     return (32 * (((net_lp(L) + 13) >> 5) + 2) + 63) / 64;
@@ -190,19 +191,25 @@ struct HaloSlots {
 // sharing the weights.
 //
 // Layer 1 (1 -> 32, K = 5 padded to 16) and layer 2 (32 -> 32, K = 160) run
-// on the matrix cores, channels as the rows of the product and positions as
-// its columns: each lane ends with 4 consecutive channels of one position.
-// The layer-2 contraction index is taken tap-major, q = t * 32 + c', so that
-// one 16x16x32 step covers one tap: its B operand is 8 consecutive channels
-// of one position, a 16-byte read of the position-major array.  The
+// on the matrix cores with positions as the rows of each product and channels
+// as its columns: a lane ends with one channel at 4 consecutive positions, so
+// per-channel sums take one register per channel tile and the W1 gradient is
+// one more product (bf16 dz1 against the exact +-1 inputs).  The layer-2
+// contraction index is taken tap-major, q = t * 32 + c', so that one 16x16x32
+// step covers one tap: its A operand is 8 consecutive channels of h1 (or g2)
+// at one position, a 16-byte read of the position-major array, and its B
+// operand (the weights) stays in registers for the whole kernel.  The
 // weight-gradient pass contracts over positions (16x16x16) and reads the
-// channel-major copies; the tap shift of its B operand is taken from two
+// channel-major copies; the tap shift of its B operand is formed from two
 // aligned 8-byte reads with byte alignment, all five taps from one pair.
 //
-// The position-major array holds h1 during the forward pass and g2 after it:
-// the g2 of a position tile is written one tile late, once the next tile has
-// read the h1 rows they share.  The scalar delta = d loss / d f of a sample is
-// applied after the matrix products (in float32): the products run on
+// The two layer-2 passes are software-pipelined over position tiles (A
+// operands read a tile ahead, the products of the next tile in flight during
+// the epilogue of the current one).  The position-major array holds h1 during
+// the forward pass and g2 after it: each tile writes its g2 at the end of its
+// epilogue, after the reads of the next tile, the only one that shares rows
+// with it, were issued.  The scalar delta = d loss / d f of a sample is applied
+// after the matrix products (in float32): the products run on
 // g2 = w3s (1 - h2^2) and the results are scaled by delta.  Layer-1
 // activations are recomputed on the matrix cores where 1 - h1^2 is needed.
 // ---------------------------------------------------------------------------
