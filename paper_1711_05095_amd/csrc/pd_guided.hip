@@ -154,13 +154,19 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
                 // bits o..o+12 of the 26 sites from b-12, o = 0..13
                 const uint32_t win0 = ring_bits<W>(x, L, b >= 12 ? b - 12 : b - 12 + L, 26);
                 const uint32_t win1 = win0 ^ (3u << 12);
+                // bit i: sites i and i+1 of the window differ (the bond is a hop)
+                const uint32_t al0 = win0 ^ (win0 >> 1), al1 = win1 ^ (win1 >> 1);
                 uint64_t add = 0, sub = 0;
+                // branch-free: every neighbourhood's entry is read (any 13-bit u
+                // has a compact index) and masked by its bond's bit
 #pragma unroll
                 for (int o = 0; o < 14; ++o) {
                     const uint32_t u0 = (win0 >> o) & 0x1FFFu;
                     const uint32_t u1 = (win1 >> o) & 0x1FFFu;
-                    if (bond_allowed(u0)) sub += s_eg[gidx(u0)];
-                    if (bond_allowed(u1)) add += s_eg[gidx(u1)];
+                    const uint32_t k0 = (uint32_t)__builtin_amdgcn_sbfe((int)al0, o + 6, 1);
+                    const uint32_t k1 = (uint32_t)__builtin_amdgcn_sbfe((int)al1, o + 6, 1);
+                    sub += s_eg[gidx(u0)] & k0;
+                    add += s_eg[gidx(u1)] & k1;
                 }
                 hop<W>(x, b, L);
                 bond_mask<W>(x, lb, m);
