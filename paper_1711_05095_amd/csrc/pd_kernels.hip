@@ -407,8 +407,6 @@ __global__ __launch_bounds__(64 * kQWaves) __attribute__((amdgpu_waves_per_eu(OC
         C.dt = I.dt; C.ln2_hi = I.ln2_hi; C.ln2_lo = I.ln2_lo;
 #pragma unroll
         for (int k = 0; k < 8; ++k) C.poly[k] = I.log_poly[k];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) C.poly[k] = I.log_poly[k];
         C.beta = (uint32_t)(I.ctl->beta + 1); C.c3 = TAG_DYN | I.tag_hi;
         C.key0 = I.key0; C.key1 = I.key1; C.L = L; C.lb = (L - 1) & 63;
         const auto st_src = gptr(I.state[src]);
