@@ -232,8 +232,9 @@ typedef struct {
                              events in sixteenths of the expected number per
                              clone (later rounds: 0.15 of it) */
     int32_t graph_cycles; /* cycles per captured graph in pd_run (even, 0: no graph) */
-    int32_t scan_tiles;   /* tiles of 256 clones per block of the cloning stage: 1, 2, 4
-                             or 8 (0 means 1) */
+    int32_t scan_tiles;   /* tiles of 256 clones per wave of the cloning stage: 1, 2, 4
+                             or 8 (0 means 1); a wave loads them all before it
+                             scans the first */
 } pd_tuning;
 
 /* A new context starts with {step_variant 4, refill 13, graph_cycles 16, scan_tiles 1}.

@@ -339,6 +339,11 @@ pd_status pd_create(const pd_params* params, int32_t n, void* d_workspace, size_
         std::memset(&d, 0, sizeof d);
         d.L = p.L; d.N = p.N; d.W = words_of(p.L); d.mode = p.weight_mode;
         for (int k = 0; k < 8; ++k) d.log_poly[k] = ((k & 1) ? -1.0 : 1.0) / (double)(9 - k);
+        for (int k = 0; k < 14; ++k) {
+            long double f = 1.0L;
+            for (int q = 2; q <= 13 - k; ++q) f *= (long double)q;
+            d.exp_poly[k] = (double)(1.0L / f);
+        }
         d.selection = p.selection; d.ntiles = o.ntiles; d.log_cycles = p.log_cycles;
         d.key0 = (uint32_t)p.seed; d.key1 = (uint32_t)(p.seed >> 32);
         d.tag_hi = p.instance << 8;

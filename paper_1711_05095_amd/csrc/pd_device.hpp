@@ -81,6 +81,25 @@ __device__ __forceinline__ double log_unit(double u, const double* __restrict__ 
     return t + (fma(e, ln2_lo, nlc_lo) + l1p);
 }
 
+// e^x for x <= 0 (Cody and Waite's reduction): x = k ln2 + r with k the
+// integer nearest x / ln2 and |r| <= ln2 / 2; k ln2_hi is exact (ln2_hi is a
+// multiple of 2^-42 and |k| < 2^11), e^r is its Taylor series to r^13
+// (coefficients pc = 1/13!, ..., 1/1!, 1, uniform over the wave so the fma
+// take them from scalar registers; the truncation is below 2^-56 relative) and
+// 2^k is applied exactly by ldexp.  Arguments below -1000 are taken as -1000:
+// the result is zero either way.
+__device__ __forceinline__ double exp_nonpos(double x, double ln2_hi, double ln2_lo,
+                                             const double (&pc)[14])
+{
+    x = fmax(x, -1000.0);
+    const double k = rint(x * 1.4426950408889634);
+    const double r = fma(-k, ln2_lo, fma(-k, ln2_hi, x));
+    double p = pc[0];
+#pragma unroll
+    for (int i = 1; i < 14; ++i) p = fma(p, r, pc[i]);
+    return ldexp(p, (int)k);
+}
+
 // floor(((a << 32) | b) * r / 2^64) for r < 2^31: a uniform index in [0, r).
 __device__ __forceinline__ uint32_t mulhi64_small(uint32_t a, uint32_t b, uint32_t r)
 {

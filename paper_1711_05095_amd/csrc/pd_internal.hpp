@@ -60,6 +60,7 @@ struct InstDev {
     double ln2_hi, ln2_lo; // ln 2 = ln2_hi (a multiple of 2^-42) + ln2_lo
     double log_poly[8];    // 1/9, -1/8, ..., -1/2: Taylor coefficients of log1p (uniform
                            // operands, so the polynomial's fma take them from SGPRs)
+    double exp_poly[14];   // 1/13!, 1/12!, ..., 1/1!, 1: Taylor coefficients of exp (uniform)
     InstCtl* ctl;
     uint32_t* next_tile;   // work counters of the persistent step launches
 };

@@ -619,65 +619,114 @@ __global__ __launch_bounds__(kTile) void k_prefix(const InstDev* __restrict__ in
 // ---------------------------------------------------------------------------
 
 // #{ j in [0, Nc) : j + d < y }, exactly: y - j is exact whenever it lies in
-// [0, 1), so the test fl(y - j) > d decides j + d < y without error.
-__device__ __forceinline__ int64_t count_points_below(double y, double d, int64_t Nc)
+// [0, 1), so the test fl(y - j) > d decides j + d < y without error.  Slots
+// fit in 31 bits (Nc < 2^31).
+__device__ __forceinline__ int count_points_below(double y, double d, int Nc)
 {
-    double c = ceil(y - d);
-    int64_t m = (c <= 0.0) ? 0 : (c >= (double)Nc ? Nc : (int64_t)c);
+    int m = (int)fmin(fmax(ceil(y - d), 0.0), (double)Nc);
     while (m > 0 && !((y - (double)(m - 1)) > d)) --m;
     while (m < Nc && ((y - (double)m) > d)) ++m;
     return m;
 }
 
-// Each block takes TPB consecutive tiles of the step order, one after the
-// other (the scan tiling the autotuner chooses; the per-tile arithmetic and so
-// every result is the same for any TPB).
-template <int TPB>
+// One wave per tile of 256 clones: lane l holds clones 4l .. 4l+3 of the tile,
+// sums their weights in order, and a wave scan of the lane totals carries the
+// sum across lanes, so the tile needs no block barrier.  A wave takes TPW
+// consecutive tiles of the step order and loads all of them before it works on
+// the first, so their memory latencies overlap (the tiling the autotuner
+// chooses; the per-tile arithmetic and so every result is the same for any
+// TPW).  The interval ends are y_k = C_k (Nc / T) with one quotient per tile,
+// so the end of a tile and the start of the next are the same number.
+template <int TPW>
 __global__ __launch_bounds__(kTile) void k_resample(const InstDev* __restrict__ insts,
                                                     const TileDesc* __restrict__ tiles,
                                                     int ntiles)
 {
-    __shared__ double s_d[kTile / 64];
-    __shared__ int64_t s_hi[kTile];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (kTile / 64) +
+                                                          (threadIdx.x >> 6)));
+    const int t0 = wave * TPW;
+    if (t0 >= ntiles) return;   // uniform over the wave; no barrier follows
 
+    TileDesc td[TPW];
+    double e[TPW][4];
 #pragma unroll
-    for (int tb = 0; tb < TPB; ++tb) {
-    const int tix = blockIdx.x * TPB + tb;
-    if (TPB > 1 && tix >= ntiles) break;
-    const TileDesc td = tiles[tix];
-    const InstDev& I = insts[td.inst];
-    const int tid = threadIdx.x;
-    const bool valid = tid < td.count;
-    const int64_t k = td.first + tid;
-    const int64_t Nc = I.Nc;
-    const double Ncd = (double)Nc;
-    const double M = I.ctl->lmax;
-    const int b = td.tile;
-    const double off0 = I.tile_off[b];
-    const double off1 = I.tile_off[b + 1];
-    const double T = I.tile_off[I.ntiles];
-    const double d = I.ctl->d_eq;   // k_prefix drew it for this interval
-
-    const double w = valid ? exp(gptr(I.ell)[k] - M) : 0.0;
-    double tot;
-    double incl = block_scan_incl(w, OpSum(), s_d, tot);
-    incl = block_scan_incl(incl, OpMax(), s_d, tot);  // non-decreasing in k
-    const bool last = (tid == td.count - 1);
-    const double Ck = last ? off1 : fmin(off0 + incl, off1);
-    int64_t hi = count_points_below((Ck * Ncd) / T, d, Nc);
-    if (k == Nc - 1) hi = Nc;
-    s_hi[tid] = hi;
-    __syncthreads();
-    if (valid) {
-        if (I.ykey) I.ykey[k] = (Ck * Ncd) / T;
-        if (I.selection == SEL_EQ) {
-            const int64_t lo =
-                (tid == 0) ? count_points_below((off0 * Ncd) / T, d, Nc) : s_hi[tid - 1];
-            const auto anc = gptr(I.anc);
-            for (int64_t jj = lo; jj < hi; ++jj) anc[jj] = (int32_t)k;
+    for (int t = 0; t < TPW; ++t) td[t] = tiles[min(t0 + t, ntiles - 1)];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+        const InstDev& I = insts[td[t].inst];
+        const int first = 4 * lane;
+        const auto ell = gptr(I.ell) + td[t].first + first;
+        if (first + 3 < td[t].count) {
+            typedef double f64x2 __attribute__((ext_vector_type(2)));
+            const f64x2 a = *(const __attribute__((address_space(1))) f64x2*)(ell);
+            const f64x2 b = *(const __attribute__((address_space(1))) f64x2*)(ell + 2);
+            e[t][0] = a.x; e[t][1] = a.y; e[t][2] = b.x; e[t][3] = b.y;
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) e[t][i] = (first + i < td[t].count) ? ell[i] : -INFINITY;
         }
     }
-    if (TPB > 1) __syncthreads();   // s_hi and s_d are reused by the next tile
+
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+        if (t0 + t >= ntiles) break;
+        const InstDev& I = insts[td[t].inst];
+        const int count = td[t].count;
+        const int k0 = td[t].first + 4 * lane;   // first of the lane's clones
+        const int Nc = (int)I.Nc;
+        const double M = I.ctl->lmax;
+        const int b = td[t].tile;
+        const double off0 = I.tile_off[b];
+        const double off1 = I.tile_off[b + 1];
+        const double sN = (double)Nc / I.tile_off[I.ntiles];   // Nc / T
+        const double d = I.ctl->d_eq;   // k_prefix drew it for this interval
+        double pc[14];
+#pragma unroll
+        for (int q = 0; q < 14; ++q) pc[q] = I.exp_poly[q];
+
+        // weights and their running sum over the lane's four clones
+        double c[4];
+        double run = 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double w = exp_nonpos(e[t][i] - M, I.ln2_hi, I.ln2_lo, pc);
+            run += (4 * lane + i < count) ? w : 0.0;
+            c[i] = run;
+        }
+        // (every lane takes part in each shuffle; the lane-0 case is a select
+        // after it, never a condition around it)
+        const double incl = wave_scan_incl(run, OpSum());
+        const double up = __shfl_up(incl, 1, 64);
+        const double base = lane ? up : 0.0;
+        const double top = base + c[3];
+        // non-decreasing over the tile: a lane starts no lower than the end of
+        // every lane before it (the scan's rounding order differs from the
+        // lanes' own)
+        const double pmax = wave_scan_incl(top, OpMax());
+        const double pup = __shfl_up(pmax, 1, 64);
+        const double floor_ = lane ? pup : -INFINITY;
+        int hi[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double v = fmax(base + c[i], floor_);
+            const bool last = (4 * lane + i == count - 1);
+            const double Ck = last ? off1 : fmin(off0 + v, off1);
+            const double y = Ck * sN;
+            hi[i] = (k0 + i == Nc - 1) ? Nc : count_points_below(y, d, Nc);
+            if (I.ykey && 4 * lane + i < count) gptr(I.ykey)[k0 + i] = y;
+        }
+        if (I.selection == SEL_EQ) {
+            const int prev = __shfl_up(hi[3], 1, 64);
+            int lo = lane ? prev : count_points_below(off0 * sN, d, Nc);
+            const auto anc = gptr(I.anc);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (4 * lane + i < count)
+                    for (int jj = lo; jj < hi[i]; ++jj) anc[jj] = k0 + i;
+                lo = hi[i];
+            }
+        }
     }
 }
 
@@ -874,7 +923,8 @@ hipError_t launch_prefix(const InstDev* insts, int n_inst, hipStream_t st)
 hipError_t launch_resample(const InstDev* insts, const TileDesc* tiles, int ntiles, int tpb,
                            hipStream_t st)
 {
-    const int blocks = (ntiles + tpb - 1) / tpb;
+    const int waves = (ntiles + tpb - 1) / tpb;
+    const int blocks = (waves + kTile / 64 - 1) / (kTile / 64);
     switch (tpb) {
         case 1: hipLaunchKernelGGL(k_resample<1>, dim3(blocks), dim3(kTile), 0, st, insts, tiles, ntiles); break;
         case 2: hipLaunchKernelGGL(k_resample<2>, dim3(blocks), dim3(kTile), 0, st, insts, tiles, ntiles); break;
