@@ -264,6 +264,35 @@ __device__ __forceinline__ T wave_scan_incl(T v, Op op)
     return v;
 }
 
+// One DPP move of a double (both halves); lanes without a source, and rows
+// that ROWS leaves out, get id.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double v, double id)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(v), o = (uint64_t)__double_as_longlong(id);
+    const int lo = __builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)u, CTRL, ROWS,
+                                               0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32), (int)(uint32_t)(u >> 32),
+                                               CTRL, ROWS, 0xF, false);
+    return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+// Inclusive wave64 scan of doubles on DPP (all 64 lanes active; id is the
+// identity of op): shifts by 1, 2, 4 and 8 lanes within each row of 16, then
+// rows 1 and 3 take lane 15 and 47 of their left neighbour row, then rows 2
+// and 3 take lane 31.  The association is fixed, so the result is too.
+template <class Op>
+__device__ __forceinline__ double wave_scan_dpp(double v, Op op, double id)
+{
+    v = op(v, dpp_f64<0x111, 0xF>(v, id));   // row_shr:1
+    v = op(v, dpp_f64<0x112, 0xF>(v, id));   // row_shr:2
+    v = op(v, dpp_f64<0x114, 0xF>(v, id));   // row_shr:4
+    v = op(v, dpp_f64<0x118, 0xF>(v, id));   // row_shr:8
+    v = op(v, dpp_f64<0x142, 0xA>(v, id));   // row_bcast:15 into rows 1, 3
+    v = op(v, dpp_f64<0x143, 0xC>(v, id));   // row_bcast:31 into rows 2, 3
+    return v;
+}
+
 // Block-wide reduction; every thread gets the result.  `sh` holds kTile/64 Ts.
 template <class T, class Op>
 __device__ __forceinline__ T block_reduce(T v, Op op, T* sh)

@@ -619,14 +619,15 @@ __global__ __launch_bounds__(kTile) void k_prefix(const InstDev* __restrict__ in
 // ---------------------------------------------------------------------------
 
 // #{ j in [0, Nc) : j + d < y }, exactly: y - j is exact whenever it lies in
-// [0, 1), so the test fl(y - j) > d decides j + d < y without error.  Slots
-// fit in 31 bits (Nc < 2^31).
-__device__ __forceinline__ int count_points_below(double y, double d, int Nc)
+// [0, 1), so the test fl(y - j) > d decides j + d < y without error.  The
+// count is kept as a double (integers below 2^31 are exact) until it is
+// returned.
+__device__ __forceinline__ int count_points_below(double y, double d, double Ncd)
 {
-    int m = (int)fmin(fmax(ceil(y - d), 0.0), (double)Nc);
-    while (m > 0 && !((y - (double)(m - 1)) > d)) --m;
-    while (m < Nc && ((y - (double)m) > d)) ++m;
-    return m;
+    double m = fmin(fmax(ceil(y - d), 0.0), Ncd);
+    while (m > 0.0 && !((y - (m - 1.0)) > d)) m -= 1.0;
+    while (m < Ncd && ((y - m) > d)) m += 1.0;
+    return (int)m;
 }
 
 // One wave per tile of 256 clones: lane l holds clones 4l .. 4l+3 of the tile,
@@ -675,11 +676,12 @@ __global__ __launch_bounds__(kTile) void k_resample(const InstDev* __restrict__ 
         const int count = td[t].count;
         const int k0 = td[t].first + 4 * lane;   // first of the lane's clones
         const int Nc = (int)I.Nc;
+        const double Ncd = (double)Nc;
         const double M = I.ctl->lmax;
         const int b = td[t].tile;
         const double off0 = I.tile_off[b];
         const double off1 = I.tile_off[b + 1];
-        const double sN = (double)Nc / I.tile_off[I.ntiles];   // Nc / T
+        const double sN = Ncd / I.tile_off[I.ntiles];   // Nc / T
         const double d = I.ctl->d_eq;   // k_prefix drew it for this interval
         double pc[14];
 #pragma unroll
@@ -696,14 +698,14 @@ __global__ __launch_bounds__(kTile) void k_resample(const InstDev* __restrict__ 
         }
         // (every lane takes part in each shuffle; the lane-0 case is a select
         // after it, never a condition around it)
-        const double incl = wave_scan_incl(run, OpSum());
+        const double incl = wave_scan_dpp(run, OpSum(), 0.0);
         const double up = __shfl_up(incl, 1, 64);
         const double base = lane ? up : 0.0;
         const double top = base + c[3];
         // non-decreasing over the tile: a lane starts no lower than the end of
         // every lane before it (the scan's rounding order differs from the
         // lanes' own)
-        const double pmax = wave_scan_incl(top, OpMax());
+        const double pmax = wave_scan_dpp(top, OpMax(), -INFINITY);
         const double pup = __shfl_up(pmax, 1, 64);
         const double floor_ = lane ? pup : -INFINITY;
         int hi[4];
@@ -713,12 +715,12 @@ __global__ __launch_bounds__(kTile) void k_resample(const InstDev* __restrict__ 
             const bool last = (4 * lane + i == count - 1);
             const double Ck = last ? off1 : fmin(off0 + v, off1);
             const double y = Ck * sN;
-            hi[i] = (k0 + i == Nc - 1) ? Nc : count_points_below(y, d, Nc);
+            hi[i] = (k0 + i == Nc - 1) ? Nc : count_points_below(y, d, Ncd);
             if (I.ykey && 4 * lane + i < count) gptr(I.ykey)[k0 + i] = y;
         }
         if (I.selection == SEL_EQ) {
             const int prev = __shfl_up(hi[3], 1, 64);
-            int lo = lane ? prev : count_points_below(off0 * sN, d, Nc);
+            int lo = lane ? prev : count_points_below(off0 * sN, d, Ncd);
             const auto anc = gptr(I.anc);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
