@@ -550,6 +550,32 @@ __device__ __forceinline__ double eq_offset(const InstDev& I, uint32_t beta)
     return (hi + lo) * 0x1p-52;
 }
 
+// The interval's closing work, on one thread: the total, ln of the mean
+// weight and the psi sums, the per-interval log, beta, and the [eq] offset of
+// the next cloning stage.
+__device__ __forceinline__ void prefix_finish(const InstDev& I, uint32_t beta, double M, double T,
+                                              uint64_t hops)
+{
+    I.tile_off[I.ntiles] = T;
+    InstCtl* c = I.ctl;
+    const double lbeta = M + log(T / (double)I.Nc);
+    c->lmax = M;
+    c->lbeta = lbeta;
+    neumaier_add(c->psi_sum, c->psi_comp, lbeta);
+    if ((int64_t)beta > I.burn_in) neumaier_add(c->psib_sum, c->psib_comp, lbeta);
+    c->hops += hops;
+    if ((int64_t)beta <= (int64_t)I.log_cycles) {
+        I.log[2 * (beta - 1)] = lbeta;
+        I.log[2 * (beta - 1) + 1] = (double)hops / (double)I.Nc;
+    }
+    c->beta = beta;
+    c->d_eq = eq_offset(I, beta);
+}
+
+// Tiles per thread that k_prefix keeps in registers (instances of up to
+// kTile * kPrefixRegs tiles); larger instances re-read their tile arrays.
+constexpr int kPrefixRegs = 16;
+
 __global__ __launch_bounds__(kTile) void k_prefix(const InstDev* __restrict__ insts)
 {
     __shared__ double s_d[kTile / 64];
@@ -561,6 +587,63 @@ __global__ __launch_bounds__(kTile) void k_prefix(const InstDev* __restrict__ in
     if (blockIdx.x == 0 && tid < kMaxGroups) I.next_tile[tid] = 0;
     const uint32_t beta = (uint32_t)(I.ctl->beta + 1);
 
+    // thread tid owns tiles [b0, b1)
+    const int ch = (n + kTile - 1) / kTile;
+    const int b0 = min(tid * ch, n), b1 = min(b0 + ch, n);
+    double T;
+    if (ch <= kPrefixRegs) {
+        // every tile value is loaded once, up front, and kept in registers;
+        // the arithmetic is the same as below, in the same order
+        double tm[kPrefixRegs], ts[kPrefixRegs];
+        double m = -INFINITY;
+        uint64_t h = 0;
+#pragma unroll
+        for (int q = 0; q < kPrefixRegs; ++q) {
+            if (b0 + q < b1) {
+                tm[q] = I.tile_max[b0 + q];
+                ts[q] = I.tile_sum[b0 + q];
+                h += I.tile_hops[b0 + q];
+                m = fmax(m, tm[q]);
+            }
+        }
+        const double M = block_reduce(m, OpMax(), s_d);
+        const uint64_t hops = block_reduce(h, OpSum(), s_u);
+        double loc = 0.0;
+#pragma unroll
+        for (int q = 0; q < kPrefixRegs; ++q) {
+            if (b0 + q < b1) {
+                ts[q] = ts[q] * exp(tm[q] - M);   // the tile's weight
+                loc += ts[q];
+            }
+        }
+        double total;
+        const double incl = block_scan_incl(loc, OpSum(), s_d, total);
+        s_x[tid] = incl;
+        __syncthreads();
+        const double base = (tid == 0) ? 0.0 : s_x[tid - 1];
+        double lp = 0.0, run = -INFINITY;
+#pragma unroll
+        for (int q = 0; q < kPrefixRegs; ++q) {
+            if (b0 + q < b1) {
+                run = fmax(run, base + lp);
+                tm[q] = run;   // the tile's offset before the fix-up below
+                lp += ts[q];
+            }
+        }
+        double all_max;
+        const double pm = block_scan_incl(run, OpMax(), s_d, all_max);
+        __syncthreads();
+        s_x[tid] = pm;
+        __syncthreads();
+        const double before = (tid == 0) ? -INFINITY : s_x[tid - 1];
+#pragma unroll
+        for (int q = 0; q < kPrefixRegs; ++q)
+            if (b0 + q < b1) I.tile_off[b0 + q] = fmax(tm[q], before);
+        T = fmax(total, all_max);
+        if (tid == 0) prefix_finish(I, beta, M, T, hops);
+        return;
+    }
+
     double m = -INFINITY;
     uint64_t h = 0;
     for (int b = tid; b < n; b += kTile) {
@@ -570,9 +653,6 @@ __global__ __launch_bounds__(kTile) void k_prefix(const InstDev* __restrict__ in
     const double M = block_reduce(m, OpMax(), s_d);
     const uint64_t hops = block_reduce(h, OpSum(), s_u);
 
-    // thread tid owns tiles [b0, b1)
-    const int ch = (n + kTile - 1) / kTile;
-    const int b0 = min(tid * ch, n), b1 = min(b0 + ch, n);
     double loc = 0.0;
     for (int b = b0; b < b1; ++b) loc += tile_weight(I, b, M);
     double total;
@@ -594,24 +674,8 @@ __global__ __launch_bounds__(kTile) void k_prefix(const InstDev* __restrict__ in
     __syncthreads();
     const double before = (tid == 0) ? -INFINITY : s_x[tid - 1];
     for (int b = b0; b < b1; ++b) I.tile_off[b] = fmax(I.tile_off[b], before);
-    const double T = fmax(total, all_max);
-
-    if (tid == 0) {
-        I.tile_off[n] = T;
-        InstCtl* c = I.ctl;
-        const double lbeta = M + log(T / (double)I.Nc);
-        c->lmax = M;
-        c->lbeta = lbeta;
-        neumaier_add(c->psi_sum, c->psi_comp, lbeta);
-        if ((int64_t)beta > I.burn_in) neumaier_add(c->psib_sum, c->psib_comp, lbeta);
-        c->hops += hops;
-        if ((int64_t)beta <= (int64_t)I.log_cycles) {
-            I.log[2 * (beta - 1)] = lbeta;
-            I.log[2 * (beta - 1) + 1] = (double)hops / (double)I.Nc;
-        }
-        c->beta = beta;
-        c->d_eq = eq_offset(I, beta);
-    }
+    T = fmax(total, all_max);
+    if (tid == 0) prefix_finish(I, beta, M, T, hops);
 }
 
 // ---------------------------------------------------------------------------

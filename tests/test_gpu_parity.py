@@ -76,6 +76,8 @@ STEP_CASES = [
     (400, 200, 1.25e-4, MOD, 1.0, 300), (512, 256, 0.0, DIR, 0.3, 256),
     (2, 1, 0.3, MOD, 2.0, 64), (3, 1, -0.2, MOD, 1.5, 65), (20, 0, 0.5, MOD, 1.0, 50),
     (20, 20, 0.5, DIR, 1.0, 50), (13, 6, 0.7, MOD, 5.0, 1),
+    # 4297 tiles: more than the prefix kernel keeps in registers (16 per thread)
+    (10, 5, 0.4, MOD, 0.1, 1_100_000),
 ]
 
 
@@ -107,7 +109,9 @@ def test_one_cycle_bit_exact(L, N, s, mode, dt, Nc):
     assert np.array_equal(w2, w_gpu[:, anc]) and np.array_equal(K2, K_gpu[anc])
     e = S.estimates()
     assert e["cycles"] == 1 and e["hops"] == int(Kb_o.sum())
-    assert e["psi"] * dt == pytest.approx(lm, rel=1e-12, abs=1e-15)
+    # the oracle sums the Nc weights one after the other: relative error of the
+    # total below (Nc - 1) u, which dominates at a million clones
+    assert e["psi"] * dt == pytest.approx(lm, rel=1e-12, abs=1e-15 + Nc * 2.0 ** -53)
 
 
 @pytest.mark.parametrize("L,N,s,mode,Nc", [(10, 5, 0.4, MOD, 1000), (10, 5, -0.3, DIR, 600),
