@@ -302,21 +302,28 @@ __global__ __launch_bounds__(kTile) void k_step_c(const InstDev* __restrict__ in
     const int later = max(2, (int)fmin(0.15 * ev + 1.0, 1.0e6));
     __syncthreads();
 
+    bool fin = false;   // finished in this round, outputs not yet written
     for (;;) {
         for (int it = 0; active && it < budget; ++it) {
             if (one_event<W, true>(C, (uint32_t)(td.first + t), x, m, r, tau, A, k, kb)) {
-                const int64_t j = td.first + t;
-                const double ell = directw ? -I.s * (double)kb : -I.c * A;
-#pragma unroll
-                for (int w = 0; w < W; ++w) gptr(I.state[dst])[w * Nc + j] = x[w];
-                gptr(I.K[dst])[j] = Kfrom + kb;
-                gptr(I.Kb)[j] = kb;
-                gptr(I.A)[j] = A;
-                gptr(I.ell)[j] = ell;
-                s_ell[t] = ell;
-                s_kb[t] = kb;
                 active = false;
+                fin = true;
             }
+        }
+        // the clones that finished in this round write their outputs once,
+        // after the event loop (their registers are left as they finished)
+        if (fin) {
+            const int64_t j = td.first + t;
+            const double ell = directw ? -I.s * (double)kb : -I.c * A;
+#pragma unroll
+            for (int w = 0; w < W; ++w) gptr(I.state[dst])[w * Nc + j] = x[w];
+            gptr(I.K[dst])[j] = Kfrom + kb;
+            gptr(I.Kb)[j] = kb;
+            gptr(I.A)[j] = A;
+            gptr(I.ell)[j] = ell;
+            s_ell[t] = ell;
+            s_kb[t] = kb;
+            fin = false;
         }
         // rank of each unfinished clone among the block's unfinished clones
         const uint64_t bal = __ballot(active);

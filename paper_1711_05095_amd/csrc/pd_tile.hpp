@@ -21,8 +21,11 @@ __device__ __forceinline__ void tile_aggregate(const InstDev& I, int tile, const
     double mx = -INFINITY;
     for (int i = lane; i < n; i += 64) mx = fmax(mx, sell[i]);
     mx = wave_reduce(mx, OpMax());
+    double pc[14];   // exp's Taylor coefficients as uniform operands
+#pragma unroll
+    for (int q = 0; q < 14; ++q) pc[q] = I.exp_poly[q];
     double sm = 0.0;
-    for (int i = lane; i < n; i += 64) sm += exp(sell[i] - mx);
+    for (int i = lane; i < n; i += 64) sm += exp_nonpos(sell[i] - mx, I.ln2_hi, I.ln2_lo, pc);
     sm = wave_reduce(sm, OpSum());
     const uint64_t th = wave_reduce(hops_lane, OpSum());
     if (lane == 0) {
