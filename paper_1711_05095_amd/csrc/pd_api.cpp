@@ -101,6 +101,7 @@ std::string validate(const pd_params& p)
 
 struct Layout {
     size_t state[2], K[2], Kb, A, ell, anc, origin[2], ykey, tmax, tsum, thops, toff, log, ctl;
+    size_t cu64, cf64, cu32;   // guided continuation (0: not guided)
     size_t end;
     int ntiles;
 };
@@ -125,6 +126,10 @@ Layout layout_of(const pd_params& p, size_t base)
     o.origin[0] = p.track_origin ? take(4 * Nc) : 0;
     o.origin[1] = p.track_origin ? take(4 * Nc) : 0;
     o.ykey = (p.selection == PD_SEL_IID) ? take(8 * Nc) : 0;
+    const bool guided = p.weight_mode == PD_W_GUIDED;
+    o.cu64 = guided ? take(8 * Nc * (W + 2)) : 0;
+    o.cf64 = guided ? take(8 * Nc * 4) : 0;
+    o.cu32 = guided ? take(4 * Nc * 5) : 0;
     o.tmax = take(8 * (size_t)o.ntiles);
     o.tsum = take(8 * (size_t)o.ntiles);
     o.thops = take(8 * (size_t)o.ntiles);
@@ -379,6 +384,9 @@ pd_status pd_create(const pd_params* params, int32_t n, void* d_workspace, size_
         d.ln2_hi = ln2_hi;
         d.ln2_lo = ln2_lo;
         d.next_tile = (uint32_t*)(b + pl.counters_off);
+        d.cont_u64 = o.cu64 ? (uint64_t*)(b + o.cu64) : nullptr;
+        d.cont_f64 = o.cf64 ? (double*)(b + o.cf64) : nullptr;
+        d.cont_u32 = o.cu32 ? (uint32_t*)(b + o.cu32) : nullptr;
         ctx->dev.push_back(d);
         if (p.selection == PD_SEL_IID) ctx->any_iid = true;
         if (p.weight_mode == PD_W_GUIDED) ctx->any_guided = true;

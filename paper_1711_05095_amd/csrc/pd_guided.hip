@@ -1,8 +1,9 @@
 // Guided dynamical stage for gfx950 (arXiv:1711.05095, Sec. 2.2): the
 // continuous-time SSEP with every allowed hop's rate multiplied by a guide
 // factor from a table over the bond's 13-site neighbourhood, and the exact
-// compensating weight that keeps psi-hat unbiased.  One clone per lane; the
-// tile aggregates are the plain step kernels' (pd_tile.hpp).
+// compensating weight that keeps psi-hat unbiased.  One clone per lane in two
+// launches (a budgeted one, then the unfinished clones densely), and the tile
+// aggregates of the plain step kernels (pd_tile.hpp) in a third.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -66,23 +67,31 @@ __device__ __forceinline__ uint64_t guided_total(const uint64_t (&x)[W], const u
     return S;
 }
 
-template <int W>
+// The guided stage runs in two launches of this kernel.  CONT = false: one
+// clone per lane, at most ev_budget events (about 1.1 times the mean of the
+// previous interval); a clone not done by then is handed on, registers and
+// slot, to the second launch.  CONT = true: block b of an instance's tiles
+// takes the handed-on clones 256 b .. 256 b + 255 (in hand-on order) and runs
+// each to the end of the interval, so a wave of the first launch never waits
+// for the Poisson tail of its 64 clones.  Random numbers are keyed by slot and
+// by the event and proposal indices the clone carries, so the split changes
+// no result.
+template <int W, bool CONT>
 __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ insts,
                                                   const TileDesc* __restrict__ tiles,
                                                   int tile_base, int src, int use_anc)
 {
-    // the table, then (once every lane is done with it) the tile's ln Ups and hops
-    __shared__ __align__(16) char s_raw[kGuideCompact * sizeof(uint32_t)];
-    static_assert(kTile * (sizeof(double) + sizeof(uint64_t)) <= sizeof(s_raw), "aliasing");
-    uint32_t* s_eg = (uint32_t*)s_raw;
-    double* s_ell = (double*)s_raw;
-    uint64_t* s_u = (uint64_t*)(s_raw + kTile * sizeof(double));
+    __shared__ __align__(16) uint32_t s_eg[kGuideCompact];
     __shared__ double s_log[kLogRows * 4];
     __shared__ uint8_t s_sel[2048];
 
     const TileDesc td = tiles[tile_base + blockIdx.x];
     const InstDev& I = insts[td.inst];
     const int L = I.L;
+    const int64_t Nc = I.Nc;
+    const uint32_t ncont = CONT ? I.ctl->ncont : 0u;
+    const uint32_t e0 = (uint32_t)td.tile * kTile;   // first handed-on clone of the block
+    if (CONT && e0 >= ncont) return;                  // uniform over the block
     for (int i = threadIdx.x; i < kLogRows * 4; i += kTile) s_log[i] = gptr(I.log_tab)[i];
     fill_select_table(s_sel, threadIdx.x, kTile);
     for (int i = threadIdx.x; i < kGuideCompact; i += kTile) {
@@ -92,115 +101,165 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
     __syncthreads();
 
     const int tid = threadIdx.x;
-    const bool valid = tid < td.count;
-    const int64_t j = td.first + tid;
-    const int64_t Nc = I.Nc;
+    const uint32_t q = e0 + (uint32_t)tid;            // handed-on clone (CONT)
+    if (CONT ? q >= ncont : tid >= td.count) return;  // no barrier follows
     const uint32_t beta = (uint32_t)(I.ctl->beta + 1);
     const uint32_t c3 = TAG_GUIDE | I.tag_hi, cp = TAG_GUIDE_PROP | I.tag_hi;
     const double es = I.es, dt = I.dt;
     const uint64_t egmax = I.guide_max;
     double poly[8];   // log1p coefficients as uniform operands
 #pragma unroll
-    for (int q = 0; q < 8; ++q) poly[q] = I.log_poly[q];
+    for (int w = 0; w < 8; ++w) poly[w] = I.log_poly[w];
+    const int dst = src ^ 1;
+    const int lb = (L - 1) & 63;
 
-    uint32_t kb = 0;
-    double ell = -INFINITY;
-    if (valid) {
+    int64_t j;
+    uint64_t x[W], m[W], Kfrom, S;
+    uint32_t k, prop, kb;
+    double tau, A, AS, P;
+    int pexp;
+    if (CONT) {
+        j = gptr(I.cont_u32)[q];
+#pragma unroll
+        for (int w = 0; w < W; ++w) x[w] = gptr(I.cont_u64)[w * Nc + q];
+        Kfrom = gptr(I.cont_u64)[W * Nc + q];
+        S = gptr(I.cont_u64)[(W + 1) * Nc + q];
+        tau = gptr(I.cont_f64)[q];
+        A = gptr(I.cont_f64)[Nc + q];
+        AS = gptr(I.cont_f64)[2 * Nc + q];
+        P = gptr(I.cont_f64)[3 * Nc + q];
+        k = gptr(I.cont_u32)[Nc + q];
+        prop = gptr(I.cont_u32)[2 * Nc + q];
+        kb = gptr(I.cont_u32)[3 * Nc + q];
+        pexp = (int)gptr(I.cont_u32)[4 * Nc + q];
+        bond_mask<W>(x, lb, m);
+    } else {
+        j = td.first + tid;
         const int64_t from = use_anc ? (int64_t)gptr(I.anc)[j] : j;
-        uint64_t x[W], m[W];
 #pragma unroll
         for (int w = 0; w < W; ++w) x[w] = gptr(I.state[src])[w * Nc + from];
-        const uint64_t Kfrom = gptr(I.K[src])[from];
-        const int lb = (L - 1) & 63;
-        bond_mask<W>(x, lb, m);
-        int r = popcount_words<W>(m);
-        uint64_t S = guided_total<W>(x, m, L, s_eg);
-        uint32_t k = 0, prop = 0;
-        double tau = 0.0, A = 0.0, AS = 0.0, P = 1.0;
-        int pexp = 0;
-        int events = 0;
-        while (r > 0 && events < (1 << 30)) {
-            ++events;
-            const uint4 y = philox10(k, (uint32_t)j, beta, c3, I.key0, I.key1);
-            ++k;
-            const double E = -log_unit(unit_open0(y.x, y.y), s_log, I.ln2_hi, I.ln2_lo, poly);
-            const double R = es * ((double)S * 0x1p-16);
-            const double w = E / R;
-            if (tau + w >= dt) {
-                A = fma((double)r, dt - tau, A);
-                AS = fma((double)S, dt - tau, AS);
-                break;
-            }
-            A = fma((double)r, w, A);
-            AS = fma((double)S, w, AS);
-            tau = tau + w;
-            int b = 0;
-            uint32_t e = 0;
-            uint32_t qh = y.z, ql = y.w;   // bond word of the first proposal
-            for (int tries = 0; tries < (1 << 20); ++tries) {
-                b = select_bit_lut<W>(m, mulhi64_small(qh, ql, (uint32_t)r), s_sel);
-                e = s_eg[gidx(ring_bits<W>(x, L, ring_mod(b - 6, L), 13))];
-                const uint4 a = philox10(prop, (uint32_t)j, beta, cp, I.key0, I.key1);
-                ++prop;
-                if (__umul64hi(((uint64_t)a.x << 32) | a.y, egmax) < (uint64_t)e) break;
-                qh = a.z;
-                ql = a.w;
-            }
-            P *= (double)e;
-            pexp += __builtin_amdgcn_frexp_exp(P);
-            P = __builtin_amdgcn_frexp_mant(P);
-            if (L >= 26) {
-                // the 14 bonds whose neighbourhood holds site b or b+1 are
-                // bits o..o+12 of the 26 sites from b-12, o = 0..13
-                const uint32_t win0 = ring_bits<W>(x, L, b >= 12 ? b - 12 : b - 12 + L, 26);
-                const uint32_t win1 = win0 ^ (3u << 12);
-                // bit i: sites i and i+1 of the window differ (the bond is a hop)
-                const uint32_t al0 = win0 ^ (win0 >> 1), al1 = win1 ^ (win1 >> 1);
-                uint64_t add = 0, sub = 0;
-                // branch-free: every neighbourhood's entry is read (any 13-bit u
-                // has a compact index) and masked by its bond's bit
-#pragma unroll
-                for (int o = 0; o < 14; ++o) {
-                    const uint32_t u0 = (win0 >> o) & 0x1FFFu;
-                    const uint32_t u1 = (win1 >> o) & 0x1FFFu;
-                    const uint32_t k0 = (uint32_t)__builtin_amdgcn_sbfe((int)al0, o + 6, 1);
-                    const uint32_t k1 = (uint32_t)__builtin_amdgcn_sbfe((int)al1, o + 6, 1);
-                    sub += s_eg[gidx(u0)] & k0;
-                    add += s_eg[gidx(u1)] & k1;
-                }
-                hop<W>(x, b, L);
-                bond_mask<W>(x, lb, m);
-                S = S + add - sub;
-            } else {
-                hop<W>(x, b, L);
-                bond_mask<W>(x, lb, m);
-                S = guided_total<W>(x, m, L, s_eg);
-            }
-            r = popcount_words<W>(m);
-            ++kb;
-        }
-        // sum_jumps ln(eg 2^-16) = ln P + (pexp - 16 kb) ln 2
-        const double G = log_unit(P, s_log, I.ln2_hi, I.ln2_lo, poly) +
-                         (double)(pexp - 16 * (int)kb) * (I.ln2_hi + I.ln2_lo);
-        ell = -G - (A - (es * 0x1p-16) * AS);
-        const int dst = src ^ 1;
-#pragma unroll
-        for (int w = 0; w < W; ++w) gptr(I.state[dst])[w * Nc + j] = x[w];
-        gptr(I.K[dst])[j] = Kfrom + kb;
-        gptr(I.Kb)[j] = kb;
-        gptr(I.A)[j] = A;
-        gptr(I.ell)[j] = ell;
+        Kfrom = gptr(I.K[src])[from];
         if (I.origin[0]) gptr(I.origin[dst])[j] = gptr(I.origin[src])[from];
+        bond_mask<W>(x, lb, m);
+        S = guided_total<W>(x, m, L, s_eg);
+        tau = 0.0; A = 0.0; AS = 0.0; P = 1.0;
+        k = 0; prop = 0; kb = 0; pexp = 0;
     }
-    __syncthreads();   // every lane is done with the table before it is overwritten
-    s_ell[tid] = ell;
-    s_u[tid] = kb;
-    __syncthreads();
-    if (tid < 64) {
-        uint64_t h = 0;
-        for (int i = tid; i < td.count; i += 64) h += s_u[i];
-        tile_aggregate(I, td.tile, s_ell, td.count, h);
+    int r = popcount_words<W>(m);
+    const uint32_t eb = CONT ? 0u : I.ctl->ev_budget;
+    const uint32_t kend = eb ? eb : 0xFFFFFFFFu;   // the first launch stops at event kend
+    bool done = true;
+    while (r > 0 && k < (1u << 30)) {
+        if (!CONT && k >= kend) {
+            done = false;
+            break;
+        }
+        const uint4 y = philox10(k, (uint32_t)j, beta, c3, I.key0, I.key1);
+        ++k;
+        const double E = -log_unit(unit_open0(y.x, y.y), s_log, I.ln2_hi, I.ln2_lo, poly);
+        const double R = es * ((double)S * 0x1p-16);
+        const double w = E / R;
+        if (tau + w >= dt) {
+            A = fma((double)r, dt - tau, A);
+            AS = fma((double)S, dt - tau, AS);
+            break;
+        }
+        A = fma((double)r, w, A);
+        AS = fma((double)S, w, AS);
+        tau = tau + w;
+        int b = 0;
+        uint32_t e = 0;
+        uint32_t qh = y.z, ql = y.w;   // bond word of the first proposal
+        for (int tries = 0; tries < (1 << 20); ++tries) {
+            b = select_bit_lut<W>(m, mulhi64_small(qh, ql, (uint32_t)r), s_sel);
+            e = s_eg[gidx(ring_bits<W>(x, L, ring_mod(b - 6, L), 13))];
+            const uint4 a = philox10(prop, (uint32_t)j, beta, cp, I.key0, I.key1);
+            ++prop;
+            if (__umul64hi(((uint64_t)a.x << 32) | a.y, egmax) < (uint64_t)e) break;
+            qh = a.z;
+            ql = a.w;
+        }
+        P *= (double)e;
+        pexp += __builtin_amdgcn_frexp_exp(P);
+        P = __builtin_amdgcn_frexp_mant(P);
+        if (L >= 26) {
+            // the 14 bonds whose neighbourhood holds site b or b+1 are
+            // bits o..o+12 of the 26 sites from b-12, o = 0..13
+            const uint32_t win0 = ring_bits<W>(x, L, b >= 12 ? b - 12 : b - 12 + L, 26);
+            const uint32_t win1 = win0 ^ (3u << 12);
+            // bit i: sites i and i+1 of the window differ (the bond is a hop)
+            const uint32_t al0 = win0 ^ (win0 >> 1), al1 = win1 ^ (win1 >> 1);
+            uint64_t add = 0, sub = 0;
+            // branch-free: every neighbourhood's entry is read (any 13-bit u
+            // has a compact index) and masked by its bond's bit
+#pragma unroll
+            for (int o = 0; o < 14; ++o) {
+                const uint32_t u0 = (win0 >> o) & 0x1FFFu;
+                const uint32_t u1 = (win1 >> o) & 0x1FFFu;
+                const uint32_t k0 = (uint32_t)__builtin_amdgcn_sbfe((int)al0, o + 6, 1);
+                const uint32_t k1 = (uint32_t)__builtin_amdgcn_sbfe((int)al1, o + 6, 1);
+                sub += s_eg[gidx(u0)] & k0;
+                add += s_eg[gidx(u1)] & k1;
+            }
+            hop<W>(x, b, L);
+            bond_mask<W>(x, lb, m);
+            S = S + add - sub;
+        } else {
+            hop<W>(x, b, L);
+            bond_mask<W>(x, lb, m);
+            S = guided_total<W>(x, m, L, s_eg);
+        }
+        r = popcount_words<W>(m);
+        ++kb;
     }
+    if (!done) {
+        // one atomic per wave (the counter is shared by every block of the
+        // instance): the wave's handing-on lanes take consecutive entries
+        const int lane = tid & 63;
+        const uint64_t hm = __ballot(1);
+        const int lead = __ffsll((unsigned long long)hm) - 1;
+        const uint32_t rank = (uint32_t)__popcll(hm & ((1ull << lane) - 1ull));
+        uint32_t base = 0;
+        if (lane == lead) base = atomicAdd(&I.ctl->ncont, (uint32_t)__popcll(hm));
+        const uint32_t h = (uint32_t)__shfl((int)base, lead, 64) + rank;
+#pragma unroll
+        for (int w = 0; w < W; ++w) gptr(I.cont_u64)[w * Nc + h] = x[w];
+        gptr(I.cont_u64)[W * Nc + h] = Kfrom;
+        gptr(I.cont_u64)[(W + 1) * Nc + h] = S;
+        gptr(I.cont_f64)[h] = tau;
+        gptr(I.cont_f64)[Nc + h] = A;
+        gptr(I.cont_f64)[2 * Nc + h] = AS;
+        gptr(I.cont_f64)[3 * Nc + h] = P;
+        gptr(I.cont_u32)[h] = (uint32_t)j;
+        gptr(I.cont_u32)[Nc + h] = k;
+        gptr(I.cont_u32)[2 * Nc + h] = prop;
+        gptr(I.cont_u32)[3 * Nc + h] = kb;
+        gptr(I.cont_u32)[4 * Nc + h] = (uint32_t)pexp;
+        return;
+    }
+    // sum_jumps ln(eg 2^-16) = ln P + (pexp - 16 kb) ln 2
+    const double G = log_unit(P, s_log, I.ln2_hi, I.ln2_lo, poly) +
+                     (double)(pexp - 16 * (int)kb) * (I.ln2_hi + I.ln2_lo);
+    const double ell = -G - (A - (es * 0x1p-16) * AS);
+#pragma unroll
+    for (int w = 0; w < W; ++w) gptr(I.state[dst])[w * Nc + j] = x[w];
+    gptr(I.K[dst])[j] = Kfrom + kb;
+    gptr(I.Kb)[j] = kb;
+    gptr(I.A)[j] = A;
+    gptr(I.ell)[j] = ell;
+}
+
+// Tile aggregates of the guided stage, from the outputs written by slot (in
+// the order every step kernel uses).
+__global__ __launch_bounds__(64) void k_tile_stats(const InstDev* __restrict__ insts,
+                                                   const TileDesc* __restrict__ tiles,
+                                                   int tile_base)
+{
+    const TileDesc td = tiles[tile_base + blockIdx.x];
+    const InstDev& I = insts[td.inst];
+    uint64_t h = 0;
+    for (int i = threadIdx.x; i < td.count; i += 64) h += gptr(I.Kb)[td.first + i];
+    tile_aggregate(I, td.tile, I.ell + td.first, td.count, h);
 }
 
 hipError_t launch_step_guided(int W, int count, const InstDev* insts, const TileDesc* tiles,
@@ -209,14 +268,17 @@ hipError_t launch_step_guided(int W, int count, const InstDev* insts, const Tile
     switch (W) {
 #define PD_CASE(w)                                                                            \
     case w:                                                                                   \
-        hipLaunchKernelGGL(k_step_g<w>, dim3(count), dim3(kTile), 0, st, insts, tiles, base,  \
-                           src, use_anc);                                                     \
+        hipLaunchKernelGGL((k_step_g<w, false>), dim3(count), dim3(kTile), 0, st, insts,      \
+                           tiles, base, src, use_anc);                                        \
+        hipLaunchKernelGGL((k_step_g<w, true>), dim3(count), dim3(kTile), 0, st, insts,       \
+                           tiles, base, src, use_anc);                                        \
         break;
         PD_CASE(1) PD_CASE(2) PD_CASE(3) PD_CASE(4) PD_CASE(5) PD_CASE(6) PD_CASE(7)
         PD_CASE(8)
 #undef PD_CASE
         default: return hipErrorInvalidValue;
     }
+    hipLaunchKernelGGL(k_tile_stats, dim3(count), dim3(64), 0, st, insts, tiles, base);
     return hipGetLastError();
 }
 

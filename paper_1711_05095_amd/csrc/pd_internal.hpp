@@ -21,7 +21,8 @@ enum : int32_t { SEL_EQ = 0, SEL_IID = 1 };
 // graphs advance it on every replay.
 struct InstCtl {
     int64_t beta;          // intervals whose dynamical stage has run
-    uint32_t pad_a, pad_b;
+    uint32_t ncont;        // clones the guided stage's first launch handed on (zeroed by k_prefix)
+    uint32_t ev_budget;    // events per clone of the guided stage's first launch (0: no limit)
     double lmax;           // max_i ln Ups_i of the current interval
     double lbeta;          // ln mean Ups of the current interval
     double psi_sum, psi_comp;    // Neumaier sum of lbeta over all intervals
@@ -63,6 +64,11 @@ struct InstDev {
     double exp_poly[14];   // 1/13!, 1/12!, ..., 1/1!, 1: Taylor coefficients of exp (uniform)
     InstCtl* ctl;
     uint32_t* next_tile;   // work counters of the persistent step launches
+    // clones the guided stage's first launch left unfinished, in the order it
+    // handed them on (guided instances only, else null)
+    uint64_t* cont_u64;    // [W + 2][Nc]: state words, carried K, S
+    double* cont_f64;      // [4][Nc]: tau, integral of r dt, integral of S dt, jump product
+    uint32_t* cont_u32;    // [5][Nc]: slot, event index, proposal index, hops, jump exponent
 };
 
 constexpr int kMaxGroups = 16;     // step launches per cycle (one per word count)

@@ -79,6 +79,8 @@ __global__ void k_reset_ctl(const InstDev* __restrict__ insts, int n)
     if (i >= n) return;
     InstCtl* c = insts[i].ctl;
     c->beta = 0;
+    c->ncont = 0;
+    c->ev_budget = 0;
     c->lmax = 0.0;
     c->lbeta = 0.0;
     c->psi_sum = c->psi_comp = 0.0;
@@ -577,6 +579,10 @@ __device__ __forceinline__ void prefix_finish(const InstDev& I, uint32_t beta, d
     }
     c->beta = beta;
     c->d_eq = eq_offset(I, beta);
+    // the guided stage's next first launch: 1.1 times this interval's mean
+    // events per clone (hops + the closing draw), the rest in its second launch
+    c->ncont = 0;
+    c->ev_budget = (uint32_t)fmin(1.1 * ((double)hops / (double)I.Nc + 1.0) + 2.0, 1073741824.0);
 }
 
 // Tiles per thread that k_prefix keeps in registers (instances of up to
