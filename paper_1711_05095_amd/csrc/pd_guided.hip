@@ -67,10 +67,11 @@ __device__ __forceinline__ uint64_t guided_total(const uint64_t (&x)[W], const u
     return S;
 }
 
-// The guided stage runs in two launches of this kernel.  CONT = false: one
-// clone per lane, at most ev_budget events (about 1.1 times the mean of the
-// previous interval); a clone not done by then is handed on, registers and
-// slot, to the second launch.  CONT = true: block b of an instance's tiles
+// The guided stage runs in two launches of this kernel (one when the launch is
+// small, see kGuidedSplitTiles).  CONT = false: one clone per lane, at most
+// ev_budget events (about 1.1 times the mean of the previous interval); a
+// clone not done by then is handed on, registers and slot, to the second
+// launch.  CONT = true: block b of an instance's tiles
 // takes the handed-on clones 256 b .. 256 b + 255 (in hand-on order) and runs
 // each to the end of the interval, so a wave of the first launch never waits
 // for the Poisson tail of its 64 clones.  Random numbers are keyed by slot and
@@ -79,7 +80,8 @@ __device__ __forceinline__ uint64_t guided_total(const uint64_t (&x)[W], const u
 template <int W, bool CONT>
 __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ insts,
                                                   const TileDesc* __restrict__ tiles,
-                                                  int tile_base, int src, int use_anc)
+                                                  int tile_base, int src, int use_anc,
+                                                  int budgeted)
 {
     __shared__ __align__(16) uint32_t s_eg[kGuideCompact];
     __shared__ double s_log[kLogRows * 4];
@@ -146,7 +148,7 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
         k = 0; prop = 0; kb = 0; pexp = 0;
     }
     int r = popcount_words<W>(m);
-    const uint32_t eb = CONT ? 0u : I.ctl->ev_budget;
+    const uint32_t eb = (CONT || !budgeted) ? 0u : I.ctl->ev_budget;
     const uint32_t kend = eb ? eb : 0xFFFFFFFFu;   // the first launch stops at event kend
     bool done = true;
     while (r > 0 && k < (1u << 30)) {
@@ -262,16 +264,24 @@ __global__ __launch_bounds__(64) void k_tile_stats(const InstDev* __restrict__ i
     tile_aggregate(I, td.tile, I.ell + td.first, td.count, h);
 }
 
+// Tiles from which on the guided stage is split in two launches: below it the
+// whole launch is resident at once (7 blocks per CU), so the lanes a wave's
+// Poisson tail leaves idle hold no other work back, and a second launch would
+// only add its own time.
+constexpr int kGuidedSplitTiles = 2 * 7 * 256;
+
 hipError_t launch_step_guided(int W, int count, const InstDev* insts, const TileDesc* tiles,
                               int base, int src, int use_anc, hipStream_t st)
 {
+    const int split = count >= kGuidedSplitTiles;
     switch (W) {
 #define PD_CASE(w)                                                                            \
     case w:                                                                                   \
         hipLaunchKernelGGL((k_step_g<w, false>), dim3(count), dim3(kTile), 0, st, insts,      \
-                           tiles, base, src, use_anc);                                        \
-        hipLaunchKernelGGL((k_step_g<w, true>), dim3(count), dim3(kTile), 0, st, insts,       \
-                           tiles, base, src, use_anc);                                        \
+                           tiles, base, src, use_anc, split);                                 \
+        if (split)                                                                            \
+            hipLaunchKernelGGL((k_step_g<w, true>), dim3(count), dim3(kTile), 0, st, insts,   \
+                               tiles, base, src, use_anc, 1);                                 \
         break;
         PD_CASE(1) PD_CASE(2) PD_CASE(3) PD_CASE(4) PD_CASE(5) PD_CASE(6) PD_CASE(7)
         PD_CASE(8)

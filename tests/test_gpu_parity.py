@@ -284,6 +284,42 @@ def test_guided_cycles_bit_exact(L, N, s, Nc, table_seed):
         occ, K = np.ascontiguousarray(occ[anc]), K[anc]
 
 
+def test_guided_full_size_sampled():
+    """A guided launch large enough to be split in two (3907 tiles): the third
+    cycle runs with an event budget from the second, so clones are handed on to
+    the second launch; 2000 sampled clones stepped by the oracle, bit-exact, and
+    the selection (which reads the third launch's tile aggregates) checked
+    against the oracle's on the GPU's log-weights."""
+    from guide_tables import random_table
+    L, N, s, Nc, dt = 100, 50, 0.002, 1_000_000, 0.5
+    print(f"guided full size L={L} Nc={Nc}", flush=True)
+    table = random_table(6)
+    p = pd.make_params(L, N, s, Nc, 10 * dt, dt, seed=41, weight_mode=GUIDED)
+    o = oracle.Oracle(L, N, s, Nc, dt, M=10, seed=41, mode=GUIDED, guide=table)
+    S = pd.Sampler(p)
+    S.set_guide(_guide_tensor(table))
+    S.run(2)
+    words, K = S.get_population()
+    rng = np.random.default_rng(5)
+    slots = np.sort(rng.choice(Nc, 2000, replace=False))
+    occ_s = unpack(words[:, slots], L)
+    K_s = K[slots].copy()
+    S.step()
+    w_gpu, K_gpu = S.get_population()
+    Kb_g, A_g, ell_g = S.step_outputs()
+    Kb_o, A_o, ell_o = o.step_slots(3, slots, occ_s, K_s)
+    # the budget is 1.1 x the mean events + 2: a quarter of the clones or so
+    # exceed it and finish in the second launch
+    assert np.mean(Kb_g + 1 > 1.1 * (Kb_g.mean() + 1) + 2) > 0.05
+    assert np.array_equal(Kb_g[slots], Kb_o)
+    assert np.array_equal(w_gpu[:, slots], pack(occ_s))
+    assert np.array_equal(K_gpu[slots], K_s)
+    assert np.allclose(A_g[slots], A_o, rtol=1e-12)
+    assert np.allclose(ell_g[slots], ell_o, rtol=1e-11, atol=1e-12)
+    S.resample()
+    check_selection(S.ancestors(), ell_g, o.eq_offset(3), "guided full size")
+
+
 def test_guided_whole_run_and_guide_validation():
     from guide_tables import constant_table, random_table
     w = inputs.SMALL
