@@ -101,7 +101,7 @@ std::string validate(const pd_params& p)
 
 struct Layout {
     size_t state[2], K[2], Kb, A, ell, anc, origin[2], ykey, tmax, tsum, thops, toff, log, ctl;
-    size_t cu64, cf64, cu32;   // guided continuation (0: not guided)
+    size_t cu64, cf64, cu32;   // guided continuation records (0: not guided)
     size_t end;
     int ntiles;
 };
@@ -126,6 +126,7 @@ Layout layout_of(const pd_params& p, size_t base)
     o.origin[0] = p.track_origin ? take(4 * Nc) : 0;
     o.origin[1] = p.track_origin ? take(4 * Nc) : 0;
     o.ykey = (p.selection == PD_SEL_IID) ? take(8 * Nc) : 0;
+    // records of clones the guided stage's first launch hands on to its second
     const bool guided = p.weight_mode == PD_W_GUIDED;
     o.cu64 = guided ? take(8 * Nc * (W + 2)) : 0;
     o.cf64 = guided ? take(8 * Nc * 4) : 0;

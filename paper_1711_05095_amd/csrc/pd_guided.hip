@@ -68,7 +68,7 @@ __device__ __forceinline__ uint64_t guided_total(const uint64_t (&x)[W], const u
 }
 
 // The guided stage runs in two launches of this kernel (one when the launch is
-// small, see kGuidedSplitTiles).  CONT = false: one clone per lane, at most
+// small, see kSplitTiles).  CONT = false: one clone per lane, at most
 // ev_budget events (about 1.1 times the mean of the previous interval); a
 // clone not done by then is handed on, registers and slot, to the second
 // launch.  CONT = true: block b of an instance's tiles
@@ -251,29 +251,34 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
     gptr(I.ell)[j] = ell;
 }
 
-// Tile aggregates of the guided stage, from the outputs written by slot (in
-// the order every step kernel uses).
-__global__ __launch_bounds__(64) void k_tile_stats(const InstDev* __restrict__ insts,
-                                                   const TileDesc* __restrict__ tiles,
-                                                   int tile_base)
+// Tile aggregates from the outputs written by slot, one wave per tile (the
+// order of tile_aggregate, as in every step kernel).
+__global__ __launch_bounds__(kTile) void k_tile_stats(const InstDev* __restrict__ insts,
+                                                      const TileDesc* __restrict__ tiles,
+                                                      int tile_base, int count)
 {
-    const TileDesc td = tiles[tile_base + blockIdx.x];
+    const int t = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (kTile / 64) +
+                                                       (threadIdx.x >> 6)));
+    if (t >= count) return;   // uniform over the wave; no barrier follows
+    const TileDesc td = tiles[tile_base + t];
     const InstDev& I = insts[td.inst];
     uint64_t h = 0;
-    for (int i = threadIdx.x; i < td.count; i += 64) h += gptr(I.Kb)[td.first + i];
+    for (int i = threadIdx.x & 63; i < td.count; i += 64) h += gptr(I.Kb)[td.first + i];
     tile_aggregate(I, td.tile, I.ell + td.first, td.count, h);
 }
 
-// Tiles from which on the guided stage is split in two launches: below it the
-// whole launch is resident at once (7 blocks per CU), so the lanes a wave's
-// Poisson tail leaves idle hold no other work back, and a second launch would
-// only add its own time.
-constexpr int kGuidedSplitTiles = 2 * 7 * 256;
+hipError_t launch_tile_stats(const InstDev* insts, const TileDesc* tiles, int base, int count,
+                             hipStream_t st)
+{
+    const int blocks = (count + kTile / 64 - 1) / (kTile / 64);
+    hipLaunchKernelGGL(k_tile_stats, dim3(blocks), dim3(kTile), 0, st, insts, tiles, base, count);
+    return hipGetLastError();
+}
 
 hipError_t launch_step_guided(int W, int count, const InstDev* insts, const TileDesc* tiles,
                               int base, int src, int use_anc, hipStream_t st)
 {
-    const int split = count >= kGuidedSplitTiles;
+    const int split = count >= kSplitTiles;
     switch (W) {
 #define PD_CASE(w)                                                                            \
     case w:                                                                                   \
@@ -288,8 +293,9 @@ hipError_t launch_step_guided(int W, int count, const InstDev* insts, const Tile
 #undef PD_CASE
         default: return hipErrorInvalidValue;
     }
-    hipLaunchKernelGGL(k_tile_stats, dim3(count), dim3(64), 0, st, insts, tiles, base);
-    return hipGetLastError();
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_tile_stats(insts, tiles, base, count, st);
 }
 
 }  // namespace pd

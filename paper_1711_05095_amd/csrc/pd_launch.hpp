@@ -22,6 +22,13 @@ hipError_t launch_init(const InstDev* insts, int n_inst, const TileDesc* tiles, 
                        hipStream_t st);
 hipError_t launch_step(const StepLaunch& s, const InstDev* insts, const TileDesc* tiles, int src,
                        int use_anc, hipStream_t st);
+// Tiles from which the guided stage is split in two launches (a budgeted one,
+// then the clones it handed on, densely): below it the whole launch is
+// resident at once (7 blocks per CU), so the lanes a wave's Poisson tail
+// leaves idle hold no other work back, and a second launch would only add its
+// own time.
+constexpr int kSplitTiles = 2 * 7 * 256;
+
 hipError_t launch_step_guided(int W, int count, const InstDev* insts, const TileDesc* tiles,
                               int base, int src, int use_anc, hipStream_t st);
 hipError_t step_occupancy(int W, int variant, int* blocks_per_cu);

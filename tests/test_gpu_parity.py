@@ -468,6 +468,35 @@ def test_batch_equals_separate():
         assert np.array_equal(ws, wb) and np.array_equal(Ks, Kb)
 
 
+@pytest.mark.parametrize("guided", [False, True])
+def test_split_launch_equals_unsplit(guided):
+    """Four instances of 938 tiles each, in one context (a step launch of 3752
+    tiles; the guided stage is then split in two, the clones past the event
+    budget finishing in a second launch) and each alone (one launch).  Every
+    result is the same bit for bit."""
+    from guide_tables import random_table
+    specs = [(10, 5, 0.3, 0.1), (30, 14, -0.05, 0.5), (64, 30, 0.01, 0.3), (20, 9, 0.2, 0.4)]
+    Nc, M = 240_000, 4
+    mode = GUIDED if guided else MOD
+    params = [pd.make_params(L, N, s, Nc, M * dt, dt, seed=60 + i, instance=i, weight_mode=mode)
+              for i, (L, N, s, dt) in enumerate(specs)]
+    table = _guide_tensor(random_table(8)) if guided else None
+    print(f"split vs unsplit guided={guided}", flush=True)
+    B = pd.Sampler(params)
+    if guided:
+        B.set_guide(table)
+    B.run(M)
+    for i, q in enumerate(params):
+        S = pd.Sampler(q)
+        if guided:
+            S.set_guide(table)
+        S.run(M)
+        assert S.estimates() == B.estimates(i), i
+        ws, Ks = S.get_population()
+        wb, Kb = B.get_population(i)
+        assert np.array_equal(ws, wb) and np.array_equal(Ks, Kb), i
+
+
 def test_small_workload_matches_exact_diagonalisation():
     """All 9 biases x 16 seeds of the L=10 workload as one batch; the mean of
     psi-hat over seeds is within 3 sigma of (1/t_obs) ln Z(s, t_obs)."""
@@ -525,6 +554,7 @@ def test_call_order_and_validation():
 
 
 @pytest.mark.parametrize("L,N,lam,Nc,dt", [(100, 50, 20.0, 100_000, 0.5),
+                                           (100, 50, 20.0, 1_000_000, 0.5),
                                            (400, 200, 20.0, 1_000_000, 1.0)])
 def test_full_size_sampled(L, N, lam, Nc, dt):
     """At the full workload sizes: one cycle from a GPU-evolved population,
