@@ -47,6 +47,17 @@ pd_tuning default_tuning()
 
 // Table of the device logarithm (rows of [c, -ln c (multiple of 2^-42),
 // remainder, 0]) and the split of ln 2, computed in extended precision.
+// Byte table of the device's bond selection: entry b * 8 + q is the position
+// of the q-th set bit (ascending) of the byte b for q < popcount(b), else 0.
+std::vector<uint8_t> select_table()
+{
+    std::vector<uint8_t> t(2048, 0);
+    for (int b = 0; b < 256; ++b)
+        for (int i = 0, q = 0; i < 8; ++i)
+            if ((b >> i) & 1) t[b * 8 + q++] = (uint8_t)i;
+    return t;
+}
+
 std::vector<double> log_table(double* ln2_hi, double* ln2_lo)
 {
     const long double two42 = 4398046511104.0L;
@@ -142,7 +153,7 @@ Layout layout_of(const pd_params& p, size_t base)
 }
 
 struct Plan {
-    size_t insts_off, tiles_off, log_off, invc_off, counters_off, total;
+    size_t insts_off, tiles_off, log_off, sel_off, invc_off, counters_off, total;
     std::vector<Layout> lay;
     int ntiles;
 };
@@ -159,6 +170,8 @@ Plan plan_of(const pd_params* p, int n)
     at = align_up(at + sizeof(TileDesc) * (size_t)nt);
     pl.log_off = at;
     at = align_up(at + sizeof(double) * 4 * kLogRows);
+    pl.sel_off = at;
+    at = align_up(at + 2048);
     pl.invc_off = at;
     at = align_up(at + sizeof(double) * (kMaxSites + 1));
     pl.counters_off = at;
@@ -338,6 +351,7 @@ pd_status pd_create(const pd_params* params, int32_t n, void* d_workspace, size_
     // descriptors and rate tables
     double ln2_hi = 0.0, ln2_lo = 0.0;
     const std::vector<double> logt = log_table(&ln2_hi, &ln2_lo);
+    const std::vector<uint8_t> selt = select_table();
     for (int i = 0; i < n; ++i) {
         const pd_params& p = params[i];
         const Layout& o = pl.lay[i];
@@ -382,6 +396,7 @@ pd_status pd_create(const pd_params* params, int32_t n, void* d_workspace, size_
         d.guide = nullptr;
         d.ctl = (InstCtl*)(b + o.ctl);
         d.log_tab = (const double*)(b + pl.log_off);
+        d.sel_tab = (const uint8_t*)(b + pl.sel_off);
         d.ln2_hi = ln2_hi;
         d.ln2_lo = ln2_lo;
         d.next_tile = (uint32_t*)(b + pl.counters_off);
@@ -457,6 +472,8 @@ pd_status pd_create(const pd_params* params, int32_t n, void* d_workspace, size_
     PD_HIP_CREATE(hipMemcpyAsync(ctx->ws + pl.invc_off, invc.data(), sizeof(double) * invc.size(),
                                  hipMemcpyHostToDevice, ctx->stream));
     PD_HIP_CREATE(hipMemcpyAsync(ctx->ws + pl.log_off, logt.data(), sizeof(double) * logt.size(),
+                                 hipMemcpyHostToDevice, ctx->stream));
+    PD_HIP_CREATE(hipMemcpyAsync(ctx->ws + pl.sel_off, selt.data(), selt.size(),
                                  hipMemcpyHostToDevice, ctx->stream));
     PD_HIP_CREATE(launch_init(ctx->d_insts, n, ctx->d_tiles, (int)ctx->tiles.size(), ctx->stream));
     {

@@ -137,24 +137,19 @@ __device__ __forceinline__ int popcount_words(const uint64_t (&m)[W])
 }
 
 // Byte table of select_bit_lut: entry b * 8 + q is the position of the q-th
-// set bit (0-based, ascending) of the byte b for q < popcount(b), else 0.
-__device__ __forceinline__ void fill_select_table(uint8_t* t, int tid, int nthr)
+// set bit (0-based, ascending) of the byte b for q < popcount(b), else 0.  The
+// host builds it once (2 KB in the shared workspace); a block copies it into
+// LDS (8-byte aligned), 8 bytes per thread.
+__device__ __forceinline__ void load_select_table(uint8_t* t, const uint8_t* src, int tid,
+                                                  int nthr)
 {
-    for (int e = tid; e < 2048; e += nthr) {
-        const uint32_t b = (uint32_t)e >> 3, q = (uint32_t)e & 7u;
-        uint32_t pos = 0, seen = 0;
-        for (uint32_t i = 0; i < 8; ++i)
-            if ((b >> i) & 1u) {
-                if (seen == q) pos = i;
-                ++seen;
-            }
-        t[e] = (uint8_t)pos;
-    }
+    const auto s = gptr((const uint64_t*)src);
+    for (int e = tid; e < 256; e += nthr) ((uint64_t*)t)[e] = s[e];
 }
 
 // Position of the q-th set bit (0-based, ascending) of the W-word mask, for
 // q < its popcount: the word, then halvings down to a byte, then one lookup
-// in the byte table (fill_select_table, in LDS).
+// in the byte table (load_select_table, in LDS).
 template <int W>
 __device__ __forceinline__ int select_bit_lut(const uint64_t (&m)[W], uint32_t q,
                                               const uint8_t* __restrict__ sel)

@@ -85,7 +85,7 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
 {
     __shared__ __align__(16) uint32_t s_eg[kGuideCompact];
     __shared__ double s_log[kLogRows * 4];
-    __shared__ uint8_t s_sel[2048];
+    __shared__ __align__(8) uint8_t s_sel[2048];
 
     const TileDesc td = tiles[tile_base + blockIdx.x];
     const InstDev& I = insts[td.inst];
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
     const uint32_t e0 = (uint32_t)td.tile * kTile;   // first handed-on clone of the block
     if (CONT && e0 >= ncont) return;                  // uniform over the block
     for (int i = threadIdx.x; i < kLogRows * 4; i += kTile) s_log[i] = gptr(I.log_tab)[i];
-    fill_select_table(s_sel, threadIdx.x, kTile);
+    load_select_table(s_sel, I.sel_tab, threadIdx.x, kTile);
     for (int i = threadIdx.x; i < kGuideCompact; i += kTile) {
         const uint32_t b6 = (i >> 6) & 1u;
         s_eg[i] = gptr(I.guide)[(i & 0x7F) | ((b6 ^ 1u) << 7) | ((i >> 7) << 8)];

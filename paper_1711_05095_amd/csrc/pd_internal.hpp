@@ -58,6 +58,7 @@ struct InstDev {
     const uint32_t* guide; // [8192] guide table e^g 2^16 over bond neighbourhoods
     uint64_t guide_max;    // largest table entry (acceptance bound)
     const double* log_tab; // [kLogRows][4] table of the device logarithm
+    const uint8_t* sel_tab;// [2048] byte table of select_bit_lut (shared)
     double ln2_hi, ln2_lo; // ln 2 = ln2_hi (a multiple of 2^-42) + ln2_lo
     double log_poly[8];    // 1/9, -1/8, ..., -1/2: Taylor coefficients of log1p (uniform
                            // operands, so the polynomial's fma take them from SGPRs)

@@ -167,13 +167,13 @@ __global__ __launch_bounds__(kTile) void k_step(const InstDev* __restrict__ inst
     __shared__ double s_log[kLogRows * 4];
     __shared__ double s_ell[kTile];
     __shared__ uint64_t s_u[kTile];
-    __shared__ uint8_t s_sel[2048];
+    __shared__ __align__(8) uint8_t s_sel[2048];
 
     const TileDesc td = tiles[tile_base + blockIdx.x];
     const InstDev& I = insts[td.inst];
     const int L = I.L;
     load_tables(I, s_log, s_invr, threadIdx.x, kTile, kMaxSites, true);
-    fill_select_table(s_sel, threadIdx.x, kTile);
+    load_select_table(s_sel, I.sel_tab, threadIdx.x, kTile);
     __syncthreads();
 
     StepConst C;
@@ -253,14 +253,14 @@ __global__ __launch_bounds__(kTile) void k_step_c(const InstDev* __restrict__ in
     __shared__ double s_ell[kTile];
     __shared__ uint32_t s_kb[kTile];
     __shared__ int s_wc[kTile / 64];
-    __shared__ uint8_t s_sel[2048];
+    __shared__ __align__(8) uint8_t s_sel[2048];
     __shared__ Pack<W> P;
 
     const TileDesc td = tiles[tile_base + blockIdx.x];
     const InstDev& I = insts[td.inst];
     const int L = I.L;
     load_tables(I, s_log, s_invr, threadIdx.x, kTile, 64 * W, true);
-    fill_select_table(s_sel, threadIdx.x, kTile);
+    load_select_table(s_sel, I.sel_tab, threadIdx.x, kTile);
 
     StepConst C;
     C.invr = s_invr; C.logt = s_log; C.sel = s_sel; C.inv_scale = I.inv_scale;
@@ -384,12 +384,12 @@ __global__ __launch_bounds__(64 * kQWaves) __attribute__((amdgpu_waves_per_eu(OC
     __shared__ double s_invr[kMaxSites + 1];
     __shared__ double s_ell[kQWaves][kTile];
     __shared__ int32_t s_from[kQWaves][kTile];
-    __shared__ uint8_t s_sel[2048];
+    __shared__ __align__(8) uint8_t s_sel[2048];
 
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     load_tables(insts[0], s_log, s_invr, threadIdx.x, 64 * kQWaves, kMaxSites, false);
-    fill_select_table(s_sel, threadIdx.x, 64 * kQWaves);
+    load_select_table(s_sel, insts[0].sel_tab, threadIdx.x, 64 * kQWaves);
     __syncthreads();
 
     double* sell = s_ell[wave];
