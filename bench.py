@@ -40,8 +40,8 @@ PEAK_HBM_GBS = 8000.0
 # VALU instructions in one pass of the event loop of the step kernel (W = 2),
 # counted from its gfx950 assembly by paper_1711_05095_amd.isa_count (a test
 # keeps this constant equal to that count).  It is the algorithmic work of an
-# event for every variant: the compacting variant's loop adds 8 instructions of
-# round bookkeeping, which count as overhead.
+# event for every variant (the compacting variant's loop has the same count;
+# its rounds' bookkeeping lies outside the loop and counts as overhead).
 VALU_PER_EVENT_W2 = 164
 VALU_PER_EVENT_W7 = 287   # the same loop for 400-site states (7 words)
 # HBM bytes the cloning stage must move per clone: ln Ups read (8) by the
