@@ -472,29 +472,44 @@ def test_batch_equals_separate():
 def test_split_launch_equals_unsplit(guided):
     """Four instances of 938 tiles each, in one context (a step launch of 3752
     tiles; the guided stage is then split in two, the clones past the event
-    budget finishing in a second launch) and each alone (one launch).  Every
-    result is the same bit for bit."""
+    budget finishing in a second launch), also restored from a mid-run
+    checkpoint, and each alone (one launch).  Every result is the same bit for
+    bit, and so are the carried origins of the run without a checkpoint."""
     from guide_tables import random_table
     specs = [(10, 5, 0.3, 0.1), (30, 14, -0.05, 0.5), (64, 30, 0.01, 0.3), (20, 9, 0.2, 0.4)]
     Nc, M = 240_000, 4
     mode = GUIDED if guided else MOD
-    params = [pd.make_params(L, N, s, Nc, M * dt, dt, seed=60 + i, instance=i, weight_mode=mode)
+    params = [pd.make_params(L, N, s, Nc, M * dt, dt, seed=60 + i, instance=i, weight_mode=mode,
+                             track_origin=1)
               for i, (L, N, s, dt) in enumerate(specs)]
     table = _guide_tensor(random_table(8)) if guided else None
     print(f"split vs unsplit guided={guided}", flush=True)
-    B = pd.Sampler(params)
-    if guided:
-        B.set_guide(table)
-    B.run(M)
-    for i, q in enumerate(params):
+
+    def sampler(q):
         S = pd.Sampler(q)
         if guided:
             S.set_guide(table)
+        for i in range(S.n):
+            S.reset_origin(i)
+        return S
+
+    B = sampler(params)
+    B.run(2)
+    blob = B.save()      # mid-run checkpoint: the event budget is part of it
+    B.run(M - 2)
+    R = sampler(params)
+    R.load(blob)
+    R.run(M - 2)
+    for i, q in enumerate(params):
+        S = sampler(q)
         S.run(M)
-        assert S.estimates() == B.estimates(i), i
-        ws, Ks = S.get_population()
-        wb, Kb = B.get_population(i)
-        assert np.array_equal(ws, wb) and np.array_equal(Ks, Kb), i
+        for X in (B, R):
+            assert S.estimates() == X.estimates(i), i
+            ws, Ks = S.get_population()
+            wb, Kb = X.get_population(i)
+            assert np.array_equal(ws, wb) and np.array_equal(Ks, Kb), i
+        # origins are not part of a checkpoint: compared for the run without one
+        assert np.array_equal(S.origin(), B.origin(i)), i
 
 
 def test_small_workload_matches_exact_diagonalisation():
