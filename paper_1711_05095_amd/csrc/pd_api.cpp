@@ -45,8 +45,6 @@ pd_tuning default_tuning()
     return t;
 }
 
-// Table of the device logarithm (rows of [c, -ln c (multiple of 2^-42),
-// remainder, 0]) and the split of ln 2, computed in extended precision.
 // Byte table of the device's bond selection: entry b * 8 + q is the position
 // of the q-th set bit (ascending) of the byte b for q < popcount(b), else 0.
 std::vector<uint8_t> select_table()
@@ -58,6 +56,8 @@ std::vector<uint8_t> select_table()
     return t;
 }
 
+// Table of the device logarithm (rows of [c, -ln c (multiple of 2^-42),
+// remainder, 0]) and the split of ln 2, computed in extended precision.
 std::vector<double> log_table(double* ln2_hi, double* ln2_lo)
 {
     const long double two42 = 4398046511104.0L;
