@@ -42,8 +42,8 @@ PEAK_HBM_GBS = 8000.0
 # keeps this constant equal to that count).  It is the algorithmic work of an
 # event for every variant (the compacting variant's loop has the same count;
 # its rounds' bookkeeping lies outside the loop and counts as overhead).
-VALU_PER_EVENT_W2 = 164
-VALU_PER_EVENT_W7 = 287   # the same loop for 400-site states (7 words)
+VALU_PER_EVENT_W2 = 160
+VALU_PER_EVENT_W7 = 285   # the same loop for 400-site states (7 words)
 # HBM bytes the cloning stage must move per clone: ln Ups read (8) by the
 # resample scan, ancestor written (4); the gather of the states is fused into
 # the next dynamical stage's load.
@@ -51,7 +51,7 @@ RESAMPLE_BYTES_PER_CLONE = 12
 # HBM bytes per launch of the step kernel on this workload, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE runs scaled by a plain 1 GiB copy (factors 2 and
 # 1), valid only for the kernel sources they were taken on (STEP_SOURCES).
-STEP_TRAFFIC = {"bytes": 236.5e6, "kernels_sha1": "9d0a9510fbd3", "kernel": "k_step_c<2>"}
+STEP_TRAFFIC = {"bytes": 236.0e6, "kernels_sha1": "cbfe0bb41f8b", "kernel": "k_step_c<2>"}
 STEP_SOURCES = ["pd_kernels.hip", "pd_tile.hpp", "pd_device.hpp", "pd_internal.hpp"]
 
 

@@ -57,7 +57,9 @@ std::vector<uint8_t> select_table()
 }
 
 // Table of the device logarithm (rows of [c, -ln c (multiple of 2^-42),
-// remainder, 0]) and the split of ln 2, computed in extended precision.
+// remainder]: row i covers m in [0.75 + 0.75 i/128, 0.75 + 0.75 (i+1)/128)
+// and c ~ 1/centre, exactly 1 on the row that holds 1) and the split of ln 2,
+// computed in extended precision.
 std::vector<double> log_table(double* ln2_hi, double* ln2_lo)
 {
     const long double two42 = 4398046511104.0L;
@@ -65,17 +67,19 @@ std::vector<double> log_table(double* ln2_hi, double* ln2_lo)
     const long double l2h = nearbyintl(l2 * two42) / two42;
     *ln2_hi = (double)l2h;
     *ln2_lo = (double)(l2 - l2h);
-    std::vector<double> t(4 * kLogRows, 0.0);
+    std::vector<double> t(kLogCols * kLogRows, 0.0);
+    const long double width = 0.75L / kLogRows;
     for (int i = 0; i < kLogRows; ++i) {
-        const long double lo = 0.75L + (long double)i / 128.0L;
-        const long double centre = lo + 1.0L / 256.0L;
-        // the two rows touching m = 1 use c = 1 so that r = m - 1 exactly
-        const double c = (i == 31 || i == 32) ? 1.0 : (double)(1.0L / centre);
+        const long double lo = 0.75L + (long double)i * width;
+        const long double centre = lo + width / 2;
+        // the row that holds m = 1 uses c = 1 so that r = m - 1 exactly
+        const bool one = lo <= 1.0L && 1.0L < lo + width;
+        const double c = one ? 1.0 : (double)(1.0L / centre);
         const long double nlc = -logl((long double)c);
         const long double hi = nearbyintl(nlc * two42) / two42;
-        t[4 * i] = c;
-        t[4 * i + 1] = (double)hi;
-        t[4 * i + 2] = (double)(nlc - hi);
+        t[kLogCols * i] = c;
+        t[kLogCols * i + 1] = (double)hi;
+        t[kLogCols * i + 2] = (double)(nlc - hi);
     }
     return t;
 }
@@ -169,7 +173,7 @@ Plan plan_of(const pd_params* p, int n)
     pl.tiles_off = at;
     at = align_up(at + sizeof(TileDesc) * (size_t)nt);
     pl.log_off = at;
-    at = align_up(at + sizeof(double) * 4 * kLogRows);
+    at = align_up(at + sizeof(double) * kLogCols * kLogRows);
     pl.sel_off = at;
     at = align_up(at + 2048);
     pl.invc_off = at;
@@ -358,7 +362,7 @@ pd_status pd_create(const pd_params* params, int32_t n, void* d_workspace, size_
         InstDev d;
         std::memset(&d, 0, sizeof d);
         d.L = p.L; d.N = p.N; d.W = words_of(p.L); d.mode = p.weight_mode;
-        for (int k = 0; k < 8; ++k) d.log_poly[k] = ((k & 1) ? -1.0 : 1.0) / (double)(9 - k);
+        for (int k = 0; k < kLogPoly; ++k) d.log_poly[k] = ((k & 1) ? -1.0 : 1.0) / (double)(7 - k);
         for (int k = 0; k < 14; ++k) {
             long double f = 1.0L;
             for (int q = 2; q <= 13 - k; ++q) f *= (long double)q;

@@ -43,39 +43,42 @@ __device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
     return make_uint4(c0, c1, c2, c3);
 }
 
-// u in (0, 1]: 53 bits of (a, b) plus one, times 2^-53.  Every step is exact.
-__device__ __forceinline__ double unit_open0(uint32_t a, uint32_t b)
+// X = 53 bits of (a, b) plus one, an integer in [1, 2^53]: the uniform
+// variate u = X 2^-53 in (0, 1] without its scale (log_unit takes the scale as
+// an exponent offset).  Every step is exact.
+__device__ __forceinline__ double unit_scaled(uint32_t a, uint32_t b)
 {
-    const double hi = (double)a * 2097152.0;          // a * 2^21, exact
-    const double lo = (double)(b >> 11) + 1.0;        // < 2^21 + 1, exact
-    return (hi + lo) * 0x1p-53;                       // < 2^53 + 1, exact
+    return fma((double)a, 2097152.0, (double)((b >> 11) + 1u));   // a 2^21 + lo <= 2^53
 }
 
-// ln u for u in (0, 1] (Tang's table-driven method).  u = m 2^e with m in
-// [0.75, 1.5); the table row i covers m in [0.75 + i/128, 0.75 + (i+1)/128)
-// and holds c ~ 1/centre (exactly 1 on the two rows touching 1, so ln u is
-// accurate to the last bit near u = 1), -ln c split into a part that is a
-// multiple of 2^-42 and a remainder.  With r = m c - 1 (one rounding, |r| <=
-// 2^-7), ln u = e ln2 - ln c + log1p(r); e*ln2_hi - ln c_hi is exact and
-// log1p(r) is its Taylor series to r^9, coefficients pc = 1/9, -1/8, ..., -1/2
-// (passed in as values uniform over the wave, so the fma take them from
-// scalar registers).  The result is within about one ulp.
-__device__ __forceinline__ double log_unit(double u, const double* __restrict__ tab,
-                                           double ln2_hi, double ln2_lo, const double (&pc)[8])
+// ln(x 2^-eoff) for x 2^-eoff in (0, 1] (Tang's table-driven method).  x =
+// m 2^e with m in [0.75, 1.5); the table row i covers m in [0.75 + 0.75 i/128,
+// 0.75 + 0.75 (i+1)/128) (the row index is rounded once, so m may lie an ulp
+// outside its row) and holds c ~ 1/centre (exactly 1 on the row that holds 1,
+// so the result is accurate to the last bit near 1), -ln c split into a part
+// that is a multiple of 2^-42 and a remainder.  With r = m c - 1 (one
+// rounding, |r| <= 2^-8), the logarithm is (e - eoff) ln2 - ln c + log1p(r);
+// (e - eoff) ln2_hi - ln c_hi is exact and log1p(r) is its Taylor series to
+// r^7, coefficients pc = 1/7, -1/6, ..., -1/2 (passed in as values uniform
+// over the wave, so the fma take them from scalar registers; the truncation is
+// below 2^-59 relative).  The result is within about one ulp.
+__device__ __forceinline__ double log_unit(double x, const double* __restrict__ tab,
+                                           double ln2_hi, double ln2_lo,
+                                           const double (&pc)[kLogPoly], int eoff)
 {
-    const int e0 = __builtin_amdgcn_frexp_exp(u);
-    const double f = __builtin_amdgcn_frexp_mant(u);   // [0.5, 1)
+    const int e0 = __builtin_amdgcn_frexp_exp(x);
+    const double f = __builtin_amdgcn_frexp_mant(x);   // [0.5, 1)
     const bool low = f < 0.75;
     const double m = low ? f * 2.0 : f;                 // [0.75, 1.5), exact
-    const double e = (double)(low ? e0 - 1 : e0);
-    const int i = (int)fma(m, 128.0, -96.0);            // exact, then truncated
-    const double c = tab[4 * i];
-    const double nlc_hi = tab[4 * i + 1];
-    const double nlc_lo = tab[4 * i + 2];
+    const double e = (double)(e0 - eoff - (low ? 1 : 0));
+    const int i = (int)fma(m, 128.0 / 0.75, -128.0);   // in [0, 127]
+    const double c = tab[kLogCols * i];
+    const double nlc_hi = tab[kLogCols * i + 1];
+    const double nlc_lo = tab[kLogCols * i + 2];
     const double r = fma(m, c, -1.0);
     double p = pc[0];
 #pragma unroll
-    for (int k = 1; k < 8; ++k) p = fma(p, r, pc[k]);
+    for (int k = 1; k < kLogPoly; ++k) p = fma(p, r, pc[k]);
     const double l1p = fma(r * r, p, r);
     const double t = fma(e, ln2_hi, nlc_hi);            // exact
     return t + (fma(e, ln2_lo, nlc_lo) + l1p);

@@ -84,7 +84,7 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
                                                   int budgeted)
 {
     __shared__ __align__(16) uint32_t s_eg[kGuideCompact];
-    __shared__ double s_log[kLogRows * 4];
+    __shared__ double s_log[kLogRows * kLogCols];
     __shared__ __align__(8) uint8_t s_sel[2048];
 
     const TileDesc td = tiles[tile_base + blockIdx.x];
@@ -94,7 +94,7 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
     const uint32_t ncont = CONT ? I.ctl->ncont : 0u;
     const uint32_t e0 = (uint32_t)td.tile * kTile;   // first handed-on clone of the block
     if (CONT && e0 >= ncont) return;                  // uniform over the block
-    for (int i = threadIdx.x; i < kLogRows * 4; i += kTile) s_log[i] = gptr(I.log_tab)[i];
+    for (int i = threadIdx.x; i < kLogRows * kLogCols; i += kTile) s_log[i] = gptr(I.log_tab)[i];
     load_select_table(s_sel, I.sel_tab, threadIdx.x, kTile);
     for (int i = threadIdx.x; i < kGuideCompact; i += kTile) {
         const uint32_t b6 = (i >> 6) & 1u;
@@ -109,9 +109,9 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
     const uint32_t c3 = TAG_GUIDE | I.tag_hi, cp = TAG_GUIDE_PROP | I.tag_hi;
     const double es = I.es, dt = I.dt;
     const uint64_t egmax = I.guide_max;
-    double poly[8];   // log1p coefficients as uniform operands
+    double poly[kLogPoly];   // log1p coefficients as uniform operands
 #pragma unroll
-    for (int w = 0; w < 8; ++w) poly[w] = I.log_poly[w];
+    for (int w = 0; w < kLogPoly; ++w) poly[w] = I.log_poly[w];
     const int dst = src ^ 1;
     const int lb = (L - 1) & 63;
 
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
         }
         const uint4 y = philox10(k, (uint32_t)j, beta, c3, I.key0, I.key1);
         ++k;
-        const double E = -log_unit(unit_open0(y.x, y.y), s_log, I.ln2_hi, I.ln2_lo, poly);
+        const double E = -log_unit(unit_scaled(y.x, y.y), s_log, I.ln2_hi, I.ln2_lo, poly, 53);
         const double R = es * ((double)S * 0x1p-16);
         const double w = E / R;
         if (tau + w >= dt) {
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
         return;
     }
     // sum_jumps ln(eg 2^-16) = ln P + (pexp - 16 kb) ln 2
-    const double G = log_unit(P, s_log, I.ln2_hi, I.ln2_lo, poly) +
+    const double G = log_unit(P, s_log, I.ln2_hi, I.ln2_lo, poly, 0) +
                      (double)(pexp - 16 * (int)kb) * (I.ln2_hi + I.ln2_lo);
     const double ell = -G - (A - (es * 0x1p-16) * AS);
 #pragma unroll

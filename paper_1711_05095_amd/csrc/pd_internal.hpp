@@ -9,7 +9,9 @@ namespace pd {
 constexpr int kTile = 256;          // clones per tile = threads per block
 constexpr int kMaxWords = 8;        // 64-site words per state
 constexpr int kMaxSites = 512;      // L <= kMaxSites
-constexpr int kLogRows = 96;        // rows of the logarithm table
+constexpr int kLogRows = 128;       // rows of the logarithm table
+constexpr int kLogCols = 3;         // c, -ln c (multiple of 2^-42), remainder
+constexpr int kLogPoly = 6;         // log1p coefficients 1/7, -1/6, ..., -1/2
 
 enum : uint32_t { TAG_INIT = 1, TAG_DYN = 2, TAG_RESAMPLE = 3, TAG_IID = 4, TAG_GUIDE = 5,
                   TAG_GUIDE_PROP = 6 };
@@ -57,10 +59,10 @@ struct InstDev {
     double* log;           // [log_cycles][2] (lbeta, mean K^beta)
     const uint32_t* guide; // [8192] guide table e^g 2^16 over bond neighbourhoods
     uint64_t guide_max;    // largest table entry (acceptance bound)
-    const double* log_tab; // [kLogRows][4] table of the device logarithm
+    const double* log_tab; // [kLogRows][kLogCols] table of the device logarithm
     const uint8_t* sel_tab;// [2048] byte table of select_bit_lut (shared)
     double ln2_hi, ln2_lo; // ln 2 = ln2_hi (a multiple of 2^-42) + ln2_lo
-    double log_poly[8];    // 1/9, -1/8, ..., -1/2: Taylor coefficients of log1p (uniform
+    double log_poly[kLogPoly]; // 1/7, -1/6, ..., -1/2: Taylor coefficients of log1p (uniform
                            // operands, so the polynomial's fma take them from SGPRs)
     double exp_poly[14];   // 1/13!, 1/12!, ..., 1/1!, 1: Taylor coefficients of exp (uniform)
     InstCtl* ctl;

@@ -108,7 +108,7 @@ struct StepConst {
     const uint8_t* sel;    // LDS: byte table of select_bit_lut
     double inv_scale;      // 1 / rate of one allowed hop
     double dt, ln2_hi, ln2_lo;
-    double poly[8];        // log1p coefficients (uniform)
+    double poly[kLogPoly]; // log1p coefficients (uniform)
     uint32_t beta, c3, key0, key1;
     int L, lb;
 };
@@ -125,7 +125,7 @@ __device__ __forceinline__ bool one_event(const StepConst& C, uint32_t slot, uin
     if (r == 0) return true;
     const uint4 y = philox10(k, slot, C.beta, C.c3, C.key0, C.key1);
     ++k;
-    const double E = -log_unit(unit_open0(y.x, y.y), C.logt, C.ln2_hi, C.ln2_lo, C.poly);
+    const double E = -log_unit(unit_scaled(y.x, y.y), C.logt, C.ln2_hi, C.ln2_lo, C.poly, 53);
     // waiting time E / R with R = (rate of one hop) * r
     const double w = E * (SCALED ? C.invr[r] : C.inv_scale * C.invr[r]);
     if (tau + w >= C.dt || k >= 0x80000000u) {
@@ -149,7 +149,7 @@ __device__ __forceinline__ bool one_event(const StepConst& C, uint32_t slot, uin
 __device__ __forceinline__ void load_tables(const InstDev& I, double* s_log, double* s_invr,
                                             int tid, int nthr, int rmax, bool scaled)
 {
-    for (int i = tid; i < kLogRows * 4; i += nthr) s_log[i] = gptr(I.log_tab)[i];
+    for (int i = tid; i < kLogRows * kLogCols; i += nthr) s_log[i] = gptr(I.log_tab)[i];
     const double sc = I.inv_scale;
     for (int i = tid; i <= rmax; i += nthr)
         s_invr[i] = scaled ? sc * gptr(I.inv_count)[i] : gptr(I.inv_count)[i];
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(kTile) void k_step(const InstDev* __restrict__ inst
                                                 int src, int use_anc)
 {
     __shared__ double s_invr[kMaxSites + 1];
-    __shared__ double s_log[kLogRows * 4];
+    __shared__ double s_log[kLogRows * kLogCols];
     __shared__ double s_ell[kTile];
     __shared__ uint64_t s_u[kTile];
     __shared__ __align__(8) uint8_t s_sel[2048];
@@ -180,7 +180,7 @@ __global__ __launch_bounds__(kTile) void k_step(const InstDev* __restrict__ inst
     C.invr = s_invr; C.logt = s_log; C.sel = s_sel; C.inv_scale = I.inv_scale;
     C.dt = I.dt; C.ln2_hi = I.ln2_hi; C.ln2_lo = I.ln2_lo;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) C.poly[k] = I.log_poly[k];
+    for (int k = 0; k < kLogPoly; ++k) C.poly[k] = I.log_poly[k];
     C.beta = (uint32_t)(I.ctl->beta + 1); C.c3 = TAG_DYN | I.tag_hi;
     C.key0 = I.key0; C.key1 = I.key1; C.L = L; C.lb = (L - 1) & 63;
 
@@ -249,7 +249,7 @@ __global__ __launch_bounds__(kTile) void k_step_c(const InstDev* __restrict__ in
                                                   int first16)
 {
     __shared__ double s_invr[64 * W + 1];     // r <= L <= 64 W
-    __shared__ double s_log[kLogRows * 4];
+    __shared__ double s_log[kLogRows * kLogCols];
     __shared__ double s_ell[kTile];
     __shared__ uint32_t s_kb[kTile];
     __shared__ int s_wc[kTile / 64];
@@ -266,7 +266,7 @@ __global__ __launch_bounds__(kTile) void k_step_c(const InstDev* __restrict__ in
     C.invr = s_invr; C.logt = s_log; C.sel = s_sel; C.inv_scale = I.inv_scale;
     C.dt = I.dt; C.ln2_hi = I.ln2_hi; C.ln2_lo = I.ln2_lo;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) C.poly[k] = I.log_poly[k];
+    for (int k = 0; k < kLogPoly; ++k) C.poly[k] = I.log_poly[k];
     C.beta = (uint32_t)(I.ctl->beta + 1); C.c3 = TAG_DYN | I.tag_hi;
     C.key0 = I.key0; C.key1 = I.key1; C.L = L; C.lb = (L - 1) & 63;
 
@@ -380,7 +380,7 @@ __global__ __launch_bounds__(64 * kQWaves) __attribute__((amdgpu_waves_per_eu(OC
                                                          uint32_t* __restrict__ counter,
                                                          int src, int use_anc, int refill)
 {
-    __shared__ double s_log[kLogRows * 4];
+    __shared__ double s_log[kLogRows * kLogCols];
     __shared__ double s_invr[kMaxSites + 1];
     __shared__ double s_ell[kQWaves][kTile];
     __shared__ int32_t s_from[kQWaves][kTile];
@@ -415,7 +415,7 @@ __global__ __launch_bounds__(64 * kQWaves) __attribute__((amdgpu_waves_per_eu(OC
         C.invr = s_invr; C.logt = s_log; C.sel = s_sel; C.inv_scale = I.inv_scale;
         C.dt = I.dt; C.ln2_hi = I.ln2_hi; C.ln2_lo = I.ln2_lo;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) C.poly[k] = I.log_poly[k];
+        for (int k = 0; k < kLogPoly; ++k) C.poly[k] = I.log_poly[k];
         C.beta = (uint32_t)(I.ctl->beta + 1); C.c3 = TAG_DYN | I.tag_hi;
         C.key0 = I.key0; C.key1 = I.key1; C.L = L; C.lb = (L - 1) & 63;
         const auto st_src = gptr(I.state[src]);
