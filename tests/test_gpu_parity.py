@@ -284,6 +284,46 @@ def test_guided_cycles_bit_exact(L, N, s, Nc, table_seed):
         occ, K = np.ascontiguousarray(occ[anc]), K[anc]
 
 
+def test_twenty_million_clones_sampled():
+    """Nc = 2e7 (78125 tiles: 31-bit slot arithmetic, the prefix kernel's path
+    that re-reads its tiles, interval ends up to 2e7 spacings): 2000 sampled
+    clones stepped by the oracle; the selection by its defining properties
+    (a non-decreasing map, every clone copied floor or ceil of Nc w_k / sum w
+    times), since the oracle's own sequential sum of 2e7 weights is only good
+    to ~0.04 spacings here; psi against the exactly rounded sum of the GPU's
+    weights."""
+    import math
+    L, N, s, Nc, dt = 10, 5, 0.3, 20_000_000, 0.1
+    print(f"large population L={L} Nc={Nc}", flush=True)
+    p, o = make(L, N, s, Nc, dt, M=4, seed=77)
+    S = pd.Sampler(p)
+    S.run(2)
+    words, K = S.get_population()
+    rng = np.random.default_rng(9)
+    slots = np.sort(rng.choice(Nc, 2000, replace=False))
+    occ_s = unpack(words[:, slots], L)
+    K_s = K[slots].copy()
+    psi2 = S.estimates()["psi"] * 2 * dt
+    S.step()
+    w_gpu, K_gpu = S.get_population()
+    Kb_g, A_g, ell_g = S.step_outputs()
+    Kb_o, A_o, ell_o = o.step_slots(3, slots, occ_s, K_s)
+    assert np.array_equal(Kb_g[slots], Kb_o)
+    assert np.array_equal(w_gpu[:, slots], pack(occ_s))
+    assert np.array_equal(K_gpu[slots], K_s)
+    assert np.allclose(ell_g[slots], ell_o, rtol=1e-12, atol=1e-300)
+    S.resample()
+    anc = S.ancestors()
+    assert np.all(np.diff(anc) >= 0) and anc[0] >= 0 and anc[-1] < Nc
+    counts = np.bincount(anc, minlength=Nc)
+    wgt = np.exp(ell_g - ell_g.max())
+    mean = Nc * wgt / wgt.sum()
+    assert np.all(counts >= np.floor(mean - 1e-6)) and np.all(counts <= np.ceil(mean + 1e-6))
+    exact = ell_g.max() + math.log(math.fsum(wgt) / Nc)
+    lb3 = S.estimates()["psi"] * 3 * dt - psi2
+    assert lb3 == pytest.approx(exact, rel=1e-10, abs=1e-12)
+
+
 def test_guided_full_size_sampled():
     """A guided launch large enough to be split in two (3907 tiles): the third
     cycle runs with an event budget from the second, so clones are handed on to
