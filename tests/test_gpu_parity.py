@@ -324,14 +324,15 @@ def test_twenty_million_clones_sampled():
     assert lb3 == pytest.approx(exact, rel=1e-10, abs=1e-12)
 
 
-def test_guided_full_size_sampled():
-    """A guided launch large enough to be split in two (3907 tiles): the third
-    cycle runs with an event budget from the second, so clones are handed on to
-    the second launch; 2000 sampled clones stepped by the oracle, bit-exact, and
-    the selection (which reads the third launch's tile aggregates) checked
-    against the oracle's on the GPU's log-weights."""
+@pytest.mark.parametrize("L,N,s,dt", [(100, 50, 0.002, 0.5), (400, 200, 1e-4, 1.0)])
+def test_guided_full_size_sampled(L, N, s, dt):
+    """A guided launch large enough to be split in two (3907 tiles), with 2- and
+    7-word states: the third cycle runs with an event budget from the second,
+    so clones are handed on to the second launch; 2000 sampled clones stepped
+    by the oracle, bit-exact, and the selection (which reads the third launch's
+    tile aggregates) checked against the oracle's on the GPU's log-weights."""
     from guide_tables import random_table
-    L, N, s, Nc, dt = 100, 50, 0.002, 1_000_000, 0.5
+    Nc = 1_000_000
     print(f"guided full size L={L} Nc={Nc}", flush=True)
     table = random_table(6)
     p = pd.make_params(L, N, s, Nc, 10 * dt, dt, seed=41, weight_mode=GUIDED)
