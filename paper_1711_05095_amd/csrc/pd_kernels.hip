@@ -356,7 +356,9 @@ __global__ __launch_bounds__(kTile) void k_step_c(const InstDev* __restrict__ in
             r = popcount_words<W>(m);
         }
         __syncthreads();
-        budget = later;
+        // once the unfinished clones fit in one wave no pack can empty another:
+        // that wave runs them to the end in one round
+        budget = total <= 64 ? 0x7FFFFFFF : later;
     }
     if (tid < 64) {
         uint64_t h = 0;
