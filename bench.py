@@ -51,7 +51,7 @@ RESAMPLE_BYTES_PER_CLONE = 12
 # HBM bytes per launch of the step kernel on this workload, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE runs scaled by a plain 1 GiB copy (factors 2 and
 # 1), valid only for the kernel sources they were taken on (STEP_SOURCES).
-STEP_TRAFFIC = {"bytes": 236.0e6, "kernels_sha1": "cbfe0bb41f8b", "kernel": "k_step_c<2>"}
+STEP_TRAFFIC = {"bytes": 239.9e6, "kernels_sha1": "f643ba6df47a", "kernel": "k_step_c<2>"}
 STEP_SOURCES = ["pd_kernels.hip", "pd_tile.hpp", "pd_device.hpp", "pd_internal.hpp"]
 
 
