@@ -71,12 +71,11 @@ __device__ __forceinline__ uint64_t guided_total(const uint64_t (&x)[W], const u
 // small, see kSplitTiles).  CONT = false: one clone per lane, at most
 // ev_budget events (about 1.1 times the mean of the previous interval); a
 // clone not done by then is handed on, registers and slot, to the second
-// launch.  CONT = true: block b of an instance's tiles
-// takes the handed-on clones 256 b .. 256 b + 255 (in hand-on order) and runs
-// each to the end of the interval, so a wave of the first launch never waits
-// for the Poisson tail of its 64 clones.  Random numbers are keyed by slot and
-// by the event and proposal indices the clone carries, so the split changes
-// no result.
+// launch.  CONT = true: block b of an instance's tiles takes the handed-on
+// clones 256 b .. 256 b + 255 (in hand-on order) and runs each to the end of
+// the interval, so a wave of the first launch never waits for the Poisson
+// tail of its 64 clones.  Random numbers are keyed by slot and by the event
+// and proposal indices the clone carries, so the split changes no result.
 template <int W, bool CONT>
 __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ insts,
                                                   const TileDesc* __restrict__ tiles,
