@@ -271,7 +271,7 @@ pd_status apply_tuning(pd_ctx* ctx, const pd_tuning& t)
     PD_HIP(hipGetDevice(&dev));
     PD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     for (auto& g : ctx->steps) {
-        // the guided stage has one kernel; the queued variants do not carry origins
+        // the guided stage has no variants; the queued variants do not carry origins
         g.variant = g.guided ? 0
                   : (ctx->any_origin && t.step_variant >= 1 && t.step_variant <= 3) ? 0
                   : t.step_variant;
