@@ -284,6 +284,45 @@ def test_guided_cycles_bit_exact(L, N, s, Nc, table_seed):
         occ, K = np.ascontiguousarray(occ[anc]), K[anc]
 
 
+def test_full_size_iid_direct_sampled():
+    """Direct weights (e^{-s K}) and [iid] selection at Nc = 1e6: 2000 sampled
+    clones stepped by the oracle, bit-exact; every new slot's point (the
+    oracle's [iid] points) lies in the interval of the clone the GPU chose,
+    with the intervals from a long-double cumulative sum of the GPU's weights
+    and a tolerance of 1e-6 spacings (the GPU's two-level FP64 scan is good to
+    ~2e-7 here, the oracle's sequential one only to ~1e-4)."""
+    L, N, lam, Nc, dt = 100, 50, 20.0, 1_000_000, 0.5
+    s = inputs.s_of_lambda(lam, L)
+    print(f"full size iid direct L={L} Nc={Nc}", flush=True)
+    p, o = make(L, N, s, Nc, dt, M=10, seed=2025, mode=DIR, sel=IID)
+    S = pd.Sampler(p)
+    S.run(3)
+    words, K = S.get_population()
+    rng = np.random.default_rng(1)
+    slots = np.sort(rng.choice(Nc, 2000, replace=False))
+    occ_s = unpack(words[:, slots], L)
+    K_s = K[slots].copy()
+    S.step()
+    w_gpu, K_gpu = S.get_population()
+    Kb_g, A_g, ell_g = S.step_outputs()
+    Kb_o, A_o, ell_o = o.step_slots(4, slots, occ_s, K_s)
+    assert np.array_equal(Kb_g[slots], Kb_o)
+    assert np.array_equal(w_gpu[:, slots], pack(occ_s))
+    assert np.array_equal(K_gpu[slots], K_s)
+    assert np.allclose(ell_g[slots], ell_o, rtol=1e-12, atol=1e-300)
+    S.resample()
+    anc = S.ancestors().astype(np.int64)
+    assert anc.min() >= 0 and anc.max() < Nc
+    pts = o.iid_points(4)
+    w = np.exp((ell_g - ell_g.max()).astype(np.longdouble))
+    y = np.cumsum(w)
+    y = y * Nc / y[-1]
+    lo = np.where(anc > 0, y[np.maximum(anc - 1, 0)], 0.0)
+    hi = np.where(anc < Nc - 1, y[anc], np.inf)
+    tol = 1e-6
+    assert np.all(lo - tol <= pts) and np.all(pts < hi + tol)
+
+
 def test_twenty_million_clones_sampled():
     """Nc = 2e7 (78125 tiles: 31-bit slot arithmetic, the prefix kernel's path
     that re-reads its tiles, interval ends up to 2e7 spacings): 2000 sampled
