@@ -8,7 +8,10 @@
     distribution p_end of Sec. 2.4);
   * ancestral_mean: the average over the current clones of a value recorded
     for their ancestors at an earlier time (the ancestral distribution p_ave
-    of Sec. 2.4, eq. Opave), given each clone's origin slot.
+    of Sec. 2.4, eq. Opave), given each clone's origin slot;
+  * histogram: counts of a per-clone quantity in equal bins, over the current
+    clones (p_end) or over their ancestors (p_ave), as the distributions of
+    Sec. 2.4 are shown (the activity distributions of Sec. 5).
 """
 import numpy as np
 
@@ -30,3 +33,17 @@ def ancestral_mean(values_at_origin, origin):
     """(1/Nc) sum_j values[origin[j]]."""
     v = np.asarray(values_at_origin, np.float64)
     return float(np.mean(v[np.asarray(origin)]))
+
+
+def histogram(values, lo, width, nbins, origin=None):
+    """counts[b] = #{j : floor((v_j - lo) / width) = b}, b = 0..nbins-1, with
+    v_j = values[j], or values[origin[j]] when origins are given; values whose
+    (v - lo) / width lies outside [0, nbins), and NaN, are not counted.  The
+    bin is decided by one FP64 subtraction and one FP64 division, then the
+    floor."""
+    v = np.asarray(values, np.float64)
+    if origin is not None:
+        v = v[np.asarray(origin)]
+    t = (v - np.float64(lo)) / np.float64(width)
+    keep = (t >= 0) & (t < nbins)
+    return np.bincount(np.floor(t[keep]).astype(np.int64), minlength=nbins).astype(np.uint64)
