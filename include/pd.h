@@ -189,6 +189,20 @@ pd_status pd_density_mode(pd_ctx* ctx, int32_t inst, int32_t n, double* d_out);
 pd_status pd_mean(pd_ctx* ctx, int32_t inst, const double* d_values, int32_t ancestral,
                   double* mean);
 
+/* Histogram of a per-clone quantity, as the distributions p_end and p_ave of
+ * Sec. 2.4 are shown (the activity distributions of Sec. 5): d_counts[b] =
+ * #{j : floor((v_j - lo) / width) = b} for b = 0 .. nbins-1, with v_j as in
+ * pd_mean (d_values[j], or d_values[origin_j] when ancestral = 1, which needs
+ * track_origin).  The bin is decided by one FP64 subtraction and one FP64
+ * division, then the floor; values outside [lo, lo + nbins width) and NaN
+ * are not counted.  d_values: caller-owned device array of Nc doubles;
+ * d_counts: caller-owned device array of nbins uint64, overwritten.
+ * 1 <= nbins <= 4096, lo finite, width finite and > 0; PD_EINVAL otherwise,
+ * PD_ESTATE between pd_step and pd_resample.  Queued on the context stream
+ * (no synchronisation). */
+pd_status pd_histogram(pd_ctx* ctx, int32_t inst, const double* d_values, int32_t ancestral,
+                       double lo, double width, int32_t nbins, uint64_t* d_counts);
+
 /* Per-interval log of instance `inst` (params.log_cycles > 0): for interval
  * beta = 1..n_rows, lbeta[beta-1] = ln((1/Nc) sum_i Upsilon_i^beta) and
  * mean_kb[beta-1] = population mean of K^beta before cloning.  Synchronises. */

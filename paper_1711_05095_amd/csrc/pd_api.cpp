@@ -898,6 +898,26 @@ pd_status pd_mean(pd_ctx* ctx, int32_t inst, const double* d_values, int32_t anc
     return PD_OK;
 }
 
+pd_status pd_histogram(pd_ctx* ctx, int32_t inst, const double* d_values, int32_t ancestral,
+                       double lo, double width, int32_t nbins, uint64_t* d_counts)
+{
+    pd_status st = check_inst(ctx, inst);
+    if (st != PD_OK) return st;
+    if (!d_values || !d_counts) return fail(ctx, PD_EINVAL, "null argument");
+    if (ancestral != 0 && ancestral != 1) return fail(ctx, PD_EINVAL, "ancestral must be 0 or 1");
+    if (nbins < 1 || nbins > kMaxHistBins) return fail(ctx, PD_EINVAL, "nbins must be in [1, 4096]");
+    if (!std::isfinite(lo) || !(width > 0.0) || !std::isfinite(width))
+        return fail(ctx, PD_EINVAL, "lo must be finite and width finite and positive");
+    if (ancestral && !ctx->dev[inst].origin[0])
+        return fail(ctx, PD_ESTATE, "instance does not track origins");
+    if (ctx->stepped) return fail(ctx, PD_ESTATE, "observable between pd_step and pd_resample");
+    st = materialise(ctx);
+    if (st != PD_OK) return st;
+    PD_HIP(launch_histogram(ctx->d_insts, inst, ctx->params[inst].Nc, ctx->cur, d_values,
+                            ancestral, lo, width, nbins, d_counts, ctx->stream));
+    return PD_OK;
+}
+
 pd_status pd_get_tuning(pd_ctx* ctx, pd_tuning* out)
 {
     if (!ctx || !out) return PD_EINVAL;

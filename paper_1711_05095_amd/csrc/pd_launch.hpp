@@ -32,6 +32,10 @@ constexpr int kSplitTiles = 2 * 7 * 256;
 hipError_t launch_step_guided(int W, int count, const InstDev* insts, const TileDesc* tiles,
                               int base, int src, int use_anc, hipStream_t st);
 hipError_t step_occupancy(int W, int variant, int* blocks_per_cu);
+constexpr int kMaxHistBins = 4096;   // bins of pd_histogram (LDS counters per block)
+hipError_t launch_histogram(const InstDev* insts, int inst, int64_t Nc, int cur,
+                            const double* values, int ancestral, double lo, double width,
+                            int nbins, uint64_t* counts, hipStream_t st);
 hipError_t launch_density_mode(int W, const InstDev* insts, int inst, int64_t Nc, int cur, int n,
                                double* out, hipStream_t st);
 hipError_t launch_mean(const InstDev* insts, int inst, int64_t Nc, int cur, const double* values,

@@ -1,8 +1,8 @@
 // Observables over a population (arXiv:1711.05095, Secs. 2.4 and 3.3): the
 // squared modulus of a Fourier mode of the density (eq. fourdens) per clone,
-// and the mean of a per-clone quantity over the current population (the
-// end-time distribution) or over the ancestors of the current population at
-// the last origin reset (the ancestral distribution, eq. Opave).
+// and the mean and the histogram of a per-clone quantity over the current
+// population (the end-time distribution) or over the ancestors of the current
+// population at the last origin reset (the ancestral distribution, eq. Opave).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -77,6 +77,37 @@ __global__ __launch_bounds__(kTile) void k_mean_final(const InstDev* __restrict_
     if (threadIdx.x == 0) gptr(I.tile_off)[0] = v / (double)I.Nc;
 }
 
+__global__ void k_zero_u64(uint64_t* __restrict__ a, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = 0;
+}
+
+// counts[b] += #{j : floor((v_j - lo) / width) = b}, v_j = values[j] (or
+// values[origin[j]] when ancestral); each block counts its clones in LDS and
+// adds its nonzero bins to the global counts (integer sums: the result does
+// not depend on the order).
+__global__ __launch_bounds__(kTile) void k_histogram(const InstDev* __restrict__ insts, int inst,
+                                                     int cur, const double* __restrict__ values,
+                                                     int ancestral, double lo, double width,
+                                                     int nbins, uint64_t* __restrict__ counts)
+{
+    __shared__ uint32_t s_c[kMaxHistBins];
+    const InstDev& I = insts[inst];
+    for (int b = threadIdx.x; b < nbins; b += kTile) s_c[b] = 0;
+    __syncthreads();
+    const int64_t Nc = I.Nc;
+    for (int64_t j = (int64_t)blockIdx.x * kTile + threadIdx.x; j < Nc;
+         j += (int64_t)gridDim.x * kTile) {
+        const double v = values[ancestral ? (int64_t)gptr(I.origin[cur])[j] : j];
+        const double t = (v - lo) / width;
+        if (t >= 0.0 && t < (double)nbins) atomicAdd(&s_c[(int)t], 1u);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nbins; b += kTile)
+        if (s_c[b]) atomicAdd((unsigned long long*)&counts[b], (unsigned long long)s_c[b]);
+}
+
 hipError_t launch_density_mode(int W, const InstDev* insts, int inst, int64_t Nc, int cur, int n,
                                double* out, hipStream_t st)
 {
@@ -102,6 +133,19 @@ hipError_t launch_mean(const InstDev* insts, int inst, int64_t Nc, int cur, cons
     hipLaunchKernelGGL(k_mean_partial, dim3(nb), dim3(kTile), 0, st, insts, inst, cur, values,
                        ancestral);
     hipLaunchKernelGGL(k_mean_final, dim3(1), dim3(kTile), 0, st, insts, inst, nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_histogram(const InstDev* insts, int inst, int64_t Nc, int cur,
+                            const double* values, int ancestral, double lo, double width,
+                            int nbins, uint64_t* counts, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_zero_u64, dim3((nbins + kTile - 1) / kTile), dim3(kTile), 0, st, counts,
+                       nbins);
+    const int64_t need = (Nc + kTile - 1) / kTile;
+    const int blocks = (int)(need < 2048 ? need : 2048);
+    hipLaunchKernelGGL(k_histogram, dim3(blocks), dim3(kTile), 0, st, insts, inst, cur, values,
+                       ancestral, lo, width, nbins, counts);
     return hipGetLastError();
 }
 

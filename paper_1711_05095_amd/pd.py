@@ -24,7 +24,7 @@ EXPORTS = ["pd_workspace_bytes", "pd_create", "pd_destroy", "pd_step", "pd_resam
            "pd_scgf", "pd_estimates_get", "pd_population_bytes", "pd_get_population",
            "pd_set_population", "pd_get_step_outputs", "pd_get_ancestors", "pd_get_log",
            "pd_save_bytes", "pd_save", "pd_load", "pd_set_guide", "pd_reset_origin",
-           "pd_get_origin", "pd_density_mode", "pd_mean", "pd_get_tuning",
+           "pd_get_origin", "pd_density_mode", "pd_mean", "pd_histogram", "pd_get_tuning",
            "pd_set_tuning", "pd_autotune", "pd_last_error", "pd_status_str"]
 
 
@@ -90,6 +90,7 @@ def lib():
             "pd_get_origin": [vp, c.c_int32, vp],
             "pd_density_mode": [vp, c.c_int32, c.c_int32, vp],
             "pd_mean": [vp, c.c_int32, vp, c.c_int32, P(c.c_double)],
+            "pd_histogram": [vp, c.c_int32, vp, c.c_int32, c.c_double, c.c_double, c.c_int32, vp],
             "pd_get_tuning": [vp, P(PdTuning)],
             "pd_set_tuning": [vp, P(PdTuning)],
             "pd_autotune": [vp, c.c_int32, P(PdTuning)],
@@ -241,6 +242,11 @@ def pd_density_mode(ctx, inst, n, out_ptr):
     _check(lib().pd_density_mode(ctx, inst, int(n), ctypes.c_void_p(out_ptr)), ctx)
 
 
+def pd_histogram(ctx, inst, values_ptr, ancestral, lo, width, nbins, counts_ptr):
+    _check(lib().pd_histogram(ctx, inst, ctypes.c_void_p(values_ptr), int(ancestral), float(lo),
+                              float(width), int(nbins), ctypes.c_void_p(counts_ptr)), ctx)
+
+
 def pd_mean(ctx, inst, values_ptr, ancestral):
     m = ctypes.c_double()
     _check(lib().pd_mean(ctx, inst, ctypes.c_void_p(values_ptr), int(ancestral),
@@ -376,6 +382,21 @@ class Sampler:
         # the library reads values on its own stream
         torch.cuda.current_stream().synchronize()
         return pd_mean(self.ctx, inst, values.data_ptr(), 1 if ancestral else 0)
+
+    def histogram(self, values, lo, width, nbins, ancestral=False, inst=0):
+        """Counts of floor((v_j - lo) / width) in bins 0..nbins-1 over the clones,
+        v_j = values[j], or values[origin_j] when ancestral; values is a float64
+        CUDA tensor of Nc entries.  Returns a numpy uint64 array."""
+        import torch
+        if values.dtype != torch.float64 or not values.is_cuda or not values.is_contiguous() \
+                or values.numel() < self.params[inst].Nc:
+            raise TypeError("values must be a contiguous float64 CUDA tensor of Nc entries")
+        counts = torch.empty(max(int(nbins), 1), dtype=torch.int64, device=values.device)
+        torch.cuda.current_stream().synchronize()   # values and counts, on torch's stream
+        pd_histogram(self.ctx, inst, values.data_ptr(), 1 if ancestral else 0, lo, width, nbins,
+                     counts.data_ptr())
+        self.stream.synchronize()                   # written on the sampler's stream
+        return counts.cpu().numpy().view(np.uint64)
 
     def tuning(self):
         return pd_get_tuning(self.ctx)

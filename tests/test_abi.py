@@ -131,3 +131,14 @@ def test_create_rejects_without_device_work():
     # misaligned workspace pointer
     assert pd.lib().pd_create(arr, 1, ctypes.c_void_p(8), 1 << 40, None,
                               ctypes.byref(ctx)) == pd.PD_EINVAL
+
+
+def test_context_calls_reject_a_null_context():
+    """Calls on a context return PD_EINVAL for a null one, before anything
+    reaches the GPU."""
+    lib = pd.lib()
+    fake = ctypes.c_void_p(256)
+    assert lib.pd_histogram(None, 0, fake, 0, 0.0, 1.0, 10, fake) == pd.PD_EINVAL
+    m = ctypes.c_double()
+    assert lib.pd_mean(None, 0, fake, 0, ctypes.byref(m)) == pd.PD_EINVAL
+    assert lib.pd_density_mode(None, 0, 1, fake) == pd.PD_EINVAL

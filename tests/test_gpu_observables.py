@@ -1,8 +1,8 @@
 """Observables over the population through the C ABI (pd_density_mode,
-pd_mean) against the plain definitions in oracle/observables.py, and two
-physical checks of the density mode (eq. fourdens): its exact mean over the
-uniform distribution at s = 0, and the phase separation of Sec. 3.3 at
-lambda = 50 > lambda_c = 2 pi^2."""
+pd_mean, pd_histogram) against the plain definitions in oracle/observables.py,
+and two physical checks of the density mode (eq. fourdens): its exact mean
+over the uniform distribution at s = 0, and the phase separation of Sec. 3.3
+at lambda = 50 > lambda_c = 2 pi^2."""
 import numpy as np
 import pytest
 import torch
@@ -71,3 +71,60 @@ def test_density_mode_physics():
     S = pd.Sampler(pd.make_params(L, N, inputs.s_of_lambda(50.0, L), Nc, 3000.0, 10.0, seed=4))
     S.run(300)
     assert S.mean(S.density_mode(1)) > 4 * exact
+
+
+@pytest.mark.parametrize("L,N,s,Nc", [(100, 50, 0.002, 3000), (20, 10, 0.3, 600_000)])
+def test_histogram_matches_oracle(L, N, s, Nc):
+    """pd_histogram against the oracle, count for count: the activity K^beta of
+    the last interval over the current clones (p_end) and the same quantity
+    recorded at an origin reset, over the ancestors of the clones some cycles
+    later (p_ave); the density mode in fine bins; and values that are NaN,
+    infinite or outside the range.  Nc = 6e5 runs the kernel's grid-stride
+    loop (2048 blocks)."""
+    p = pd.make_params(L, N, s, Nc, 20.0, 0.5, seed=8, track_origin=1)
+    S = pd.Sampler(p)
+    S.run(3)
+    S.step()
+    Kb, _, _ = S.step_outputs()
+    S.resample()
+    kb_now = Kb[S.ancestors()].astype(np.float64)    # K^beta of each current clone
+    kb = torch.from_numpy(kb_now).cuda()
+    S.reset_origin()
+    top = float(kb_now.max()) + 2
+    for lo, width, nb in [(-0.5, 1.0, int(top) + 1), (0.0, 1.0, int(top)), (2.0, 3.0, 7),
+                          (0.0, 1.0, 1)]:
+        assert np.array_equal(S.histogram(kb, lo, width, nb), ob.histogram(kb_now, lo, width, nb))
+    S.run(6)
+    origin = S.origin()
+    assert np.array_equal(S.histogram(kb, -0.5, 1.0, int(top) + 1, ancestral=True),
+                          ob.histogram(kb_now, -0.5, 1.0, int(top) + 1, origin=origin))
+    rho = S.density_mode(1)
+    r = rho.cpu().numpy()
+    assert np.array_equal(S.histogram(rho, 0.0, 0.05, 4096), ob.histogram(r, 0.0, 0.05, 4096))
+    odd = r.copy()
+    odd[::7] = np.nan
+    odd[3::11] = np.inf
+    odd[5::13] = -1.0
+    t = torch.from_numpy(odd).cuda()
+    assert np.array_equal(S.histogram(t, 0.0, 0.25, 40), ob.histogram(odd, 0.0, 0.25, 40))
+    assert S.histogram(t, 1e6, 1.0, 10).sum() == 0
+
+
+def test_histogram_validation():
+    p = pd.make_params(20, 10, 0.1, 100, 5.0, 0.5, seed=1)
+    S = pd.Sampler(p)
+    v = torch.zeros(100, dtype=torch.float64, device="cuda")
+    for lo, width, nb in [(0.0, 1.0, 0), (0.0, 1.0, 4097), (0.0, 0.0, 10), (0.0, -1.0, 10),
+                          (float("nan"), 1.0, 10), (0.0, float("inf"), 10)]:
+        with pytest.raises(pd.PdError) as e:
+            S.histogram(v, lo, width, nb)
+        assert e.value.status == pd.PD_EINVAL, (lo, width, nb)
+    with pytest.raises(pd.PdError) as e:
+        S.histogram(v, 0.0, 1.0, 10, ancestral=True)
+    assert e.value.status == pd.PD_ESTATE
+    S.step()
+    with pytest.raises(pd.PdError) as e:
+        S.histogram(v, 0.0, 1.0, 10)
+    assert e.value.status == pd.PD_ESTATE
+    S.resample()
+    assert S.histogram(v, -0.5, 1.0, 3).tolist() == [100, 0, 0]
