@@ -421,7 +421,7 @@ def main():
     st = S.stream
 
     if a.variant is None:
-        tuning = S.autotune(8)           # restores the population afterwards
+        tuning = S.autotune(24)          # restores the population afterwards
     else:
         S.set_tuning(a.variant, a.refill, 16, a.scan_tiles)
         tuning = S.tuning()

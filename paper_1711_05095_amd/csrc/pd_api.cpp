@@ -951,7 +951,7 @@ pd_status pd_autotune(pd_ctx* ctx, int32_t trial_cycles, pd_tuning* best)
     t.step_variant = 0;
     cands.push_back(t);
     t.step_variant = 4;
-    for (int f : {10, 12, 14, 16}) {
+    for (int f : {12, 13, 14, 15}) {
         t.refill = f;
         cands.push_back(t);
     }
@@ -980,25 +980,31 @@ pd_status pd_autotune(pd_ctx* ctx, int32_t trial_cycles, pd_tuning* best)
         if (hipEventElapsedTime(ms, e0, e1) != hipSuccess) return PD_EDEVICE;
         return PD_OK;
     };
-    float best_ms = 1e30f;
+    // each list is timed in two interleaved passes and a candidate keeps its
+    // faster time, so one disturbed trial does not decide
+    auto pick = [&](const std::vector<pd_tuning>& list, pd_tuning* out) -> pd_status {
+        std::vector<float> best(list.size(), 1e30f);
+        for (int pass = 0; pass < 2; ++pass)
+            for (size_t i = 0; i < list.size(); ++i) {
+                float ms = 0.0f;
+                const pd_status s2 = time_one(list[i], &ms);
+                if (s2 != PD_OK) return s2;
+                best[i] = std::min(best[i], ms);
+            }
+        *out = list[std::min_element(best.begin(), best.end()) - best.begin()];
+        return PD_OK;
+    };
     pd_tuning chosen = start;
     // the dynamical stage's launch configuration, then the cloning stage's scan tiling
-    for (const auto& c : cands) {
-        float ms = 0.0f;
-        st = time_one(c, &ms);
-        if (st != PD_OK) break;
-        if (ms < best_ms) { best_ms = ms; chosen = c; }
-    }
+    st = pick(cands, &chosen);
     if (st == PD_OK) {
-        const pd_tuning step_best = chosen;
+        std::vector<pd_tuning> tilings;
         for (int tpb : {1, 2, 4, 8}) {
-            pd_tuning c = step_best;
+            pd_tuning c = chosen;
             c.scan_tiles = tpb;
-            float ms = 0.0f;
-            st = time_one(c, &ms);
-            if (st != PD_OK) break;
-            if (ms < best_ms) { best_ms = ms; chosen = c; }
+            tilings.push_back(c);
         }
+        st = pick(tilings, &chosen);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
