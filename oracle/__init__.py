@@ -50,9 +50,12 @@ _lib = None
 
 
 def lib():
+    """The compiled oracle.  PD_ORACLE_LIB, when set, names another build of it
+    to load instead (the test that plants mistakes in copies of oracle.c runs
+    the pins against each copy this way)."""
     global _lib
     if _lib is None:
-        _lib = ctypes.CDLL(build())
+        _lib = ctypes.CDLL(os.environ.get("PD_ORACLE_LIB") or build())
         P = ctypes.POINTER
         _lib.orc_philox.argtypes = [P(ctypes.c_uint32), P(ctypes.c_uint32), P(ctypes.c_uint32)]
         _lib.orc_init.argtypes = [P(Params), ctypes.c_void_p, ctypes.c_void_p]
