@@ -212,7 +212,10 @@ pd_status pd_get_log(pd_ctx* ctx, int32_t inst, double* lbeta, double* mean_kb, 
  * and, for instances with track_origin, the carried origins) into a host
  * buffer of pd_save_bytes() bytes, and its restore into a context created
  * with the same parameters.  A restored run continues bit-identically.  Both
- * synchronise. */
+ * synchronise.  pd_load checks the whole image before it uploads any of it
+ * (magic and instance count, every state holding N particles on sites
+ * 0..L-1, every origin in [0, Nc)) and returns PD_EINVAL, with the context
+ * unchanged, if any check fails. */
 pd_status pd_save_bytes(pd_ctx* ctx, size_t* bytes);
 pd_status pd_save(pd_ctx* ctx, void* host, size_t bytes);
 pd_status pd_load(pd_ctx* ctx, const void* host, size_t bytes);

@@ -641,6 +641,24 @@ pd_status pd_get_population(pd_ctx* ctx, int32_t inst, void* host, size_t bytes)
     return PD_OK;
 }
 
+// A host image of Nc states ([W][Nc] words): "" if every state has N particles on sites 0..L-1.
+static std::string check_states(const pd_params& p, const void* words)
+{
+    const size_t Nc = (size_t)p.Nc, W = (size_t)words_of(p.L);
+    for (size_t j = 0; j < Nc; ++j) {
+        int cnt = 0;
+        for (size_t w = 0; w < W; ++w) {
+            uint64_t v;
+            std::memcpy(&v, (const char*)words + 8 * (w * Nc + j), 8);
+            const int hi_bits = p.L - 64 * (int)w;
+            if (hi_bits < 64 && (v >> hi_bits) != 0) return "state has a bit set at or beyond site L";
+            cnt += __builtin_popcountll(v);
+        }
+        if (cnt != p.N) return "state does not hold N particles";
+    }
+    return "";
+}
+
 pd_status pd_set_population(pd_ctx* ctx, int32_t inst, const void* host, size_t bytes)
 {
     pd_status st = check_inst(ctx, inst);
@@ -648,18 +666,8 @@ pd_status pd_set_population(pd_ctx* ctx, int32_t inst, const void* host, size_t 
     const pd_params& p = ctx->params[inst];
     const size_t Nc = (size_t)p.Nc, W = (size_t)words_of(p.L);
     if (!host || bytes < 8 * Nc * (W + 1)) return fail(ctx, PD_ENOMEM, "host buffer too small");
-    const uint64_t* words = (const uint64_t*)host;
-    for (size_t j = 0; j < Nc; ++j) {
-        int cnt = 0;
-        for (size_t w = 0; w < W; ++w) {
-            uint64_t v = words[w * Nc + j];
-            const int hi_bits = p.L - 64 * (int)w;
-            if (hi_bits < 64 && (v >> hi_bits) != 0)
-                return fail(ctx, PD_EINVAL, "state has a bit set at or beyond site L");
-            cnt += __builtin_popcountll(v);
-        }
-        if (cnt != p.N) return fail(ctx, PD_EINVAL, "state does not hold N particles");
-    }
+    std::string m = check_states(p, host);
+    if (!m.empty()) return fail(ctx, PD_EINVAL, m);
     st = materialise(ctx);   // keep the other instances' populations in slot order
     if (st != PD_OK) return st;
     const InstDev& d = ctx->dev[inst];
@@ -770,14 +778,41 @@ pd_status pd_load(pd_ctx* ctx, const void* host, size_t bytes)
     pd_status st = pd_save_bytes(ctx, &need);
     if (st != PD_OK) return st;
     if (!host || bytes < need) return fail(ctx, PD_ENOMEM, "checkpoint too small");
-    const uint64_t* h = (const uint64_t*)host;
-    if (h[0] != kMagic || h[1] != (uint64_t)ctx->n)
+    uint64_t h[3];
+    std::memcpy(h, host, sizeof h);
+    if (h[0] != kMagic || h[1] != (uint64_t)ctx->n || h[2] > (uint64_t)INT64_MAX)
         return fail(ctx, PD_EINVAL, "not a checkpoint of this configuration");
+    // Everything is checked before anything is uploaded, so a rejected checkpoint leaves the
+    // context as it was.  Origins index the caller's values in pd_mean/pd_histogram and ncont
+    // counts records of the guided stage, so neither is taken on trust; a checkpoint is taken
+    // after a cloning stage, where ncont is 0.
+    std::vector<InstCtl> ctl(ctx->n);
     const char* at = (const char*)host + 24;
+    for (int i = 0; i < ctx->n; ++i) {
+        const pd_params& p = ctx->params[i];
+        const size_t Nc = (size_t)p.Nc, W = (size_t)words_of(p.L);
+        std::memcpy(&ctl[i], at, sizeof(InstCtl));
+        ctl[i].ncont = 0;
+        if (ctl[i].beta < 0) return fail(ctx, PD_EINVAL, "checkpoint has a negative interval count");
+        at += sizeof(InstCtl);
+        std::string m = check_states(p, at);
+        if (!m.empty()) return fail(ctx, PD_EINVAL, "instance " + std::to_string(i) + ": " + m);
+        at += 8 * Nc * (W + 1);
+        if (ctx->dev[i].origin[0]) {
+            for (size_t j = 0; j < Nc; ++j) {
+                int32_t o;
+                std::memcpy(&o, at + 4 * j, 4);
+                if (o < 0 || (size_t)o >= Nc)
+                    return fail(ctx, PD_EINVAL, "checkpoint has an origin outside [0, Nc)");
+            }
+            at += (4 * Nc + 7) / 8 * 8;
+        }
+    }
+    at = (const char*)host + 24;
     for (int i = 0; i < ctx->n; ++i) {
         const InstDev& d = ctx->dev[i];
         const size_t Nc = (size_t)ctx->params[i].Nc, W = (size_t)words_of(ctx->params[i].L);
-        PD_HIP(hipMemcpyAsync(d.ctl, at, sizeof(InstCtl), hipMemcpyHostToDevice, ctx->stream));
+        PD_HIP(hipMemcpyAsync(d.ctl, &ctl[i], sizeof(InstCtl), hipMemcpyHostToDevice, ctx->stream));
         at += sizeof(InstCtl);
         PD_HIP(hipMemcpyAsync(d.state[ctx->cur], at, 8 * Nc * W, hipMemcpyHostToDevice, ctx->stream));
         at += 8 * Nc * W;

@@ -2,6 +2,7 @@
 // kernels of pd_guide.hip.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 #include <string>
@@ -42,16 +43,29 @@ std::string check_batch(const void* states, int64_t ld, int32_t L, int64_t n)
     return "";
 }
 
-// Dynamic LDS of the sample kernels grows with L; raise the limit once per L.
-pd_status smem_limit(int L)
+// A kernel attribute (hipFuncSetAttribute) holds for the device that is current when it is set:
+// each flag records, per device, that it has been set there.  Setting it twice is harmless, so
+// two threads racing on the first call need no lock.
+constexpr int kMaxDevices = 64;
+std::atomic<bool> g_net_smem_set[kMaxDevices];
+std::atomic<bool> g_stats_smem_set[kMaxDevices];
+
+pd_status once_per_device(std::atomic<bool>* flags, hipError_t (*set)())
 {
-    thread_local int done_for = 0;
-    const int LP = (L + 15) / 16 * 16;
-    if (LP <= done_for) return PD_OK;
-    pd_status st = gdev(net_set_smem_limit(PD_MAX_L), "hipFuncSetAttribute");
-    if (st == PD_OK) done_for = PD_MAX_L;
+    int dev = 0;
+    pd_status st = gdev(hipGetDevice(&dev), "hipGetDevice");
+    if (st != PD_OK) return st;
+    if (dev < 0 || dev >= kMaxDevices) return gfail(PD_EDEVICE, "device ordinal beyond 63");
+    if (flags[dev].load(std::memory_order_acquire)) return PD_OK;
+    st = gdev(set(), "hipFuncSetAttribute");
+    if (st == PD_OK) flags[dev].store(true, std::memory_order_release);
     return st;
 }
+
+// The sample kernels' dynamic LDS grows with L: the limit is raised once, for the largest ring.
+hipError_t net_smem_max_l() { return net_set_smem_limit(PD_MAX_L); }
+
+pd_status smem_limit() { return once_per_device(g_net_smem_set, net_smem_max_l); }
 
 }  // namespace
 
@@ -70,7 +84,7 @@ pd_status pdg_forward(const float* theta, const uint64_t* states, int64_t ld, in
     std::string m = check_batch(states, ld, L, n);
     if (!m.empty()) return gfail(PD_EINVAL, m);
     if (!theta || !f_out) return gfail(PD_EINVAL, "null pointer");
-    pd_status st = smem_limit(L);
+    pd_status st = smem_limit();
     if (st != PD_OK) return st;
     return gdev(launch_net(0, theta, states, ld, nullptr, L, n, f_out, nullptr, nullptr, nullptr,
                            (hipStream_t)hip_stream),
@@ -88,7 +102,7 @@ pd_status pdg_loss_grad(const float* theta, const uint64_t* states, int64_t ld,
     size_t need = 0;
     pdg_workspace_bytes(n, &need);
     if (work_bytes < need) return gfail(PD_ENOMEM, "workspace too small");
-    pd_status st = smem_limit(L);
+    pd_status st = smem_limit();
     if (st != PD_OK) return st;
     return gdev(launch_net(1, theta, states, ld, counts, L, n, nullptr, (float*)work, grad, loss,
                            (hipStream_t)hip_stream),
@@ -119,7 +133,7 @@ pd_status pdg_train_epoch(float* theta, float* m, float* v, const uint64_t* stat
     size_t need = 0;
     pdg_workspace_bytes(batch < n ? batch : n, &need);
     if (work_bytes < need) return gfail(PD_ENOMEM, "workspace too small");
-    pd_status st = smem_limit(L);
+    pd_status st = smem_limit();
     if (st != PD_OK) return st;
     return gdev(launch_train_epoch(theta, m, v, states, ld, counts, L, n, batch, step0, lr,
                                    loss_sum, (float*)work, (hipStream_t)hip_stream),
@@ -154,12 +168,8 @@ pd_status pdg_bond_table_cond(const float* window_table, const uint64_t* states,
     if (!(gmax >= 0.0) || !(gmax <= PDG_MAX_GMAX)) return gfail(PD_EINVAL, "gmax out of range");
     if (!aligned256(work)) return gfail(PD_EINVAL, "workspace must be 256-byte aligned");
     if (work_bytes < kCondWorkBytes) return gfail(PD_ENOMEM, "workspace too small");
-    thread_local bool attr_done = false;
-    if (!attr_done) {
-        pd_status st = gdev(stats_set_smem_limit(), "hipFuncSetAttribute");
-        if (st != PD_OK) return st;
-        attr_done = true;
-    }
+    pd_status st = once_per_device(g_stats_smem_set, stats_set_smem_limit);
+    if (st != PD_OK) return st;
     return gdev(launch_bond_table_cond(window_table, states, ld, L, n, (uint32_t)min_count, gmax,
                                        eg, G, counts, work, (hipStream_t)hip_stream),
                 "conditional bond table launch");

@@ -473,6 +473,65 @@ def test_checkpoint_and_autotune_keep_origins():
     assert B.estimates() == A.estimates()
 
 
+def test_load_rejects_a_corrupt_checkpoint():
+    """pd_load checks a checkpoint whole before uploading any of it: an origin
+    outside [0, Nc), a bit beyond site L, a missing particle or a wrong magic
+    is rejected with the context unchanged, and a nonzero guided hand-on count
+    in the image is not taken over."""
+    L, Nc = 60, 2000
+    p = pd.make_params(L, 30, 0.01, Nc, 10.0, 0.5, seed=95, track_origin=1)
+    A = pd.Sampler(p)
+    A.run(3)
+    A.reset_origin()
+    A.run(2)
+    blob = A.save()
+    A.run(4)
+    want = (A.get_population(), A.origin(), A.estimates())
+    ctl = blob.nbytes - 24 - 8 * Nc * 2 - (4 * Nc + 7) // 8 * 8   # InstCtl image
+    states = 24 + ctl                                             # [W=1][Nc] words, then K
+    origins = states + 16 * Nc
+    B = pd.Sampler(p)
+    B.run(3)
+    B.reset_origin()
+    B.run(2)
+
+    def corrupt(edit):
+        bad = blob.copy()
+        edit(bad)
+        with pytest.raises(pd.PdError) as e:
+            B.load(bad)
+        assert e.value.status == pd.PD_EINVAL
+
+    def set_origin(b):
+        b[origins + 4 * 7:origins + 4 * 8] = np.array([Nc], np.int32).view(np.uint8)
+    corrupt(set_origin)
+
+    def set_bit_beyond_L(b):
+        w = b[states + 8 * 11:states + 8 * 12].view(np.uint64)
+        w[0] |= np.uint64(1) << np.uint64(L)
+    corrupt(set_bit_beyond_L)
+
+    def drop_particle(b):
+        w = b[states + 8 * 13:states + 8 * 14].view(np.uint64)
+        w[0] &= w[0] - np.uint64(1)
+    corrupt(drop_particle)
+
+    def wrong_magic(b):
+        b[0] ^= 1
+    corrupt(wrong_magic)
+
+    B.run(4)   # every load was refused: B runs on as A did
+    assert np.array_equal(B.get_population()[0], want[0][0])
+    assert np.array_equal(B.origin(), want[1]) and B.estimates() == want[2]
+
+    hand_on = blob.copy()
+    hand_on[24 + 8:24 + 12] = np.array([12345], np.uint32).view(np.uint8)
+    B.load(hand_on)
+    B.run(4)
+    assert np.array_equal(B.get_population()[0], want[0][0])
+    assert np.array_equal(B.origin(), want[1]) and B.estimates() == want[2]
+
+
 def test_compacting_variant_carries_origins():
     """Variant 4 (compaction between rounds) carries origin ids exactly as
     variant 0 does."""
