@@ -256,10 +256,16 @@ def _guide_tensor(table):
 
 @pytest.mark.parametrize("L,N,s,Nc,table_seed", [(10, 5, 0.3, 1000, 1), (100, 50, 0.002, 1500, 2),
                                                  (30, 14, -0.05, 300, 3), (400, 200, 1e-4, 257, 4),
-                                                 (6, 3, 0.5, 64, 5)])
+                                                 (6, 3, 0.5, 64, 5), (25, 12, 0.1, 300, 6),
+                                                 (26, 13, 0.1, 300, 7), (65, 32, 0.01, 777, 8),
+                                                 (512, 256, 1e-4, 130, 9), (12, 12, 0.2, 70, 10)])
 def test_guided_cycles_bit_exact(L, N, s, Nc, table_seed):
     """Guided dynamics: states, hop counts and carried K bit-exact with the
-    oracle for the same guide table, weights to 1e-12, over several cycles."""
+    oracle for the same guide table, weights to 1e-12, over several cycles.
+    L = 25 and 26 sit either side of the switch from recomputing the summed
+    guide rate after a hop to updating it over the 14 changed neighbourhoods;
+    L = 65 crosses a word, 512 is the largest ring, and a full ring has no
+    allowed bond."""
     from guide_tables import random_table
     print(f"guided L={L} s={s} Nc={Nc}", flush=True)
     table = random_table(table_seed)
