@@ -230,7 +230,8 @@ pd_status pd_load(pd_ctx* ctx, const void* host, size_t bytes);
  * -sum_jumps g - integral (r - e^{-s} sum_b eg[u_b] / 2^16) dt, so psi-hat
  * stays unbiased for any table.  Entries of neighbourhoods whose bits 6 and 7
  * are equal must be 0, the others in [1, 2^31) with largest/smallest <= 1024;
- * PD_EINVAL otherwise.  The table must outlive its use.  Synchronises. */
+ * PD_EINVAL otherwise, and also if d_table is not 16-byte aligned.  The table
+ * must outlive its use.  Synchronises. */
 pd_status pd_set_guide(pd_ctx* ctx, const uint32_t* d_table, size_t n);
 
 /* Launch configuration of the dynamical stage.  It never changes results

@@ -837,6 +837,8 @@ pd_status pd_set_guide(pd_ctx* ctx, const uint32_t* d_table, size_t n)
     if (!ctx) return PD_EINVAL;
     if (!ctx->any_guided) return fail(ctx, PD_EINVAL, "no instance uses guided weights");
     if (!d_table || n != (size_t)kGuideEntries) return fail(ctx, PD_EINVAL, "table must hold 8192 entries");
+    if ((reinterpret_cast<uintptr_t>(d_table) & 15u) != 0)
+        return fail(ctx, PD_EINVAL, "table must be 16-byte aligned");
     std::vector<uint32_t> h(kGuideEntries);
     PD_HIP(hipMemcpyAsync(h.data(), d_table, sizeof(uint32_t) * h.size(), hipMemcpyDeviceToHost,
                           ctx->stream));

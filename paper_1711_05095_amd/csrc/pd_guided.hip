@@ -31,10 +31,10 @@ namespace pd {
 // its acceptance word from words 0, 1 and, if it is rejected, the next
 // proposal's bond word from words 2, 3.  Every call site draws one block per
 // pass of its loop, so no lane of a wave waits on another lane's refill.
-// In LDS the table keeps only the 4096 neighbourhoods of allowed bonds (bit 7
-// is the complement of bit 6 there, so it is dropped), and sum_jumps ln eg is
-// formed as the logarithm of the running product of the eg, kept in [0.5, 1)
-// by frexp with the binary exponents summed separately.
+// The whole table sits in LDS: its entries of neighbourhoods whose bond is no
+// hop are 0, so a sum over neighbourhoods needs no test of the bond.
+// sum_jumps ln eg is formed as the logarithm of the running product of the eg,
+// kept in [0.5, 1) by frexp with the binary exponents summed separately.
 // ---------------------------------------------------------------------------
 
 // i mod L in [0, L) for i >= -L * 8.
@@ -46,9 +46,6 @@ __device__ __forceinline__ int ring_mod(int i, int L)
 
 __device__ __forceinline__ bool bond_allowed(uint32_t u) { return ((u >> 6) ^ (u >> 7)) & 1u; }
 
-// Index of an allowed neighbourhood u in the compressed table (bit 7 dropped).
-__device__ __forceinline__ uint32_t gidx(uint32_t u) { return (u & 0x7Fu) | ((u >> 8) << 7); }
-constexpr int kGuideCompact = kGuideEntries / 2;
 
 template <int W>
 __device__ __forceinline__ uint64_t guided_total(const uint64_t (&x)[W], const uint64_t (&m)[W],
@@ -61,7 +58,7 @@ __device__ __forceinline__ uint64_t guided_total(const uint64_t (&x)[W], const u
         while (bits) {
             const int b = w * 64 + __builtin_ctzll(bits);
             bits &= bits - 1;
-            S += eg[gidx(ring_bits<W>(x, L, ring_mod(b - 6, L), 13))];
+            S += eg[ring_bits<W>(x, L, ring_mod(b - 6, L), 13)];
         }
     }
     return S;
@@ -82,7 +79,7 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
                                                   int tile_base, int src, int use_anc,
                                                   int budgeted)
 {
-    __shared__ __align__(16) uint32_t s_eg[kGuideCompact];
+    __shared__ __align__(16) uint32_t s_eg[kGuideEntries];
     __shared__ double s_log[kLogRows * kLogCols];
     __shared__ __align__(8) uint8_t s_sel[2048];
 
@@ -95,10 +92,9 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
     if (CONT && e0 >= ncont) return;                  // uniform over the block
     for (int i = threadIdx.x; i < kLogRows * kLogCols; i += kTile) s_log[i] = gptr(I.log_tab)[i];
     load_select_table(s_sel, I.sel_tab, threadIdx.x, kTile);
-    for (int i = threadIdx.x; i < kGuideCompact; i += kTile) {
-        const uint32_t b6 = (i >> 6) & 1u;
-        s_eg[i] = gptr(I.guide)[(i & 0x7F) | ((b6 ^ 1u) << 7) | ((i >> 7) << 8)];
-    }
+    // 16-byte pieces (the host checks the table's alignment)
+    for (int i = threadIdx.x; i < kGuideEntries / 4; i += kTile)
+        reinterpret_cast<uint4*>(s_eg)[i] = reinterpret_cast<const uint4*>(I.guide)[i];
     __syncthreads();
 
     const int tid = threadIdx.x;
@@ -173,7 +169,7 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
         uint32_t qh = y.z, ql = y.w;   // bond word of the first proposal
         for (int tries = 0; tries < (1 << 20); ++tries) {
             b = select_bit_lut<W>(m, mulhi64_small(qh, ql, (uint32_t)r), s_sel);
-            e = s_eg[gidx(ring_bits<W>(x, L, ring_mod(b - 6, L), 13))];
+            e = s_eg[ring_bits<W>(x, L, ring_mod(b - 6, L), 13)];
             const uint4 a = philox10(prop, (uint32_t)j, beta, cp, I.key0, I.key1);
             ++prop;
             if (__umul64hi(((uint64_t)a.x << 32) | a.y, egmax) < (uint64_t)e) break;
@@ -188,19 +184,13 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
             // bits o..o+12 of the 26 sites from b-12, o = 0..13
             const uint32_t win0 = ring_bits<W>(x, L, b >= 12 ? b - 12 : b - 12 + L, 26);
             const uint32_t win1 = win0 ^ (3u << 12);
-            // bit i: sites i and i+1 of the window differ (the bond is a hop)
-            const uint32_t al0 = win0 ^ (win0 >> 1), al1 = win1 ^ (win1 >> 1);
             uint64_t add = 0, sub = 0;
-            // branch-free: every neighbourhood's entry is read (any 13-bit u
-            // has a compact index) and masked by its bond's bit
+            // branch-free: all 14 neighbourhoods are read before and after;
+            // those whose bond is no hop read 0
 #pragma unroll
             for (int o = 0; o < 14; ++o) {
-                const uint32_t u0 = (win0 >> o) & 0x1FFFu;
-                const uint32_t u1 = (win1 >> o) & 0x1FFFu;
-                const uint32_t k0 = (uint32_t)__builtin_amdgcn_sbfe((int)al0, o + 6, 1);
-                const uint32_t k1 = (uint32_t)__builtin_amdgcn_sbfe((int)al1, o + 6, 1);
-                sub += s_eg[gidx(u0)] & k0;
-                add += s_eg[gidx(u1)] & k1;
+                sub += s_eg[(win0 >> o) & 0x1FFFu];
+                add += s_eg[(win1 >> o) & 0x1FFFu];
             }
             hop<W>(x, b, L);
             bond_mask<W>(x, lb, m);

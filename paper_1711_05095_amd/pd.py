@@ -353,9 +353,10 @@ class Sampler:
 
     def set_guide(self, table):
         """table: a torch uint32-compatible int32 CUDA tensor of 8192 entries
-        (kept alive by the sampler)."""
-        self._guide = table
+        (kept alive by the sampler; a refused table leaves the previous one in
+        use, and alive)."""
         pd_set_guide(self.ctx, table.data_ptr(), table.numel())
+        self._guide = table
 
     def reset_origin(self, inst=0):
         pd_reset_origin(self.ctx, inst)

@@ -422,6 +422,11 @@ def test_guided_whole_run_and_guide_validation():
     with pytest.raises(pd.PdError) as e:
         S.set_guide(_guide_tensor(bad))
     assert e.value.status == pd.PD_EINVAL
+    shifted = torch.zeros(8193, dtype=torch.int32, device="cuda")
+    shifted[1:] = _guide_tensor(table)
+    with pytest.raises(pd.PdError) as e:   # 4 bytes past a 16-byte boundary
+        S.set_guide(shifted[1:])
+    assert e.value.status == pd.PD_EINVAL
     S.set_guide(_guide_tensor(table))
     S.run(M)
     r = oracle.Oracle(w["L"], w["N"], 0.3, w["Nc"], w["dt"], M=M, seed=3, mode=GUIDED,
