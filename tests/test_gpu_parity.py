@@ -618,6 +618,42 @@ def test_batch_equals_separate():
         assert np.array_equal(ws, wb) and np.array_equal(Ks, Kb)
 
 
+def test_mixed_forms_in_one_context_equal_separate():
+    """One context holding instances of every weight form and both selections
+    (modified, direct, guided; [eq] and [iid]), of uneven L and Nc, run through
+    graph-replayed cycles with origins tracked: each instance equals, bit for
+    bit, the same instance alone in a context of its own."""
+    from guide_tables import random_table
+    table = _guide_tensor(random_table(11))
+    EQ = pd.PD_SEL_EQ
+    specs = [(40, 20, 0.05, 1500, 0.5, MOD, EQ), (100, 50, 0.002, 2600, 0.5, GUIDED, EQ),
+             (30, 14, 0.1, 777, 0.3, DIR, IID), (20, 9, 0.2, 300, 0.4, GUIDED, IID),
+             (512, 256, 1e-4, 130, 1.0, MOD, IID)]
+    M = 9
+    params = [pd.make_params(L, N, s, Nc, M * dt, dt, seed=80 + i, instance=i, weight_mode=mode,
+                             selection=sel, track_origin=1)
+              for i, (L, N, s, Nc, dt, mode, sel) in enumerate(specs)]
+    B = pd.Sampler(params)
+    B.set_guide(table)
+    B.run(3)
+    for i in range(len(params)):
+        B.reset_origin(i)
+    B.run(M - 3)
+    for i, q in enumerate(params):
+        S = pd.Sampler(q)
+        if q.weight_mode == GUIDED:
+            S.set_guide(table)
+        S.run(3)
+        S.reset_origin()
+        S.run(M - 3)
+        assert S.estimates() == B.estimates(i), i
+        ws, Ks = S.get_population()
+        wb, Kb = B.get_population(i)
+        assert np.array_equal(ws, wb) and np.array_equal(Ks, Kb), i
+        assert np.array_equal(S.origin(), B.origin(i)), i
+        S.close()
+
+
 @pytest.mark.parametrize("guided", [False, True])
 def test_split_launch_equals_unsplit(guided):
     """Four instances of 938 tiles each, in one context (a step launch of 3752
