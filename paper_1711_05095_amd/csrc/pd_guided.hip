@@ -104,6 +104,9 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
     const uint32_t c3 = TAG_GUIDE | I.tag_hi, cp = TAG_GUIDE_PROP | I.tag_hi;
     const double es = I.es, dt = I.dt;
     const uint64_t egmax = I.guide_max;
+    // 14 entries of at most egmax each fit 32 bits (true for any guide whose
+    // largest entry is below 2^32 / 14)
+    const bool narrow = egmax <= 0xFFFFFFFFull / 14u;
     double poly[kLogPoly];   // log1p coefficients as uniform operands
 #pragma unroll
     for (int w = 0; w < kLogPoly; ++w) poly[w] = I.log_poly[w];
@@ -184,13 +187,25 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
             // bits o..o+12 of the 26 sites from b-12, o = 0..13
             const uint32_t win0 = ring_bits<W>(x, L, b >= 12 ? b - 12 : b - 12 + L, 26);
             const uint32_t win1 = win0 ^ (3u << 12);
-            uint64_t add = 0, sub = 0;
             // branch-free: all 14 neighbourhoods are read before and after;
-            // those whose bond is no hop read 0
+            // those whose bond is no hop read 0 (`narrow` is the same for
+            // every lane of the launch)
+            uint64_t add = 0, sub = 0;
+            if (narrow) {
+                uint32_t add32 = 0, sub32 = 0;
 #pragma unroll
-            for (int o = 0; o < 14; ++o) {
-                sub += s_eg[(win0 >> o) & 0x1FFFu];
-                add += s_eg[(win1 >> o) & 0x1FFFu];
+                for (int o = 0; o < 14; ++o) {
+                    sub32 += s_eg[(win0 >> o) & 0x1FFFu];
+                    add32 += s_eg[(win1 >> o) & 0x1FFFu];
+                }
+                add = add32;
+                sub = sub32;
+            } else {
+#pragma unroll
+                for (int o = 0; o < 14; ++o) {
+                    sub += s_eg[(win0 >> o) & 0x1FFFu];
+                    add += s_eg[(win1 >> o) & 0x1FFFu];
+                }
             }
             hop<W>(x, b, L);
             bond_mask<W>(x, lb, m);

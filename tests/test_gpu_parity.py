@@ -268,8 +268,21 @@ def test_guided_cycles_bit_exact(L, N, s, Nc, table_seed):
     allowed bond."""
     from guide_tables import random_table
     print(f"guided L={L} s={s} Nc={Nc}", flush=True)
-    table = random_table(table_seed)
-    dt, M = 0.5, 5
+    _guided_cycles(L, N, s, Nc, random_table(table_seed), dt=0.5, M=5)
+
+
+def test_guided_wide_table_bit_exact():
+    """A guide whose entries reach 2^31 - 1 (the largest allowed): the summed
+    rate change of a hop then needs more than 32 bits, the other branch of the
+    step kernel's update."""
+    from guide_tables import random_table
+    print("guided wide table", flush=True)
+    table = random_table(12, lo=1 << 30, hi=(1 << 31) - 1)
+    _guided_cycles(30, 14, 0.05, 200, table, dt=0.004, M=4)
+    _guided_cycles(100, 50, 0.0, 64, table, dt=0.001, M=3)
+
+
+def _guided_cycles(L, N, s, Nc, table, dt, M):
     p = pd.make_params(L, N, s, Nc, M * dt, dt, seed=17, weight_mode=GUIDED)
     o = oracle.Oracle(L, N, s, Nc, dt, M=M, seed=17, mode=GUIDED, guide=table)
     S = pd.Sampler(p)
