@@ -169,10 +169,18 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
         tau = tau + w;
         int b = 0;
         uint32_t e = 0;
+        uint32_t win0 = 0;             // L >= 26: the 26 sites from b-12
         uint32_t qh = y.z, ql = y.w;   // bond word of the first proposal
         for (int tries = 0; tries < (1 << 20); ++tries) {
             b = select_bit_lut<W>(m, mulhi64_small(qh, ql, (uint32_t)r), s_sel);
-            e = s_eg[ring_bits<W>(x, L, ring_mod(b - 6, L), 13)];
+            // the neighbourhood of b is bits 6..18 of the window from b-12,
+            // which the update after a hop reuses
+            if (L >= 26) {
+                win0 = ring_bits<W>(x, L, b >= 12 ? b - 12 : b - 12 + L, 26);
+                e = s_eg[(win0 >> 6) & 0x1FFFu];
+            } else {
+                e = s_eg[ring_bits<W>(x, L, ring_mod(b - 6, L), 13)];
+            }
             const uint4 a = philox10(prop, (uint32_t)j, beta, cp, I.key0, I.key1);
             ++prop;
             if (__umul64hi(((uint64_t)a.x << 32) | a.y, egmax) < (uint64_t)e) break;
@@ -185,7 +193,6 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
         if (L >= 26) {
             // the 14 bonds whose neighbourhood holds site b or b+1 are
             // bits o..o+12 of the 26 sites from b-12, o = 0..13
-            const uint32_t win0 = ring_bits<W>(x, L, b >= 12 ? b - 12 : b - 12 + L, 26);
             const uint32_t win1 = win0 ^ (3u << 12);
             // branch-free: all 14 neighbourhoods are read before and after;
             // those whose bond is no hop read 0 (`narrow` is the same for
