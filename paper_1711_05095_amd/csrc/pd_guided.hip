@@ -44,6 +44,17 @@ __device__ __forceinline__ int ring_mod(int i, int L)
     return i;
 }
 
+// ring_bits for a window no longer than the ring (n <= L, n <= 32): at most
+// two pieces, the second one from site 0, formed without a loop.
+template <int W>
+__device__ __forceinline__ uint32_t ring_bits_short(const uint64_t (&x)[W], int L, int p, int n)
+{
+    const int take = min(n, L - p);                 // >= 1
+    const int rest = n - take;                      // sites wrapped to 0 .. rest-1
+    const uint32_t wrapped = (uint32_t)x[0] & ((1u << rest) - 1u);
+    return lin_bits<W>(x, p, take) | (rest ? wrapped << take : 0u);
+}
+
 __device__ __forceinline__ bool bond_allowed(uint32_t u) { return ((u >> 6) ^ (u >> 7)) & 1u; }
 
 
@@ -176,7 +187,7 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
             // the neighbourhood of b is bits 6..18 of the window from b-12,
             // which the update after a hop reuses
             if (L >= 26) {
-                win0 = ring_bits<W>(x, L, b >= 12 ? b - 12 : b - 12 + L, 26);
+                win0 = ring_bits_short<W>(x, L, b >= 12 ? b - 12 : b - 12 + L, 26);
                 e = s_eg[(win0 >> 6) & 0x1FFFu];
             } else {
                 e = s_eg[ring_bits<W>(x, L, ring_mod(b - 6, L), 13)];
