@@ -1,0 +1,132 @@
+"""Parity of the estimators and of the batched workload with the CPU oracle
+(through the C ABI).
+
+  * the per-interval log (pd_get_log): lbeta = ln((1/Nc) sum_i Ups_i^beta)
+    (eq. psihat, one term per interval) and the population mean of K^beta,
+    for every interval of whole runs at s != 0, with both weight forms, both
+    selections and a guide;
+  * the burn-in estimators psi_burn (intervals beyond burn_in, in the spirit
+    of the transient discussion of Sec. 5.1), also with burn_in on either
+    side of the run's ends;
+  * the 64 uneven instances of the batched workload (L in {20..200},
+    N = L/2, lambda in [-10, 20], Nc log-uniform in [1e3, 1e5]) in one context
+    equal, bit for bit, the same instances each in a context of its own.
+
+mean K^beta is an integer total over Nc, formed the same way on both sides,
+so it must be bit-identical; lbeta differs only by the order of the FP64 sum
+of the weights (tiled on the GPU, sequential in the oracle): at most about
+Nc ulps of the total.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1711_05095_amd import inputs, pd
+
+pytestmark = pytest.mark.gpu
+
+MOD, DIR, GUIDED = pd.PD_W_MODIFIED, pd.PD_W_DIRECT, pd.PD_W_GUIDED
+EQ, IID = pd.PD_SEL_EQ, pd.PD_SEL_IID
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pd.lib()  # raises if the library is not built
+
+
+LOG_CASES = [
+    # L, N, s, Nc, dt, M, burn_in, mode, selection
+    (10, 5, 0.4, 1000, 0.1, 120, 20, MOD, EQ),
+    (10, 5, -0.3, 700, 0.1, 90, 89, DIR, EQ),
+    (12, 5, 0.25, 513, 0.2, 60, 0, MOD, IID),
+    (40, 20, 0.02, 2000, 0.5, 40, 39, MOD, EQ),
+    (100, 50, 0.0015, 3000, 0.5, 30, 10, DIR, IID),
+    (30, 14, 0.1, 800, 0.3, 40, 7, GUIDED, EQ),
+    (10, 5, 0.2, 300, 0.1, 20, 25, MOD, EQ),      # burn-in past the end: psi_burn = 0
+]
+
+
+@pytest.mark.parametrize("L,N,s,Nc,dt,M,burn,mode,sel", LOG_CASES)
+def test_log_and_burn_in_estimators(L, N, s, Nc, dt, M, burn, mode, sel):
+    print(f"log L={L} N={N} s={s} Nc={Nc} M={M} burn={burn} mode={mode} sel={sel}", flush=True)
+    table = None
+    if mode == GUIDED:
+        from guide_tables import random_table
+        table = random_table(21)
+    seed = 700 + L
+    p = pd.make_params(L, N, s, Nc, M * dt, dt, seed=seed, selection=sel, weight_mode=mode,
+                       instance=3, log_cycles=M, burn_in=burn)
+    S = pd.Sampler(p)
+    if table is not None:
+        S.set_guide(torch.from_numpy(table.view(np.int32).copy()).cuda())
+    S.run(M)
+    e = S.estimates()
+    lb, mk = S.log(M)
+    r = oracle.Oracle(L, N, s, Nc, dt, M=M, seed=seed, instance=3, mode=mode, selection=sel,
+                      burn_in=burn, guide=table).run(per_interval=True)
+    assert e["hops"] == r["hops"]                       # the runs stayed in lockstep
+    assert np.array_equal(mk, r["mean_kb"])
+    tol = 1e-15 + Nc * 2.0 ** -53
+    assert np.max(np.abs(lb - r["lbeta"])) <= tol, np.max(np.abs(lb - r["lbeta"]))
+    assert e["psi"] == pytest.approx(r["psi"], rel=1e-9, abs=1e-15)
+    if burn >= M:
+        assert e["psi_burn"] == 0.0 and r["psi_burn"] == 0.0
+    else:
+        assert e["psi_burn"] == pytest.approx(r["psi_burn"], rel=1e-9, abs=1e-15)
+        # the burn-in estimate is the mean of the logged intervals beyond burn_in
+        assert e["psi_burn"] == pytest.approx(lb[burn:].sum() / ((M - burn) * dt), rel=1e-12,
+                                              abs=1e-15)
+    assert e["k_hat"] == pytest.approx(r["k_hat"], rel=1e-12)
+
+
+def test_log_shorter_than_run():
+    """log_cycles < M: the first log_cycles intervals are logged, the run goes on."""
+    L, N, s, Nc, dt, M, n = 10, 5, 0.3, 500, 0.1, 50, 17
+    p = pd.make_params(L, N, s, Nc, M * dt, dt, seed=9, log_cycles=n)
+    S = pd.Sampler(p)
+    S.run(M)
+    lb, mk = S.log(n)
+    r = oracle.Oracle(L, N, s, Nc, dt, M=M, seed=9).run(per_interval=True)
+    assert np.array_equal(mk, r["mean_kb"][:n])
+    assert np.max(np.abs(lb - r["lbeta"][:n])) <= 1e-15 + Nc * 2.0 ** -53
+    with pytest.raises(pd.PdError):
+        S.log(n + 1)
+
+
+def test_batched_workload_equals_separate():
+    """The 64-instance batched workload, a few graph-replayed cycles in one
+    context, against each instance in a context of its own."""
+    specs = inputs.batched_instances()
+    assert len(specs) == 64
+    M = 6
+    params = [pd.make_params(d["L"], d["N"], d["s"], d["Nc"], d["t_obs"], d["dt"], seed=d["seed"],
+                             instance=d["instance"]) for d in specs]
+    print("batched workload: %d instances, %d clones" % (len(params), sum(d["Nc"] for d in specs)),
+          flush=True)
+    B = pd.Sampler(params)
+    B.run(M)
+    for i, q in enumerate(params):
+        S = pd.Sampler(q)
+        S.run(M)
+        assert S.estimates() == B.estimates(i), i
+        ws, Ks = S.get_population()
+        wb, Kb = B.get_population(i)
+        assert np.array_equal(ws, wb) and np.array_equal(Ks, Kb), i
+        S.close()
+    # one instance of each word count against the oracle, whole run
+    seen = set()
+    for i, d in enumerate(specs):
+        W = (d["L"] + 63) // 64
+        if W in seen or d["Nc"] > 20_000:
+            continue
+        seen.add(W)
+        r = oracle.Oracle(d["L"], d["N"], d["s"], d["Nc"], d["dt"], M=M, seed=d["seed"],
+                          instance=d["instance"]).run()
+        e = B.estimates(i)
+        assert e["hops"] == r["hops"], i
+        assert e["psi"] == pytest.approx(r["psi"], rel=1e-9, abs=1e-15), i
+        assert e["k_hat"] == pytest.approx(r["k_hat"], rel=1e-12), i
+    assert len(seen) >= 3
