@@ -43,7 +43,7 @@ class Params(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [("psi", ctypes.c_double), ("psi_burn", ctypes.c_double),
                 ("k_hat", ctypes.c_double), ("hops", ctypes.c_uint64),
-                ("cycles", ctypes.c_int64)]
+                ("cycles", ctypes.c_int64), ("k_hat_burn", ctypes.c_double)]
 
 
 _lib = None
@@ -68,6 +68,8 @@ def lib():
         _lib.orc_resample.argtypes = [P(Params), ctypes.c_uint32] + [ctypes.c_void_p] * 6
         _lib.orc_resample.restype = ctypes.c_double
         _lib.orc_run.argtypes = [P(Params), P(Result), ctypes.c_void_p, ctypes.c_void_p]
+        _lib.orc_run_lineage.argtypes = [P(Params), ctypes.c_int64, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p]
         _lib.orc_step_slots.argtypes = [P(Params), ctypes.c_uint32, ctypes.c_int64] + \
             [ctypes.c_void_p] * 6
         _lib.orc_iid_points.argtypes = [P(Params), ctypes.c_uint32, ctypes.c_void_p]
@@ -162,12 +164,24 @@ class Oracle:
                            _ptr(mk) if per_interval else None)
         if rc != 0:
             raise MemoryError("oracle run failed")
-        out = dict(psi=res.psi, psi_burn=res.psi_burn, k_hat=res.k_hat, hops=res.hops,
-                   cycles=res.cycles)
+        out = dict(psi=res.psi, psi_burn=res.psi_burn, k_hat=res.k_hat,
+                   k_hat_burn=res.k_hat_burn, hops=res.hops, cycles=res.cycles)
         if per_interval:
             out["lbeta"] = lb
             out["mean_kb"] = mk
         return out
+
+    def run_lineage(self, beta0):
+        """Whole run with origins carried from interval beta0 on.  Returns
+        (occ at beta0 after cloning, final occ, origin of every final clone)."""
+        occ0 = np.zeros((self.Nc, self.L), np.uint8)
+        occ1 = np.zeros((self.Nc, self.L), np.uint8)
+        org = np.zeros(self.Nc, np.int32)
+        rc = lib().orc_run_lineage(ctypes.byref(self.p), int(beta0), _ptr(occ0), _ptr(occ1),
+                                   _ptr(org))
+        if rc != 0:
+            raise ValueError("oracle lineage run failed (%d)" % rc)
+        return occ0, occ1, org
 
 
 def select(ell, d=None, points=None):

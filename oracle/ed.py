@@ -121,3 +121,81 @@ def transition_law(L, N, rate_scale, dt, c0):
     states = basis(L, N)
     P = scipy.linalg.expm(generator(L, N, 0.0) * rate_scale * dt)
     return P[:, states.index(c0)]
+
+
+def _shifted(L, N, s):
+    """(psi, W_s - psi I): the generator shifted so that exp stays O(1) at long times."""
+    psi = scgf(L, N, s)
+    return psi, generator(L, N, s) - psi * np.eye(len(basis(L, N)))
+
+
+def ln_partition(L, N, s, t):
+    """ln Z(s, t) from a uniform start (t >= 0)."""
+    if t == 0:
+        return 0.0
+    psi, A = _shifted(L, N, s)
+    n = len(basis(L, N))
+    return float(psi * t + np.log(np.full(n, 1.0 / n) @ scipy.linalg.expm(A * t) @ np.ones(n)))
+
+
+def interval_log_limit(L, N, s, dt, M):
+    """The large-population limit of the per-interval log of the cloning
+    algorithm: the population after the cloning stage of interval beta - 1 has
+    the law q0^T e^{W_s (beta-1) dt} (normalised), so ln of its mean cloning
+    factor over interval beta tends to ln Z(s, beta dt) - ln Z(s, (beta-1) dt),
+    beta = 1..M (eq. Z-ups)."""
+    lz = [ln_partition(L, N, s, b * dt) for b in range(M + 1)]
+    return np.diff(np.array(lz))
+
+
+def _integral_expm(A, t):
+    """int_0^t exp(A u) du, from the exponential of [[A, I], [0, 0]] t."""
+    n = A.shape[0]
+    B = np.zeros((2 * n, 2 * n))
+    B[:n, :n] = A
+    B[:n, n:] = np.eye(n)
+    return scipy.linalg.expm(B * t)[:n, n:]
+
+
+def interval_mean_hops(L, N, s, dt, M, modified=True):
+    """The large-population limit of the population mean of K^beta before the
+    cloning stage of interval beta = 1..M: the population starts the interval
+    with the law p of interval_log_limit and runs the SSEP with all rates
+    times e^{-s} (modified dynamics, Sec. 3.2) or unscaled (direct weights);
+    a clone in C makes hops at rate c r(C) (c = e^{-s} or 1), so its expected
+    hops are c (int_0^dt e^{c W_0 u} du r)(C)."""
+    T, r = _hop_and_rate(L, N)
+    n = len(r)
+    c = np.exp(-s) if modified else 1.0
+    W0 = T - np.diag(r)
+    # generator acts on columns (W[C', C]); a function of the end point f
+    # evolves as e^{W^T u} f, and W_0 is symmetric
+    h = c * (_integral_expm(c * W0, dt) @ r)
+    psi, A = _shifted(L, N, s)
+    step = scipy.linalg.expm(A * dt)          # columns: from, rows: to
+    p = np.full(n, 1.0 / n)
+    out = np.empty(M)
+    for b in range(M):
+        out[b] = (p @ h) / p.sum()
+        p = step @ p
+        p = p / p.sum()
+    return out
+
+
+def activity_after(L, N, s, t_b, t):
+    """The large-population limit of k-hat with the first t_b of t left out:
+    the hops in (t_b, t] along the ancestral lines, per site and unit time,
+    -d/ds2 ln Z(s1, s2) / (L (t - t_b)) at s1 = s2 = s, where
+    Z(s1, s2) = q0^T e^{W_{s1} t_b} e^{W_{s2} (t - t_b)} 1 tilts the two parts
+    of the trajectory apart (the Frechet derivative of the exponential gives
+    d/ds2 exactly: dW/ds = -e^{-s} T).  t_b = 0 gives -d/ds ln Z(s, t)/(L t)."""
+    T, _ = _hop_and_rate(L, N)
+    n = T.shape[0]
+    psi, A = _shifted(L, N, s)
+    tau = t - t_b
+    E2, dE2 = scipy.linalg.expm_frechet(A * tau, -np.exp(-s) * T * tau)
+    q = np.full(n, 1.0 / n) @ scipy.linalg.expm(A * t_b)
+    one = np.ones(n)
+    Z = q @ E2 @ one
+    dZ = q @ dE2 @ one
+    return float(-dZ / Z / (L * tau))

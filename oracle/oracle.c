@@ -36,7 +36,12 @@
  *                   dynamics then cloning (Sec. 2.3), estimators psi-hat
  *                   (eq. psihat) and k-hat (eq. khat, with the 1/Nc the
  *                   printed formula omits; the accumulated K is carried with
- *                   the clone as Sec. 4.2 describes).
+ *                   the clone as Sec. 4.2 describes), and both with the
+ *                   intervals of a transient left out (Sec. 5.1).
+ *   orc_run_lineage the whole algorithm with the origin of every clone
+ *                   carried from a chosen interval on: the ancestral lines
+ *                   whose end points and starting points have the laws
+ *                   p_end and p_ave of Sec. 2.4 (eq. Opave).
  *
  * Readings of the paper taken here (each is also listed in the design notes):
  *   - bond i joins site i and site (i+1) mod L; it is an allowed hop iff the
@@ -107,10 +112,12 @@ typedef struct {
 
 typedef struct {
     double psi;           /* (1/t_obs) sum_beta ln mean Upsilon^beta */
-    double psi_burn;      /* the same sum over beta > burn_in */
+    double psi_burn;      /* the same sum over beta > burn_in, / ((M - burn_in) dt) */
     double k_hat;         /* sum_j K_j / (Nc L t_obs) of the final population */
     uint64_t hops;        /* every hop performed by every clone */
     int64_t cycles;
+    double k_hat_burn;    /* sum_j K'_j / (Nc L (M - burn_in) dt): K' = the hops of the
+                             intervals beyond burn_in, carried like K */
 } orc_result;
 
 static void draw(const orc_params* p, uint32_t tag, uint32_t c0, uint32_t c1, uint32_t c2,
@@ -477,7 +484,13 @@ double orc_resample(const orc_params* p, uint32_t beta, const uint8_t* occ_old,
 
 /* Runs init and M cycles of (dynamics, cloning).  Optional per-interval
  * outputs (may be NULL): lbeta[beta-1] = ln mean Upsilon^beta and
- * mean_kb[beta-1] = population mean of K^beta before cloning. */
+ * mean_kb[beta-1] = population mean of K^beta before cloning.
+ *
+ * Transient-excluded estimates (the transient of Sec. 5.1): psi_burn sums
+ * ln mean Upsilon^beta over beta > burn_in only; for k_hat_burn every clone
+ * carries a second count K' that, like K, it inherits from its ancestor at
+ * each cloning stage, but that grows only by the hops of intervals
+ * beta > burn_in.  Both are divided by the time after burn_in. */
 int orc_run(const orc_params* p, orc_result* res, double* lbeta, double* mean_kb)
 {
     const int64_t Nc = p->Nc;
@@ -490,7 +503,9 @@ int orc_run(const orc_params* p, orc_result* res, double* lbeta, double* mean_kb
     double* A = (double*)malloc(sizeof(double) * (size_t)Nc);
     double* ell = (double*)malloc(sizeof(double) * (size_t)Nc);
     int32_t* anc = (int32_t*)malloc(sizeof(int32_t) * (size_t)Nc);
-    if (!occ || !occ2 || !K || !K2 || !Kb || !A || !ell || !anc) return -2;
+    uint64_t* Kp = (uint64_t*)calloc((size_t)Nc, sizeof(uint64_t));
+    uint64_t* Kp2 = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)Nc);
+    if (!occ || !occ2 || !K || !K2 || !Kb || !A || !ell || !anc || !Kp || !Kp2) return -2;
 
     orc_init(p, occ, K);
     double psi_sum = 0.0, psi_burn_sum = 0.0;
@@ -500,23 +515,77 @@ int orc_run(const orc_params* p, orc_result* res, double* lbeta, double* mean_kb
         uint64_t hb = 0;
         for (int64_t j = 0; j < Nc; ++j) hb += Kb[j];
         hops += hb;
+        if (beta > p->burn_in)
+            for (int64_t j = 0; j < Nc; ++j) Kp[j] += Kb[j];
         double lm = orc_resample(p, (uint32_t)beta, occ, K, ell, occ2, K2, anc);
+        for (int64_t j = 0; j < Nc; ++j) Kp2[j] = Kp[anc[j]];
         psi_sum += lm;
         if (beta > p->burn_in) psi_burn_sum += lm;
         if (lbeta) lbeta[beta - 1] = lm;
         if (mean_kb) mean_kb[beta - 1] = (double)hb / (double)Nc;
         uint8_t* to = occ; occ = occ2; occ2 = to;
         uint64_t* tk = K; K = K2; K2 = tk;
+        tk = Kp; Kp = Kp2; Kp2 = tk;
     }
     double t_obs = (double)p->M * p->dt;
-    double ksum = 0.0;
-    for (int64_t j = 0; j < Nc; ++j) ksum += (double)K[j];
+    double ksum = 0.0, kpsum = 0.0;
+    for (int64_t j = 0; j < Nc; ++j) {
+        ksum += (double)K[j];
+        kpsum += (double)Kp[j];
+    }
+    const double t_after = (double)(p->M - p->burn_in) * p->dt;
     res->psi = psi_sum / t_obs;
-    res->psi_burn = (p->M > p->burn_in)
-                        ? psi_burn_sum / ((double)(p->M - p->burn_in) * p->dt) : 0.0;
+    res->psi_burn = (p->M > p->burn_in) ? psi_burn_sum / t_after : 0.0;
     res->k_hat = ksum / ((double)Nc * (double)L * t_obs);
+    res->k_hat_burn = (p->M > p->burn_in) ? kpsum / ((double)Nc * (double)L * t_after) : 0.0;
     res->hops = hops;
     res->cycles = p->M;
     free(occ); free(occ2); free(K); free(K2); free(Kb); free(A); free(ell); free(anc);
+    free(Kp); free(Kp2);
+    return 0;
+}
+
+/* Ancestral lines (Sec. 2.4): runs init and M cycles like orc_run.  After the
+ * cloning stage of interval beta0 (1 <= beta0 <= M) the population is copied
+ * to occ_b0 and every clone is marked as its own origin; from then on a clone
+ * inherits its ancestor's origin at every cloning stage.  At the end occ_end
+ * holds the final population (after the last cloning stage) and origin[j]
+ * the slot, at beta0, of the ancestor of final clone j.  occ_b0 and occ_end:
+ * Nc * L bytes; origin: Nc entries. */
+int orc_run_lineage(const orc_params* p, int64_t beta0, uint8_t* occ_b0, uint8_t* occ_end,
+                    int32_t* origin)
+{
+    const int64_t Nc = p->Nc;
+    const int L = p->L;
+    if (beta0 < 1 || beta0 > p->M) return -1;
+    uint8_t* occ = (uint8_t*)malloc((size_t)Nc * L);
+    uint8_t* occ2 = (uint8_t*)malloc((size_t)Nc * L);
+    uint64_t* K = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)Nc);
+    uint64_t* K2 = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)Nc);
+    uint32_t* Kb = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)Nc);
+    double* A = (double*)malloc(sizeof(double) * (size_t)Nc);
+    double* ell = (double*)malloc(sizeof(double) * (size_t)Nc);
+    int32_t* anc = (int32_t*)malloc(sizeof(int32_t) * (size_t)Nc);
+    int32_t* org2 = (int32_t*)malloc(sizeof(int32_t) * (size_t)Nc);
+    if (!occ || !occ2 || !K || !K2 || !Kb || !A || !ell || !anc || !org2) return -2;
+
+    orc_init(p, occ, K);
+    for (int64_t beta = 1; beta <= p->M; ++beta) {
+        orc_step(p, (uint32_t)beta, occ, K, Kb, A, ell);
+        orc_resample(p, (uint32_t)beta, occ, K, ell, occ2, K2, anc);
+        if (beta > beta0) {
+            for (int64_t j = 0; j < Nc; ++j) org2[j] = origin[anc[j]];
+            memcpy(origin, org2, sizeof(int32_t) * (size_t)Nc);
+        }
+        uint8_t* to = occ; occ = occ2; occ2 = to;
+        uint64_t* tk = K; K = K2; K2 = tk;
+        if (beta == beta0) {
+            memcpy(occ_b0, occ, (size_t)Nc * L);
+            for (int64_t j = 0; j < Nc; ++j) origin[j] = (int32_t)j;
+        }
+    }
+    memcpy(occ_end, occ, (size_t)Nc * L);
+    free(occ); free(occ2); free(K); free(K2); free(Kb); free(A); free(ell); free(anc);
+    free(org2);
     return 0;
 }

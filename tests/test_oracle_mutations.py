@@ -3,7 +3,9 @@ plausible mistake (a dropped term or factor, a wrong sign, index, constant or
 comparison) and runs the oracle's pins against that copy in a fresh process
 (PD_ORACLE_LIB names the copy); some pin must fail.  The control case compiles
 the unmodified source the same way and must pass, so a failure is the
-mistake's.  The tracked source is never modified.
+mistake's.  The reference Adam step of the guide (oracle/guide_net.py) gets
+the same treatment in-process: each altered copy of the module must fail one
+of its pins.  The tracked sources are never modified.
 
 One plausible mistake is not here because no pin can see it: drawing the
 uniform variate in [0, 1) instead of (0, 1] changes one value in 2^53."""
@@ -18,6 +20,7 @@ ORACLE_C = os.path.join(ROOT, "oracle", "oracle.c")
 PLAIN = ["tests/test_oracle_dynamics.py", "tests/test_oracle_selection.py",
          "tests/test_oracle_run.py"]
 GUIDED = ["tests/test_oracle_guided.py"]
+ESTIMATORS = ["tests/test_oracle_run.py", "tests/test_oracle_estimators.py"]
 
 MUTATIONS = [
     ("select_bit_off_by_one", "if (seen == q) return i;", "if (seen == q) return (i + 1) % L;",
@@ -55,6 +58,28 @@ MUTATIONS = [
      "if (mulhi64(word_of(y[0], y[1]), (uint64_t)egmax) < (uint64_t)e) break;",
      "if (1) break;", GUIDED),
     ("guided_drops_jump_term", "G += log((double)e * 0x1p-16);", "G += 0.0;", GUIDED),
+    ("psi_burn_counts_burn_in_interval", "if (beta > p->burn_in) psi_burn_sum += lm;",
+     "if (beta >= p->burn_in) psi_burn_sum += lm;", ESTIMATORS),
+    ("k_burn_counts_burn_in_interval",
+     "if (beta > p->burn_in)\n            for (int64_t j = 0; j < Nc; ++j) Kp[j] += Kb[j];",
+     "if (beta >= p->burn_in)\n            for (int64_t j = 0; j < Nc; ++j) Kp[j] += Kb[j];",
+     ESTIMATORS),
+    ("k_burn_not_inherited", "Kp2[j] = Kp[anc[j]];", "Kp2[j] = Kp[j];", ESTIMATORS),
+    ("log_keeps_running_sum", "if (lbeta) lbeta[beta - 1] = lm;",
+     "if (lbeta) lbeta[beta - 1] = psi_sum;", ESTIMATORS),
+    ("log_mean_hops_cumulative", "mean_kb[beta - 1] = (double)hb / (double)Nc;",
+     "mean_kb[beta - 1] = (double)hops / (double)Nc;", ESTIMATORS),
+    ("lineage_origin_not_inherited", "org2[j] = origin[anc[j]];", "org2[j] = origin[j];",
+     ["tests/test_oracle_estimators.py"]),
+]
+
+ADAM_MUTATIONS = [
+    ("adam_no_first_bias_correction", "mh = m / (1 - b1 ** step)", "mh = m"),
+    ("adam_no_second_bias_correction", "vh = v / (1 - b2 ** step)", "vh = v"),
+    ("adam_eps_inside_root", "np.sqrt(vh) + eps", "np.sqrt(vh + eps)"),
+    ("adam_second_moment_of_abs", "(1 - b2) * g * g", "(1 - b2) * np.abs(g)"),
+    ("adam_first_moment_decay", "m = b1 * m + (1 - b1) * g", "m = b2 * m + (1 - b2) * g"),
+    ("adam_ascends", "return theta - lr * mh", "return theta + lr * mh"),
 ]
 
 
@@ -71,7 +96,7 @@ def _run_pins(tmp_path, source, files):
 
 
 def test_unmodified_copy_passes(tmp_path):
-    r = _run_pins(tmp_path, open(ORACLE_C).read(), PLAIN + GUIDED)
+    r = _run_pins(tmp_path, open(ORACLE_C).read(), PLAIN + GUIDED + ESTIMATORS[1:])
     assert r.returncode == 0, r.stdout[-3000:]
 
 
@@ -82,3 +107,22 @@ def test_planted_mistake_fails_a_pin(tmp_path, name, orig, mutated, files):
     r = _run_pins(tmp_path, source.replace(orig, mutated), files)
     # 1: a test failed (not a crash, a collection error or an interruption)
     assert r.returncode == 1, (name, r.stdout[-3000:])
+
+
+@pytest.mark.parametrize("name,orig,mutated", ADAM_MUTATIONS, ids=[m[0] for m in ADAM_MUTATIONS])
+def test_planted_adam_mistake_fails_a_pin(name, orig, mutated):
+    import importlib.util
+    import test_guide_net_adam as pins
+    path = os.path.join(ROOT, "oracle", "guide_net.py")
+    source = open(path).read()
+    assert source.count(orig) == 1, name
+    spec = importlib.util.spec_from_loader("guide_net_mutant", loader=None)
+    mod = importlib.util.module_from_spec(spec)
+    exec(compile(source.replace(orig, mutated), path, "exec"), mod.__dict__)
+    failed = []
+    for pin in pins.PINS:
+        try:
+            pin(mod.adam)
+        except AssertionError:
+            failed.append(pin.__name__)
+    assert failed, name

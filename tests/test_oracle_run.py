@@ -4,7 +4,8 @@
     = Z(s, t) exactly (the identity behind eq. Z-ups with unbiased selection),
     so the mean of exp(t psi-hat) over many independent runs must match the
     exact-diagonalisation Z within its standard error, for [eq] and [iid],
-    modified and direct weights;
+    modified and direct weights; the same holds for the product over the
+    first b intervals of the per-interval log, against Z(s, b dt);
   * s = 0 with modified dynamics: every weight is exactly 1, [eq] is the
     identity, psi-hat is exactly 0 (Sec. 4.3);
   * N = 1: r = 2 always, psi-hat = 2(e^{-s} - 1) up to rounding;
@@ -49,15 +50,25 @@ def test_zero_bias_activity():
     (8, 0.5, oracle.DIRECT, oracle.SEL_EQ, 20000),
 ])
 def test_unbiased_partition_function(Nc, s, mode, sel, runs):
+    """Also interval by interval: the product of the first b per-interval
+    means, exp(lbeta_1 + ... + lbeta_b), is unbiased for Z(s, b dt) for every
+    b, so the per-interval log is pinned at s != 0 too."""
     L, N, dt, M = 6, 3, 0.25, 4
     t = M * dt
     vals = np.empty(runs)
+    prefix = np.empty((runs, M))
     for i in range(runs):
-        r = oracle.Oracle(L, N, s, Nc, dt, M=M, seed=10_000 + i, mode=mode, selection=sel).run()
+        r = oracle.Oracle(L, N, s, Nc, dt, M=M, seed=10_000 + i, mode=mode,
+                          selection=sel).run(per_interval=True)
         vals[i] = np.exp(t * r["psi"])
+        prefix[i] = np.exp(np.cumsum(r["lbeta"]))
     Z = ed.partition(L, N, s, t)
     se = vals.std() / np.sqrt(runs)
     assert abs(vals.mean() - Z) < 5 * se, (vals.mean(), Z, se)
+    for b in range(1, M + 1):
+        Zb = ed.partition(L, N, s, b * dt)
+        seb = prefix[:, b - 1].std() / np.sqrt(runs)
+        assert abs(prefix[:, b - 1].mean() - Zb) < 5 * seb, (b, prefix[:, b - 1].mean(), Zb, seb)
 
 
 @pytest.mark.parametrize("s", [-0.4, 0.2, 0.4])
