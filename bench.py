@@ -1,24 +1,31 @@
-"""Throughput of the cloning algorithm on one MI355X: clone-hops per second.
+"""Throughput of the cloning algorithm on one MI355X: clone-hops per second,
+and the wall time to |delta psi| <= 1e-3, guided against plain.
 
-Workload (the L=100 transition sweep): periodic SSEP with L=100, N=50, 32
-scaled biases lambda = s L^2 evenly spaced over [-10, 20], Nc = 1e5 clones
-each, Delta t = 0.5, t_obs = 2000 (4000 cloning intervals), [eq] selection,
-modified (e^{-s}-scaled) dynamics, uniform random initial configurations,
-Philox seeds 2000 + i.  All 32 instances run as one batch: one step = one
-cloning interval of the whole sweep (the dynamical stage of 3.2e6 clones,
-then the cloning stage of each instance).  The reported value is the number of
-hops performed in the timed steps divided by their wall time; the cloning
-stage is inside the timed region.
+Default line (the L=100 transition sweep): periodic SSEP with L=100, N=50,
+32 scaled biases lambda = s L^2 evenly spaced over [-10, 20], Nc = 1e5 clones
+each, Delta t = 0.5, [eq] selection, modified (e^{-s}-scaled) dynamics,
+uniform random initial configurations, Philox seeds 2000 + i.  All 32
+instances run as one batch: one step = one cloning interval of the whole
+sweep (the dynamical stage of 3.2e6 clones, then the cloning stage of each
+instance).  `value` is the number of hops performed in the K timed steps --
+replayed from captured HIP graphs, as pd_run runs them -- divided by their
+wall time; the cloning stage is inside the timed region.  A separate pass of
+single launches with HIP events on the sampler's stream (pd_time_stages)
+gives the step kernel's duration for the ALU roofline and the split between
+the stages.  The line also carries the bounded guided-vs-plain leg
+(bench_guided_vs_plain) and the CPU oracle's rate (cpu_baseline, one core and
+one process per core).
 
 Usage: python bench.py [--steps K] [--warmup W] [--nc NC] [--no-cpu-baseline]
+                       [--no-guided]
 By default W + K = 4000 so that the run covers exactly t_obs = 2000.
 
 --workload batch: 64 uneven instances in one context against 64 sequential
 contexts.  --workload guided-rate: guided against plain throughput at L=100,
-lambda=15.  --workload large: the L=400, Nc=1e6 workload, plain and guided.  --workload guide: wall time to |delta psi| <= 1e-3, guided
-against plain, at L=100 (lambda = 5, 10, 15, 20, Delta t = 0.5) and at the
-paper's phase-separated state point L=50, lambda=50 (Delta t = 10,
-t_obs = 1e4); see bench_guide.
+lambda=15.  --workload large: the L=400, Nc=1e6 workload, plain and guided.
+--workload guide: the wider wall-time study, at L=100 (lambda = 5, 10, 15,
+20, Delta t = 0.5), at L=50, lambda=50 (Delta t = 10, t_obs = 1e4) and at
+L=400; see bench_guide.
 """
 import argparse
 import hashlib
@@ -37,13 +44,23 @@ from paper_1711_05095_amd import inputs, pd  # noqa: E402
 # Published MI355X figures (vector ALU): 256 CUs x 64 lanes x 2.4 GHz.
 PEAK_VALU_LANE_OPS = 256 * 64 * 2.4e9
 PEAK_HBM_GBS = 8000.0
-# VALU instructions in one pass of the event loop of the step kernel (W = 2),
-# counted from its gfx950 assembly by paper_1711_05095_amd.isa_count (a test
-# keeps this constant equal to that count).  It is the algorithmic work of an
-# event for every variant (the compacting variant's loop has the same count;
-# its rounds' bookkeeping lies outside the loop and counts as overhead).
+# The unit of the ALU roofline: one event (one Philox4x32-10 block, the
+# waiting time with its logarithm, the choice and execution of a hop, the
+# update of the escape rate) counts as 160 VALU instructions, the count of the
+# event loop of k_step<2> in its gfx950 assembly (paper_1711_05095_amd.isa_count)
+# at commit 6d3c1d5.  The unit is frozen there, so `frac` follows throughput: a
+# leaner loop raises it (a test checks the loop has not grown past the unit).
+# Every variant runs the same loop; the compacting variant's rounds of
+# bookkeeping lie outside it and count as overhead.
 VALU_PER_EVENT_W2 = 160
-VALU_PER_EVENT_W7 = 285   # the same loop for 400-site states (7 words)
+VALU_PER_EVENT_W7 = 285   # the same loop for 400-site states (7 words), same commit
+VALU_UNIT_SOURCE = "event loop of k_step<2> at commit 6d3c1d5"
+# Counter readings of the step kernel on the bench's workload (rocprofv3
+# SQ_INSTS_VALU, SQ_BUSY_CYCLES, SQ_WAVES; profiles/k_step_sweep_L100_Nc1e5.txt):
+# VALU wave-instructions issued per CU per cycle of the kernel, and the
+# fraction of issued lane slots that the frozen unit accounts for.
+STEP_COUNTERS = {"source": "profiles/k_step_sweep_L100_Nc1e5.txt",
+                 "valu_issue_per_cu_cycle": 0.964, "lane_utilisation": 0.78}
 # HBM bytes the cloning stage must move per clone: ln Ups read (8) by the
 # resample scan, ancestor written (4); the gather of the states is fused into
 # the next dynamical stage's load.
@@ -69,7 +86,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=16)
     ap.add_argument("--nc", type=int, default=100_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-cycles", type=int, default=8)
+    ap.add_argument("--cpu-cycles", type=int, default=6,
+                    help="timed oracle intervals of the CPU baseline (after --cpu-warm)")
+    ap.add_argument("--cpu-warm", type=int, default=2)
+    ap.add_argument("--no-guided", action="store_true",
+                    help="leave out the guided-vs-plain wall-time leg of the default line")
     ap.add_argument("--variant", type=int, default=None,
                     help="step kernel variant (default: chosen by the autotuner)")
     ap.add_argument("--refill", type=int, default=13,
@@ -147,7 +168,9 @@ def bench_batch(a):
 
 
 def _estimates(L, N, lam, Nc, t_obs, dt, reps, mode, eg=None, seed=0, inst0=1):
-    """psi-hat of `reps` independent runs (one batch) and the wall time."""
+    """psi-hat of `reps` independent runs (one batch) and the wall time of the
+    run (the context, its initial condition and its captured graphs are made
+    before the clock starts)."""
     import torch
     s = inputs.s_of_lambda(lam, L)
     ps = [pd.make_params(L, N, s, Nc, t_obs, dt, seed=seed, weight_mode=mode, instance=inst0 + r)
@@ -155,6 +178,7 @@ def _estimates(L, N, lam, Nc, t_obs, dt, reps, mode, eg=None, seed=0, inst0=1):
     S = pd.Sampler(ps)
     if eg is not None:
         S.set_guide(eg)
+    S.run(0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     S.run(int(round(t_obs / dt)))
@@ -373,19 +397,225 @@ def bench_large(a):
             "resample_peak_GBps": PEAK_HBM_GBS, "points": rows}
 
 
-def cpu_baseline(nc, cycles):
-    """The test oracle (plain single-threaded C) on a bounded sample of the
-    same workload: instance lambda = 20, Nc clones, `cycles` intervals."""
+def _oracle_job(job):
+    """One oracle run of the sweep's lambda = 20 instance (a worker of
+    cpu_baseline): `warm` untimed intervals after the initial condition, then
+    `cycles` timed ones.  Returns (hops in the timed intervals, seconds)."""
     import oracle
+    nc, warm, cycles, seed = job
     w = inputs.SWEEP
-    s = inputs.s_of_lambda(20.0, w["L"])
-    o = oracle.Oracle(w["L"], w["N"], s, nc, w["dt"], M=cycles, seed=w["seed0"])
+    o = oracle.Oracle(w["L"], w["N"], inputs.s_of_lambda(20.0, w["L"]), nc, w["dt"],
+                      M=warm + cycles, seed=seed)
+    occ, K = o.init()
+    hops, el = 0, 0.0
+    for beta in range(1, warm + cycles + 1):
+        t0 = time.perf_counter()
+        Kb, _, ell = o.step(beta, occ, K)
+        occ, K, _, _ = o.resample(beta, occ, K, ell)
+        if beta > warm:
+            el += time.perf_counter() - t0
+            hops += int(Kb.sum())
+    return hops, el
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(nc, warm, cycles):
+    """The test oracle (plain single-threaded C, the analogue of the paper's
+    serial run time) on a bounded sample of the sweep: its lambda = 20
+    instance with Nc clones, `cycles` intervals timed after `warm` (the
+    initial condition and the first intervals excluded; dynamics and cloning
+    both timed).  First one process alone, then n independent jobs (distinct
+    seeds) as n processes at once, n = min(16, the CPUs this process may
+    use).  Runs before anything touches the GPU: the workers are spawned, not
+    forked."""
+    import multiprocessing as mp
+    h1, t1 = _oracle_job((nc, warm, cycles, inputs.SWEEP["seed0"] + 20))
+    n = max(1, min(16, len(os.sched_getaffinity(0))))
+    ctx = mp.get_context("spawn")
     t0 = time.perf_counter()
-    r = o.run()
-    dt = time.perf_counter() - t0
-    return {"value": r["hops"] / dt, "unit": "clone-hops/s", "cores": 1, "kind": "oracle",
-            "sample": "lambda=20 instance of the sweep, Nc=%d, %d intervals (%d hops, "
-                      "init included), %.1f s" % (nc, cycles, r["hops"], dt)}
+    with ctx.Pool(n) as pool:
+        res = pool.map(_oracle_job, [(nc, warm, cycles, 9000 + k) for k in range(n)])
+    wall = time.perf_counter() - t0
+    # the n-process rate counts the timed intervals of every job over the
+    # longest job's timed span (their initial conditions overlap other jobs'
+    # timed intervals only to the advantage of the single-job figure)
+    hn = sum(h for h, _ in res)
+    tn = max(t for _, t in res)
+    return {"value": h1 / t1, "unit": "clone-hops/s", "cores": 1, "kind": "oracle",
+            "sample": "lambda=20 instance of the sweep (L=100, N=50, dt=0.5), Nc=%d, %d intervals "
+                      "timed after %d (init excluded), %d hops in %.1f s" % (nc, cycles, warm, h1, t1),
+            "n_core": {"value": hn / tn, "unit": "clone-hops/s", "cores": n, "processes": n,
+                       "wall_seconds": wall,
+                       "sample": "%d independent seeds of the same job, one process each" % n},
+            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count()}
+
+
+def bench_sweep(a):
+    """The L=100 transition sweep as one batch of 32 instances: the headline
+    rate through pd_run's graph replays, then an evented pass (single
+    launches with HIP events on the sampler's stream around each stage) for
+    the step kernel's duration and the step/cloning split."""
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w = inputs.SWEEP
+    L, N, dt = w["L"], w["N"], w["dt"]
+    n_ev = max(8, min(a.steps, 50))
+    total = a.warmup + a.steps + n_ev
+    params = [pd.make_params(L, N, inputs.s_of_lambda(lam, L), a.nc, total * dt, dt,
+                             seed=w["seed0"] + i, instance=i)
+              for i, lam in enumerate(w["lambdas"])]
+    S = pd.Sampler(params)
+    if a.variant is None:
+        tuning = S.autotune(24)          # restores the population afterwards
+    else:
+        S.set_tuning(a.variant, a.refill, 16, a.scan_tiles)
+        tuning = S.tuning()
+    S.run(a.warmup)
+    S.run(0)                             # captures the graphs (runs nothing)
+    torch.cuda.synchronize()
+    hops0 = sum(S.estimates(i)["hops"] for i in range(S.n))
+    # timed region: the product path, graph-replayed cycles
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.run(a.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    est = [S.estimates(i) for i in range(S.n)]
+    hops = sum(e["hops"] for e in est) - hops0
+    # evented pass: the same kind of cycles, single launches
+    S.time_stages(True)
+    for _ in range(n_ev):
+        S.step()
+        S.resample()
+    tm = S.stage_times()
+    S.time_stages(False)
+    hops_ev = sum(S.estimates(i)["hops"] for i in range(S.n)) - hops0 - hops
+    # events of the step kernel = hops + one closing draw per clone per interval
+    events_per_launch = (hops_ev + n_ev * a.nc * S.n) / n_ev
+    step_s = tm["step_ms"] / 1e3
+    achieved = events_per_launch * VALU_PER_EVENT_W2 / step_s
+    res_bytes = RESAMPLE_BYTES_PER_CLONE * a.nc * S.n
+    value = hops / elapsed
+    sha = step_sources_sha1()
+    kname = {0: "k_step<2>", 4: "k_step_c<2>"}.get(tuning["step_variant"], "k_step_q<2>")
+    traffic = STEP_TRAFFIC["bytes"] if (sha == STEP_TRAFFIC["kernels_sha1"] and a.nc == 100_000
+                                        and kname == STEP_TRAFFIC["kernel"]) else None
+    return {
+        "metric": "clone-hops/s",
+        "value": value,
+        "unit": "clone-hops/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": elapsed / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "L=100 N=50 transition sweep: 32 lambdas in [-10,20], "
+                               "Nc=%d each, dt=0.5, [eq], modified dynamics, one batch; "
+                               "timed: %d graph-replayed cycles after %d" % (a.nc, a.steps, a.warmup),
+                   "instances": S.n, "Nc": a.nc, "L": L, "N": N, "dt": dt},
+        "roofline": {"bound": "alu", "kernel": kname,
+                     "achieved": achieved / 1e12, "peak": PEAK_VALU_LANE_OPS / 1e12,
+                     "unit": "T VALU lane-instr/s", "frac": achieved / PEAK_VALU_LANE_OPS,
+                     "traffic": traffic,
+                     "per_unit": "%d VALU instr per event (%s)" % (VALU_PER_EVENT_W2,
+                                                                   VALU_UNIT_SOURCE),
+                     "events_per_launch": events_per_launch,
+                     "kernel_ms_mean": tm["step_ms"], "evented_launches": tm["steps"],
+                     "counters": STEP_COUNTERS},
+        "stages_ms": {"step_kernels": tm["step_ms"], "prefix": tm["prefix_ms"],
+                      "cloning": tm["resample_ms"],
+                      "cycle_graph_replay": elapsed / a.steps * 1e3},
+        "resample": {"bound": "hbm", "kernel": "k_resample",
+                     "achieved": res_bytes / (tm["resample_ms"] / 1e3) / 1e9,
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": res_bytes / (tm["resample_ms"] / 1e3) / 1e9 / PEAK_HBM_GBS,
+                     "bytes_per_launch": res_bytes},
+        "tuning": tuning,
+        "physics": {"t_obs": (a.warmup + a.steps) * dt,
+                    "note": "transient values from a uniform start unless t_obs >> 100",
+                    "lambda": w["lambdas"][::8],
+                    "psi": [est[i]["psi"] for i in range(0, S.n, 8)],
+                    "k_hat": [est[i]["k_hat"] for i in range(0, S.n, 8)]},
+    }
+
+
+def bench_guided_vs_plain(a):
+    """The metric's second half, bounded: wall time to |delta psi| <= 1e-3,
+    guided against plain, at the paper's phase-separated state point
+    (L=50, N=25, lambda=50, dt=10, t_obs=1e4) and at L=100 near the
+    transition (lambda=20, dt=0.5) on a grid reaching down to Nc=10 and
+    t_obs=10.  For each form: the RMS error over 8 seeds against psi_ref at
+    every grid point; among the points that pass (RMS <= 1e-3), the smallest
+    passing Nc at each t_obs is timed (one run, median of 3), and the fastest
+    is the form's result.  psi_ref = mean of 2 plain runs at Nc=1e6 and the
+    same t_obs.  The guide is trained on the GPU from plain populations
+    (Nc=1e5) and distilled on them; its training time is reported apart."""
+    import torch
+    from paper_1711_05095_amd import guide
+    t_start = time.perf_counter()
+    points = [dict(L=50, N=25, lam=50.0, dt=10.0, t_grid=[10000.0],
+                   nc_grid=[1000, 3000, 10000, 30000], lag=5, snapshots=10, burn=100),
+              dict(L=100, N=50, lam=20.0, dt=0.5, t_grid=[10.0, 25.0, 50.0, 100.0],
+                   nc_grid=[10, 30, 100, 300, 1000], lag=100, snapshots=10, burn=400)]
+    tol, reps = 1e-3, 8
+    out = []
+    for P in points:
+        L, N, lam, dt = P["L"], P["N"], P["lam"], P["dt"]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = guide.train_guide(L, N, inputs.s_of_lambda(lam, L), Nc=100_000, dt=dt,
+                              lag_cycles=P["lag"], snapshots=P["snapshots"],
+                              burn_cycles=P["burn"], epochs=10, lr=1e-3, decay=0.8, gmax=1.0,
+                              seed=9)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        refs = {}
+        for t_obs in P["t_grid"]:
+            psi, _ = _estimates(L, N, lam, 1_000_000, t_obs, dt, 2, pd.PD_W_MODIFIED, seed=1,
+                                inst0=100)
+            refs[t_obs] = float(psi.mean())
+        row = {"L": L, "N": N, "lambda": lam, "dt": dt, "train_seconds": t_train,
+               "psi_ref": {str(k): v for k, v in refs.items()}, "grid": []}
+        for name, mode, eg in (("plain", pd.PD_W_MODIFIED, None),
+                               ("guided", pd.PD_W_GUIDED, g["eg"])):
+            passing = {}
+            for t_obs in P["t_grid"]:
+                for nc in P["nc_grid"]:
+                    psi, _ = _estimates(L, N, lam, nc, t_obs, dt, reps, mode, eg, seed=2)
+                    rms = float(np.sqrt(np.mean((psi - refs[t_obs]) ** 2)))
+                    row["grid"].append({"form": name, "Nc": nc, "t_obs": t_obs, "rms": rms})
+                    print("  L=%d lambda=%g %s Nc=%d t_obs=%g: rms %.2e"
+                          % (L, lam, name, nc, t_obs, rms), file=sys.stderr, flush=True)
+                    if rms <= tol:
+                        passing[t_obs] = (nc, rms)
+                        break
+            found = None
+            for t_obs, (nc, rms) in passing.items():
+                times = [_estimates(L, N, lam, nc, t_obs, dt, 1, mode, eg, seed=3)[1]
+                         for _ in range(3)]
+                cand = {"Nc": nc, "t_obs": t_obs, "rms": rms, "seconds": float(np.median(times))}
+                if found is None or cand["seconds"] < found["seconds"]:
+                    found = cand
+            row[name] = found
+        if row["plain"] and row["guided"]:
+            row["plain_over_guided"] = row["plain"]["seconds"] / row["guided"]["seconds"]
+        out.append(row)
+    return {"metric": "wall time to |dpsi|<=1e-3 (RMS over 8 seeds vs plain Nc=1e6, same t_obs), "
+                      "plain/guided",
+            "points": out, "seconds": time.perf_counter() - t_start}
 
 
 def main():
@@ -409,93 +639,18 @@ def main():
     if a.workload == "large":
         print(json.dumps(bench_large(a)), flush=True)
         return
-    import torch
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    w = inputs.SWEEP
-    L, N, dt = w["L"], w["N"], w["dt"]
-    total = a.warmup + a.steps
-    params = [pd.make_params(L, N, inputs.s_of_lambda(lam, L), a.nc, total * dt, dt,
-                             seed=w["seed0"] + i, instance=i)
-              for i, lam in enumerate(w["lambdas"])]
-    S = pd.Sampler(params)
-    st = S.stream
-
-    if a.variant is None:
-        tuning = S.autotune(24)          # restores the population afterwards
-    else:
-        S.set_tuning(a.variant, a.refill, 16, a.scan_tiles)
-        tuning = S.tuning()
-    for _ in range(a.warmup):
-        S.step()
-        S.resample()
-    torch.cuda.synchronize()
-    hops0 = sum(S.estimates(i)["hops"] for i in range(S.n))
-
-    ev = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(a.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(a.steps):
-        ev[k][0].record(st)
-        S.step()
-        ev[k][1].record(st)
-        S.resample()
-        ev[k][2].record(st)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-
-    est = [S.estimates(i) for i in range(S.n)]
-    hops = sum(e["hops"] for e in est) - hops0
-    step_ms = np.array([e0.elapsed_time(e1) for e0, e1, _ in ev])
-    res_ms = np.array([e1.elapsed_time(e2) for _, e1, e2 in ev])
-    res_bytes = RESAMPLE_BYTES_PER_CLONE * a.nc * S.n
-    value = hops / elapsed
-    # events of the step kernel = hops + one closing draw per clone per interval
-    events_per_launch = (hops + a.steps * a.nc * S.n) / a.steps
-    step_s = float(step_ms.mean()) / 1e3
-    achieved = events_per_launch * VALU_PER_EVENT_W2 / step_s
-
-    sha = step_sources_sha1()
-    kname = {0: "k_step<2>", 4: "k_step_c<2>"}.get(tuning["step_variant"], "k_step_q<2>")
-    traffic = STEP_TRAFFIC["bytes"] if (sha == STEP_TRAFFIC["kernels_sha1"] and a.nc == 100_000
-                                        and kname == STEP_TRAFFIC["kernel"]) else None
-    out = {
-        "metric": "clone-hops/s",
-        "value": value,
-        "unit": "clone-hops/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": elapsed / a.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": "L=100 N=50 transition sweep: 32 lambdas in [-10,20], "
-                               "Nc=%d each, dt=0.5, t_obs=%g, [eq], modified dynamics, "
-                               "one batch" % (a.nc, total * dt),
-                   "instances": S.n, "Nc": a.nc, "L": L, "N": N, "dt": dt,
-                   "intervals": total},
-        "roofline": {"bound": "alu", "kernel": kname,
-                     "achieved": achieved / 1e12, "peak": PEAK_VALU_LANE_OPS / 1e12,
-                     "unit": "T VALU lane-instr/s", "frac": achieved / PEAK_VALU_LANE_OPS,
-                     "traffic": traffic,
-                     "per_unit": "%d VALU instr per event" % VALU_PER_EVENT_W2,
-                     "events_per_launch": events_per_launch,
-                     "step_ms_mean": float(step_ms.mean()),
-                     "step_ms_median": float(np.median(step_ms))},
-        "resample": {"bound": "hbm", "kernel": "k_resample",
-                     "achieved": res_bytes / (float(res_ms.mean()) / 1e3) / 1e9,
-                     "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": res_bytes / (float(res_ms.mean()) / 1e3) / 1e9 / PEAK_HBM_GBS,
-                     "bytes_per_launch": res_bytes, "ms_mean": float(res_ms.mean())},
-        "tuning": tuning,
-        "physics": {"lambda": w["lambdas"][::8],
-                    "psi": [est[i]["psi"] for i in range(0, S.n, 8)],
-                    "k_hat": [est[i]["k_hat"] for i in range(0, S.n, 8)]},
-    }
+    cpu = None
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(a.nc, a.cpu_cycles)
+        # before anything touches the GPU (the worker processes are spawned)
+        cpu = cpu_baseline(a.nc, a.cpu_warm, a.cpu_cycles)
+        print("cpu baseline done: %.3g clone-hops/s on 1 core" % cpu["value"], file=sys.stderr,
+              flush=True)
+    out = bench_sweep(a)
+    print("sweep done: %.4g clone-hops/s" % out["value"], file=sys.stderr, flush=True)
+    if not a.no_guided:
+        out["guided_vs_plain"] = bench_guided_vs_plain(a)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

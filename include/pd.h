@@ -88,7 +88,8 @@ typedef struct {
     uint32_t instance;    /* Philox counter tag, < 2^24; distinct per instance of a batch */
     int32_t  log_cycles;  /* >= 0: keep per-interval (ln mean Ups, mean K^beta) for the
                              first log_cycles intervals (see pd_get_log) */
-    int64_t  burn_in;     /* >= 0: intervals left out of psi_burn (pd_estimates) */
+    int64_t  burn_in;     /* >= 0: intervals left out of psi_burn and k_hat_burn
+                             (pd_estimates); > 0 adds 16 bytes per clone of workspace */
     int32_t  track_origin;/* 1: every clone carries the slot it descended from at the last
                              pd_reset_origin (ancestral lines, Sec. 2.4); 0: off */
     int32_t  reserved;    /* must be 0 */
@@ -96,11 +97,18 @@ typedef struct {
 
 typedef struct {
     double   psi;         /* psi-hat = (1/(beta dt)) sum over completed intervals */
-    double   psi_burn;    /* the same sum over intervals beyond burn_in, / ((beta-burn_in) dt) */
+    double   psi_burn;    /* the same sum over intervals beyond burn_in, / ((beta-burn_in) dt);
+                             0 until beta > burn_in */
     double   k_hat;       /* sum_j K_j / (Nc L beta dt) over the current population */
     double   t;           /* beta * dt */
     int64_t  cycles;      /* beta: completed (dynamics, cloning) cycles */
     uint64_t hops;        /* every hop performed by every clone so far */
+    double   k_hat_burn;  /* k_hat with the transient left out (Sec. 5.1): sum_j K'_j /
+                             (Nc L (beta-burn_in) dt), K'_j = the hops of the intervals beyond
+                             burn_in along clone j's ancestral line (K_j minus the K its
+                             ancestor carried at the end of interval burn_in); equal to k_hat
+                             when burn_in = 0; 0 until beta > burn_in.  With burn_in > 0,
+                             pd_set_population restarts K' at 0 for the clones it installs */
 } pd_estimates;
 
 typedef struct pd_ctx pd_ctx;   /* opaque, host-side, owned by the library */
@@ -131,14 +139,25 @@ pd_status pd_step(pd_ctx* ctx);
  * immediately before. Asynchronous. */
 pd_status pd_resample(pd_ctx* ctx);
 
-/* `cycles` repetitions of (pd_step, pd_resample), replayed from captured HIP
- * graphs.  PD_ESTATE if a pd_step is waiting for its pd_resample. */
+/* `cycles` repetitions of (pd_step, pd_resample) -- the cloning algorithm's
+ * cycle of Sec. 2.3 -- replayed from captured HIP graphs of graph_cycles
+ * cycles (pd_tuning; the remainder as single launches).  Asynchronous.
+ * cycles = 0 runs nothing and captures the graphs that later calls replay (a
+ * graph is otherwise captured on its first use).  Graphs need a stream other
+ * than the legacy default stream; with NULL every cycle is a single launch.
+ * PD_ESTATE if a pd_step is waiting for its pd_resample. */
 pd_status pd_run(pd_ctx* ctx, int64_t cycles);
 
-/* Estimates of instance 0 (synchronises the stream). */
+/* Estimates of instance 0 (synchronises the stream): psi-hat = (1/(beta dt))
+ * sum over the completed intervals of ln((1/Nc) sum_i Upsilon_i) (eq. psihat),
+ * k-hat = sum_j K_j / (Nc L beta dt) (eq. khat, with the 1/Nc the printed
+ * formula omits), and beta.  Any output pointer may be NULL. */
 pd_status pd_scgf(pd_ctx* ctx, double* psi, double* k_hat, int64_t* cycles_done);
 
-/* Estimates of instance `inst` (synchronises the stream). */
+/* Estimates of instance `inst` (synchronises the stream): psi-hat (eq. psihat),
+ * k-hat (eq. khat with the 1/Nc the printed formula omits; K carried along
+ * the ancestral lines, Sec. 4.2) and both with the first burn_in intervals
+ * left out (the transient of Sec. 5.1). */
 pd_status pd_estimates_get(pd_ctx* ctx, int32_t inst, pd_estimates* out);
 
 /* Host image of a population: uint64 state words [W][Nc] (word w of clone j
@@ -230,8 +249,11 @@ pd_status pd_load(pd_ctx* ctx, const void* host, size_t bytes);
  * -sum_jumps g - integral (r - e^{-s} sum_b eg[u_b] / 2^16) dt, so psi-hat
  * stays unbiased for any table.  Entries of neighbourhoods whose bits 6 and 7
  * are equal must be 0, the others in [1, 2^31) with largest/smallest <= 1024;
- * PD_EINVAL otherwise, and also if d_table is not 16-byte aligned.  The table
- * must outlive its use.  Synchronises. */
+ * PD_EINVAL otherwise (the guide in use is then unchanged), and also if
+ * d_table is not 16-byte aligned.  The library copies the table into its
+ * workspace, so the caller may change or free d_table once the call returns;
+ * a changed table takes effect only through another pd_set_guide.
+ * Synchronises. */
 pd_status pd_set_guide(pd_ctx* ctx, const uint32_t* d_table, size_t n);
 
 /* Launch configuration of the dynamical stage.  It never changes results
@@ -266,6 +288,24 @@ pd_status pd_set_tuning(pd_ctx* ctx, const pd_tuning* tuning);
  * estimator state exactly as they were, and keeps the fastest configuration
  * (also written to `best` if not NULL).  Synchronises. */
 pd_status pd_autotune(pd_ctx* ctx, int32_t trial_cycles, pd_tuning* best);
+
+/* Stage timing, for measurement.  pd_time_stages(ctx, 1) discards earlier
+ * records and makes every later pd_step and pd_resample (and the single
+ * launches of pd_run, never its graph replays, nor the autotuner's trials)
+ * record HIP events on the context stream around its kernels: the dynamical
+ * stage's launches, the interval statistics (k_prefix) and the cloning stage.
+ * pd_get_stage_times synchronises and returns the mean durations over the
+ * recorded calls; pd_time_stages(ctx, 0) stops recording.  Both return
+ * PD_ESTATE between pd_step and pd_resample. */
+typedef struct {
+    double  step_ms;      /* dynamical-stage kernels of one pd_step */
+    double  prefix_ms;    /* interval statistics of one pd_step */
+    double  resample_ms;  /* cloning-stage kernels of one pd_resample */
+    int64_t steps;        /* recorded pd_step calls */
+    int64_t resamples;    /* recorded pd_resample calls */
+} pd_stage_times;
+pd_status pd_time_stages(pd_ctx* ctx, int32_t enable);
+pd_status pd_get_stage_times(pd_ctx* ctx, pd_stage_times* out);
 
 /* Human-readable message of the last error on ctx (or of the last failed
  * pd_create when ctx is NULL). */

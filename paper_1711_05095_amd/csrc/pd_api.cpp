@@ -115,7 +115,8 @@ std::string validate(const pd_params& p)
 }
 
 struct Layout {
-    size_t state[2], K[2], Kb, A, ell, anc, origin[2], ykey, tmax, tsum, thops, toff, log, ctl;
+    size_t state[2], K[2], Kb, A, ell, anc, origin[2], ksnap[2], ykey, tmax, tsum, thops, toff,
+        log, ctl;
     size_t cu64, cf64, cu32;   // guided continuation records (0: not guided)
     size_t end;
     int ntiles;
@@ -140,6 +141,8 @@ Layout layout_of(const pd_params& p, size_t base)
     o.anc = take(4 * Nc);
     o.origin[0] = p.track_origin ? take(4 * Nc) : 0;
     o.origin[1] = p.track_origin ? take(4 * Nc) : 0;
+    o.ksnap[0] = p.burn_in > 0 ? take(8 * Nc) : 0;
+    o.ksnap[1] = p.burn_in > 0 ? take(8 * Nc) : 0;
     o.ykey = (p.selection == PD_SEL_IID) ? take(8 * Nc) : 0;
     // records of clones the guided stage's first launch hands on to its second
     const bool guided = p.weight_mode == PD_W_GUIDED;
@@ -157,7 +160,7 @@ Layout layout_of(const pd_params& p, size_t base)
 }
 
 struct Plan {
-    size_t insts_off, tiles_off, log_off, sel_off, invc_off, counters_off, total;
+    size_t insts_off, tiles_off, log_off, sel_off, invc_off, counters_off, guide_off, total;
     std::vector<Layout> lay;
     int ntiles;
 };
@@ -180,6 +183,11 @@ Plan plan_of(const pd_params* p, int n)
     at = align_up(at + sizeof(double) * (kMaxSites + 1));
     pl.counters_off = at;
     at = align_up(at + sizeof(uint32_t) * kMaxGroups);
+    // the library's own copy of the guide table (guided instances only)
+    bool guided = false;
+    for (int i = 0; i < n; ++i) guided = guided || p[i].weight_mode == PD_W_GUIDED;
+    pl.guide_off = guided ? at : 0;
+    if (guided) at = align_up(at + sizeof(uint32_t) * kGuideEntries);
     for (int i = 0; i < n; ++i) {
         pl.lay.push_back(layout_of(p[i], at));
         at = pl.lay.back().end;
@@ -206,6 +214,7 @@ struct pd_ctx {
     bool any_guided = false;
     bool guide_set = false;
     bool any_origin = false;
+    bool any_burn = false;           // an instance carries burn-in snapshots of K
     int cur = 0;                     // buffer holding the population
     bool perm = false;               // population = state[cur][anc[j]]
     bool stepped = false;            // a dynamical stage awaits its cloning stage
@@ -213,6 +222,12 @@ struct pd_ctx {
     int64_t beta = 0;                // completed cycles (host mirror)
     int graph_cycles = 16;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
+    // stage timing (pd_time_stages): events around the launches of pd_step and
+    // pd_resample, never inside a captured graph
+    bool timing = false;
+    bool capturing = false;
+    std::vector<hipEvent_t> ev_step;     // triples: before the step kernels, before k_prefix, after
+    std::vector<hipEvent_t> ev_res;      // pairs: before and after the cloning stage
     std::string err;
 };
 
@@ -233,22 +248,48 @@ pd_status fail(pd_ctx* ctx, pd_status st, const std::string& msg)
     return st;
 }
 
+// Records a timing event on the context stream (pd_time_stages).
+pd_status record_event(pd_ctx* ctx, std::vector<hipEvent_t>& into)
+{
+    hipEvent_t e = nullptr;
+    PD_HIP(hipEventCreate(&e));
+    into.push_back(e);
+    PD_HIP(hipEventRecord(e, ctx->stream));
+    return PD_OK;
+}
+
+#define PD_TIME(into)                                                                   \
+    do {                                                                                \
+        if (ctx->timing && !ctx->capturing) {                                           \
+            pd_status s_ = record_event(ctx, into);                                     \
+            if (s_ != PD_OK) return s_;                                                 \
+        }                                                                               \
+    } while (0)
+
 // Cloning stage of every instance.
 pd_status enqueue_resample(pd_ctx* ctx)
 {
+    PD_TIME(ctx->ev_res);
     PD_HIP(launch_resample(ctx->d_insts, ctx->d_tiles, (int)ctx->tiles.size(),
                            std::max(1, ctx->tuning.scan_tiles), ctx->stream));
     if (ctx->any_iid)
         PD_HIP(launch_select_iid(ctx->d_insts, ctx->d_tiles, (int)ctx->tiles.size(), ctx->stream));
+    PD_TIME(ctx->ev_res);
     return PD_OK;
 }
 
 // Dynamical stage of every instance and the interval statistics.
 pd_status enqueue_step(pd_ctx* ctx, int use_anc, int src)
 {
+    if (ctx->any_burn)
+        PD_HIP(launch_carry_burn(ctx->d_insts, ctx->d_tiles, (int)ctx->tiles.size(), src, use_anc,
+                                 ctx->stream));
+    PD_TIME(ctx->ev_step);
     for (const auto& g : ctx->steps)
         PD_HIP(launch_step(g, ctx->d_insts, ctx->d_tiles, src, use_anc, ctx->stream));
+    PD_TIME(ctx->ev_step);
     PD_HIP(launch_prefix(ctx->d_insts, ctx->n, ctx->stream));
+    PD_TIME(ctx->ev_step);
     return PD_OK;
 }
 
@@ -389,6 +430,9 @@ pd_status pd_create(const pd_params* params, int32_t n, void* d_workspace, size_
         d.origin[0] = o.origin[0] ? (int32_t*)(b + o.origin[0]) : nullptr;
         d.origin[1] = o.origin[1] ? (int32_t*)(b + o.origin[1]) : nullptr;
         if (p.track_origin) ctx->any_origin = true;
+        d.ksnap[0] = o.ksnap[0] ? (uint64_t*)(b + o.ksnap[0]) : nullptr;
+        d.ksnap[1] = o.ksnap[1] ? (uint64_t*)(b + o.ksnap[1]) : nullptr;
+        if (p.burn_in > 0) ctx->any_burn = true;
         d.ykey = o.ykey ? (double*)(b + o.ykey) : nullptr;
         d.tile_max = (double*)(b + o.tmax);
         d.tile_sum = (double*)(b + o.tsum);
@@ -498,6 +542,11 @@ pd_status pd_destroy(pd_ctx* ctx)
     if (!ctx) return PD_EINVAL;
     for (auto& g : ctx->graph)
         if (g) (void)hipGraphExecDestroy(g);
+    if (!ctx->ev_step.empty() || !ctx->ev_res.empty()) {
+        (void)hipStreamSynchronize(ctx->stream);
+        for (hipEvent_t e : ctx->ev_step) (void)hipEventDestroy(e);
+        for (hipEvent_t e : ctx->ev_res) (void)hipEventDestroy(e);
+    }
     delete ctx;
     return PD_OK;
 }
@@ -534,12 +583,44 @@ pd_status pd_resample(pd_ctx* ctx)
     return PD_OK;
 }
 
+// Captures (without running) the graph of graph_cycles cycles that starts
+// from state buffer `which` with the population read through the ancestor
+// map; pd_run replays it.
+pd_status capture_graph(pd_ctx* ctx, int which)
+{
+    hipGraphExec_t& ex = ctx->graph[which];
+    if (ex) return PD_OK;
+    const int G = ctx->graph_cycles;
+    hipGraph_t g = nullptr;
+    PD_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+    pd_status st = PD_OK;
+    ctx->capturing = true;
+    for (int c = 0; c < G && st == PD_OK; ++c) st = enqueue_cycle(ctx, 1, which ^ (c & 1));
+    ctx->capturing = false;
+    hipError_t e = hipStreamEndCapture(ctx->stream, &g);
+    if (st != PD_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+    PD_HIP(e);
+    hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    PD_HIP(ei);
+    return PD_OK;
+}
+
 pd_status pd_run(pd_ctx* ctx, int64_t cycles)
 {
     if (!ctx || cycles < 0) return PD_EINVAL;
     if (ctx->stepped) return fail(ctx, PD_ESTATE, "a pd_step awaits its pd_resample");
     if (ctx->any_guided && !ctx->guide_set)
         return fail(ctx, PD_ESTATE, "guided instances need pd_set_guide first");
+    if (cycles == 0) {
+        // nothing runs: the graphs that later calls replay are captured now
+        if (ctx->stream != nullptr && ctx->graph_cycles > 0)
+            for (int which = 0; which < 2; ++which) {
+                pd_status st = capture_graph(ctx, which);
+                if (st != PD_OK) return st;
+            }
+        return PD_OK;
+    }
     int64_t left = cycles;
     if (left > 0 && !ctx->perm) {
         pd_status st = enqueue_cycle(ctx, 0, ctx->cur);
@@ -550,19 +631,9 @@ pd_status pd_run(pd_ctx* ctx, int64_t cycles)
     }
     const int G = ctx->graph_cycles;
     if (ctx->stream != nullptr && G > 0 && left >= G) {
-        hipGraphExec_t& ex = ctx->graph[ctx->cur];
-        if (!ex) {
-            hipGraph_t g = nullptr;
-            PD_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
-            pd_status st = PD_OK;
-            for (int c = 0; c < G && st == PD_OK; ++c) st = enqueue_cycle(ctx, 1, ctx->cur ^ (c & 1));
-            hipError_t e = hipStreamEndCapture(ctx->stream, &g);
-            if (st != PD_OK) { if (g) (void)hipGraphDestroy(g); return st; }
-            PD_HIP(e);
-            hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            PD_HIP(ei);
-        }
+        pd_status st = capture_graph(ctx, ctx->cur);
+        if (st != PD_OK) return st;
+        hipGraphExec_t ex = ctx->graph[ctx->cur];
         while (left >= G) {
             PD_HIP(hipGraphLaunch(ex, ctx->stream));
             left -= G;   // G is even: the population returns to buffer cur
@@ -601,6 +672,12 @@ pd_status pd_estimates_get(pd_ctx* ctx, int32_t inst, pd_estimates* out)
     out->psi_burn = c.beta > p.burn_in
                         ? (c.psib_sum + c.psib_comp) / ((double)(c.beta - p.burn_in) * p.dt) : 0.0;
     out->k_hat = c.beta > 0 ? (double)c.ksum / ((double)p.Nc * (double)p.L * t) : 0.0;
+    // hops of the intervals beyond burn_in along the ancestral lines: K minus its
+    // snapshot at the end of interval burn_in (every clone's K when burn_in = 0)
+    out->k_hat_burn = c.beta > p.burn_in
+                          ? (double)(c.ksum - c.ksnap_sum) /
+                                ((double)p.Nc * (double)p.L * (double)(c.beta - p.burn_in) * p.dt)
+                          : 0.0;
     return PD_OK;
 }
 
@@ -674,6 +751,10 @@ pd_status pd_set_population(pd_ctx* ctx, int32_t inst, const void* host, size_t 
     PD_HIP(hipMemcpyAsync(d.state[ctx->cur], host, 8 * Nc * W, hipMemcpyHostToDevice, ctx->stream));
     PD_HIP(hipMemcpyAsync(d.K[ctx->cur], (const char*)host + 8 * Nc * W, 8 * Nc,
                           hipMemcpyHostToDevice, ctx->stream));
+    // hops beyond burn_in count from here for the new clones
+    if (d.ksnap[0])
+        PD_HIP(hipMemcpyAsync(d.ksnap[ctx->cur], (const char*)host + 8 * Nc * W, 8 * Nc,
+                              hipMemcpyHostToDevice, ctx->stream));
     PD_HIP(hipStreamSynchronize(ctx->stream));
     ctx->stepped = false;
     ctx->anc_valid = false;
@@ -734,6 +815,7 @@ pd_status pd_save_bytes(pd_ctx* ctx, size_t* bytes)
     for (const auto& p : ctx->params) {
         b += sizeof(InstCtl) + 8 * (size_t)p.Nc * (size_t)(words_of(p.L) + 1);
         if (p.track_origin) b += (4 * (size_t)p.Nc + 7) / 8 * 8;
+        if (p.burn_in > 0) b += 8 * (size_t)p.Nc;
     }
     *bytes = b;
     return PD_OK;
@@ -766,6 +848,11 @@ pd_status pd_save(pd_ctx* ctx, void* host, size_t bytes)
             PD_HIP(hipMemcpyAsync(at, d.origin[ctx->cur], 4 * Nc, hipMemcpyDeviceToHost,
                                   ctx->stream));
             at += (4 * Nc + 7) / 8 * 8;
+        }
+        if (d.ksnap[0]) {
+            PD_HIP(hipMemcpyAsync(at, d.ksnap[ctx->cur], 8 * Nc, hipMemcpyDeviceToHost,
+                                  ctx->stream));
+            at += 8 * Nc;
         }
     }
     PD_HIP(hipStreamSynchronize(ctx->stream));
@@ -807,6 +894,7 @@ pd_status pd_load(pd_ctx* ctx, const void* host, size_t bytes)
             }
             at += (4 * Nc + 7) / 8 * 8;
         }
+        if (ctx->dev[i].ksnap[0]) at += 8 * Nc;
     }
     at = (const char*)host + 24;
     for (int i = 0; i < ctx->n; ++i) {
@@ -822,6 +910,11 @@ pd_status pd_load(pd_ctx* ctx, const void* host, size_t bytes)
             PD_HIP(hipMemcpyAsync(d.origin[ctx->cur], at, 4 * Nc, hipMemcpyHostToDevice,
                                   ctx->stream));
             at += (4 * Nc + 7) / 8 * 8;
+        }
+        if (d.ksnap[0]) {
+            PD_HIP(hipMemcpyAsync(d.ksnap[ctx->cur], at, 8 * Nc, hipMemcpyHostToDevice,
+                                  ctx->stream));
+            at += 8 * Nc;
         }
     }
     PD_HIP(hipStreamSynchronize(ctx->stream));
@@ -862,9 +955,13 @@ pd_status pd_set_guide(pd_ctx* ctx, const uint32_t* d_table, size_t n)
         if (!(rate * p.dt <= kMaxEventsPerInterval))
             return fail(ctx, PD_EINVAL, "guide makes more than 2^24 expected hops per interval");
     }
+    // the library's own copy: the caller may change or free its buffer afterwards
+    uint32_t* own = (uint32_t*)(ctx->ws + ctx->plan.guide_off);
+    PD_HIP(hipMemcpyAsync(own, d_table, sizeof(uint32_t) * kGuideEntries,
+                          hipMemcpyDeviceToDevice, ctx->stream));
     for (int i = 0; i < ctx->n; ++i) {
         if (ctx->params[i].weight_mode != PD_W_GUIDED) continue;
-        ctx->dev[i].guide = d_table;
+        ctx->dev[i].guide = own;
         ctx->dev[i].guide_max = hi;
     }
     PD_HIP(hipMemcpyAsync(ctx->d_insts, ctx->dev.data(), sizeof(InstDev) * (size_t)ctx->n,
@@ -983,6 +1080,10 @@ pd_status pd_autotune(pd_ctx* ctx, int32_t trial_cycles, pd_tuning* best)
     st = pd_save(ctx, snap.data(), nb);
     if (st != PD_OK) return st;
     const pd_tuning start = ctx->tuning;
+    // the trials are not part of a stage timing
+    const bool timing = ctx->timing;
+    ctx->timing = false;
+    struct Restore { pd_ctx* c; bool t; ~Restore() { c->timing = t; } } restore{ctx, timing};
     std::vector<pd_tuning> cands;
     pd_tuning t = start;
     t.step_variant = 0;
@@ -1052,6 +1153,46 @@ pd_status pd_autotune(pd_ctx* ctx, int32_t trial_cycles, pd_tuning* best)
     st = apply_tuning(ctx, chosen);
     if (st != PD_OK) return st;
     if (best) *best = chosen;
+    return PD_OK;
+}
+
+pd_status pd_time_stages(pd_ctx* ctx, int32_t enable)
+{
+    if (!ctx) return PD_EINVAL;
+    if (enable != 0 && enable != 1) return fail(ctx, PD_EINVAL, "enable must be 0 or 1");
+    if (ctx->stepped) return fail(ctx, PD_ESTATE, "stage timing between pd_step and pd_resample");
+    PD_HIP(hipStreamSynchronize(ctx->stream));
+    for (hipEvent_t e : ctx->ev_step) PD_HIP(hipEventDestroy(e));
+    for (hipEvent_t e : ctx->ev_res) PD_HIP(hipEventDestroy(e));
+    ctx->ev_step.clear();
+    ctx->ev_res.clear();
+    ctx->timing = enable == 1;
+    return PD_OK;
+}
+
+pd_status pd_get_stage_times(pd_ctx* ctx, pd_stage_times* out)
+{
+    if (!ctx || !out) return PD_EINVAL;
+    if (ctx->stepped) return fail(ctx, PD_ESTATE, "stage timing between pd_step and pd_resample");
+    PD_HIP(hipStreamSynchronize(ctx->stream));
+    std::memset(out, 0, sizeof *out);
+    const size_t ns = ctx->ev_step.size() / 3, nr = ctx->ev_res.size() / 2;
+    for (size_t k = 0; k < ns; ++k) {
+        float a = 0.0f, b = 0.0f;
+        PD_HIP(hipEventElapsedTime(&a, ctx->ev_step[3 * k], ctx->ev_step[3 * k + 1]));
+        PD_HIP(hipEventElapsedTime(&b, ctx->ev_step[3 * k + 1], ctx->ev_step[3 * k + 2]));
+        out->step_ms += a;
+        out->prefix_ms += b;
+    }
+    for (size_t k = 0; k < nr; ++k) {
+        float a = 0.0f;
+        PD_HIP(hipEventElapsedTime(&a, ctx->ev_res[2 * k], ctx->ev_res[2 * k + 1]));
+        out->resample_ms += a;
+    }
+    if (ns) { out->step_ms /= (double)ns; out->prefix_ms /= (double)ns; }
+    if (nr) out->resample_ms /= (double)nr;
+    out->steps = (int64_t)ns;
+    out->resamples = (int64_t)nr;
     return PD_OK;
 }
 

@@ -32,7 +32,8 @@ struct InstCtl {
     uint64_t hops;         // hops performed so far
     uint64_t ksum;         // scratch: sum of K over the population (estimates)
     double d_eq;           // offset d of the [eq] points of interval beta (set by k_prefix)
-    uint64_t pad_[3];
+    uint64_t ksnap_sum;    // scratch: sum of the burn-in snapshots of K (estimates)
+    uint64_t pad_[2];
 };
 
 // Per-instance descriptor (written by the host at creation, read-only after).
@@ -49,6 +50,8 @@ struct InstDev {
     double* ell;           // [Nc] ln Ups of the last interval
     int32_t* anc;          // [Nc] ancestor map of the last cloning stage
     int32_t* origin[2];    // [Nc] carried origin slots, two buffers (null: not tracked)
+    uint64_t* ksnap[2];    // [Nc] carried K of the ancestor at the end of interval burn_in,
+                           // two buffers (null: burn_in = 0)
     double* ykey;          // [Nc] interval ends in spacing units ([iid] only)
     double* tile_max;      // [ntiles]
     double* tile_sum;      // [ntiles] sum of exp(ell - tile_max)

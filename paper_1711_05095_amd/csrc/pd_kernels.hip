@@ -87,6 +87,7 @@ __global__ void k_reset_ctl(const InstDev* __restrict__ insts, int n)
     c->psib_sum = c->psib_comp = 0.0;
     c->hops = 0;
     c->ksum = 0;
+    c->ksnap_sum = 0;
 }
 
 // Neumaier compensated addition.
@@ -838,7 +839,8 @@ __global__ __launch_bounds__(kTile) void k_select_iid(const InstDev* __restrict_
     gptr(I.anc)[j] = (int32_t)(a < Nc ? a : Nc - 1);
 }
 
-// Sum of K over the current population (through the ancestor map if any).
+// Sums of K and of its burn-in snapshot over the current population (through
+// the ancestor map if any).
 __global__ __launch_bounds__(kTile) void k_ksum(const InstDev* __restrict__ insts,
                                                 const TileDesc* __restrict__ tiles, int cur,
                                                 int use_anc)
@@ -847,23 +849,55 @@ __global__ __launch_bounds__(kTile) void k_ksum(const InstDev* __restrict__ inst
     const TileDesc td = tiles[blockIdx.x];
     const InstDev& I = insts[td.inst];
     const int tid = threadIdx.x;
-    uint64_t v = 0;
+    uint64_t v = 0, q = 0;
     if (tid < td.count) {
         const int64_t j = td.first + tid;
         const int64_t from = use_anc ? (int64_t)I.anc[j] : j;
         v = I.K[cur][from];
+        if (I.ksnap[0]) q = I.ksnap[cur][from];
     }
     const uint64_t s = block_reduce(v, OpSum(), s_u);
     if (tid == 0) atomicAdd((unsigned long long*)&I.ctl->ksum, (unsigned long long)s);
+    if (I.ksnap[0]) {
+        __syncthreads();   // s_u is reused
+        const uint64_t sq = block_reduce(q, OpSum(), s_u);
+        if (tid == 0) atomicAdd((unsigned long long*)&I.ctl->ksnap_sum, (unsigned long long)sq);
+    }
 }
 
 __global__ void k_zero_ksum(const InstDev* __restrict__ insts, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) insts[i].ctl->ksum = 0;
+    if (i < n) {
+        insts[i].ctl->ksum = 0;
+        insts[i].ctl->ksnap_sum = 0;
+    }
 }
 
-// Materialise the population: dst[j] = src[anc[j]] for state and K.
+// The burn-in snapshot of the carried K, for the interval about to be stepped
+// (beta = the completed intervals + 1; launched before the dynamical stage):
+// in interval burn_in + 1 every new clone j records the K it inherits (its
+// ancestor's K at the end of interval burn_in); in later intervals it
+// inherits its ancestor's record, as K itself is inherited.  K minus the
+// record is then the hops of the intervals beyond burn_in along the clone's
+// ancestral line (the transient-excluded activity, Sec. 5.1).
+__global__ __launch_bounds__(kTile) void k_carry_burn(const InstDev* __restrict__ insts,
+                                                      const TileDesc* __restrict__ tiles,
+                                                      int src, int use_anc)
+{
+    const TileDesc td = tiles[blockIdx.x];
+    const InstDev& I = insts[td.inst];
+    if (!I.ksnap[0] || (int)threadIdx.x >= td.count) return;
+    const int64_t beta = I.ctl->beta + 1;
+    if (beta <= I.burn_in) return;
+    const int64_t j = td.first + threadIdx.x;
+    const int64_t from = use_anc ? (int64_t)gptr(I.anc)[j] : j;
+    gptr(I.ksnap[src ^ 1])[j] = beta == I.burn_in + 1 ? gptr(I.K[src])[from]
+                                                       : gptr(I.ksnap[src])[from];
+}
+
+// Materialise the population: dst[j] = src[anc[j]] for the state, K and the
+// carried origins and burn-in snapshots.
 template <int W>
 __global__ __launch_bounds__(kTile) void k_gather(const InstDev* __restrict__ insts,
                                                   const TileDesc* __restrict__ tiles,
@@ -879,6 +913,7 @@ __global__ __launch_bounds__(kTile) void k_gather(const InstDev* __restrict__ in
     for (int w = 0; w < W; ++w) I.state[src ^ 1][w * Nc + j] = I.state[src][w * Nc + from];
     I.K[src ^ 1][j] = I.K[src][from];
     if (I.origin[0]) I.origin[src ^ 1][j] = I.origin[src][from];
+    if (I.ksnap[0]) I.ksnap[src ^ 1][j] = I.ksnap[src][from];
 }
 
 // origin[cur][j] = j for every clone of instance `inst`.
@@ -1033,6 +1068,13 @@ hipError_t launch_ksum(const InstDev* insts, const TileDesc* tiles, int ntiles, 
                        int use_anc, hipStream_t st)
 {
     hipLaunchKernelGGL(k_ksum, dim3(ntiles), dim3(kTile), 0, st, insts, tiles, cur, use_anc);
+    return hipGetLastError();
+}
+
+hipError_t launch_carry_burn(const InstDev* insts, const TileDesc* tiles, int ntiles, int src,
+                             int use_anc, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_carry_burn, dim3(ntiles), dim3(kTile), 0, st, insts, tiles, src, use_anc);
     return hipGetLastError();
 }
 

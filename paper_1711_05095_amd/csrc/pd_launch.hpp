@@ -49,6 +49,8 @@ hipError_t launch_iota_origin(const InstDev* insts, int inst, int64_t Nc, int cu
 hipError_t launch_zero_ksum(const InstDev* insts, int n_inst, hipStream_t st);
 hipError_t launch_ksum(const InstDev* insts, const TileDesc* tiles, int ntiles, int cur,
                        int use_anc, hipStream_t st);
+hipError_t launch_carry_burn(const InstDev* insts, const TileDesc* tiles, int ntiles, int src,
+                             int use_anc, hipStream_t st);
 hipError_t launch_gather(int W, const InstDev* insts, const TileDesc* tiles, int tile_base,
                          int ntiles, int src, hipStream_t st);
 }  // namespace pd

@@ -25,7 +25,8 @@ EXPORTS = ["pd_workspace_bytes", "pd_create", "pd_destroy", "pd_step", "pd_resam
            "pd_set_population", "pd_get_step_outputs", "pd_get_ancestors", "pd_get_log",
            "pd_save_bytes", "pd_save", "pd_load", "pd_set_guide", "pd_reset_origin",
            "pd_get_origin", "pd_density_mode", "pd_mean", "pd_histogram", "pd_get_tuning",
-           "pd_set_tuning", "pd_autotune", "pd_last_error", "pd_status_str"]
+           "pd_set_tuning", "pd_autotune", "pd_time_stages", "pd_get_stage_times", "pd_last_error",
+           "pd_status_str"]
 
 
 class PdParams(ctypes.Structure):
@@ -40,7 +41,13 @@ class PdParams(ctypes.Structure):
 class PdEstimates(ctypes.Structure):
     _fields_ = [("psi", ctypes.c_double), ("psi_burn", ctypes.c_double),
                 ("k_hat", ctypes.c_double), ("t", ctypes.c_double), ("cycles", ctypes.c_int64),
-                ("hops", ctypes.c_uint64)]
+                ("hops", ctypes.c_uint64), ("k_hat_burn", ctypes.c_double)]
+
+
+class PdStageTimes(ctypes.Structure):
+    _fields_ = [("step_ms", ctypes.c_double), ("prefix_ms", ctypes.c_double),
+                ("resample_ms", ctypes.c_double), ("steps", ctypes.c_int64),
+                ("resamples", ctypes.c_int64)]
 
 
 class PdTuning(ctypes.Structure):
@@ -94,6 +101,8 @@ def lib():
             "pd_get_tuning": [vp, P(PdTuning)],
             "pd_set_tuning": [vp, P(PdTuning)],
             "pd_autotune": [vp, c.c_int32, P(PdTuning)],
+            "pd_time_stages": [vp, c.c_int32],
+            "pd_get_stage_times": [vp, P(PdStageTimes)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -172,8 +181,8 @@ def pd_scgf(ctx):
 def pd_estimates_get(ctx, inst=0):
     e = PdEstimates()
     _check(lib().pd_estimates_get(ctx, inst, ctypes.byref(e)), ctx)
-    return dict(psi=e.psi, psi_burn=e.psi_burn, k_hat=e.k_hat, t=e.t, cycles=e.cycles,
-                hops=e.hops)
+    return dict(psi=e.psi, psi_burn=e.psi_burn, k_hat=e.k_hat, k_hat_burn=e.k_hat_burn, t=e.t,
+                cycles=e.cycles, hops=e.hops)
 
 
 def words_of(L):
@@ -277,6 +286,17 @@ def pd_autotune(ctx, trial_cycles):
     return _tuning_dict(t)
 
 
+def pd_time_stages(ctx, enable):
+    _check(lib().pd_time_stages(ctx, 1 if enable else 0), ctx)
+
+
+def pd_get_stage_times(ctx):
+    t = PdStageTimes()
+    _check(lib().pd_get_stage_times(ctx, ctypes.byref(t)), ctx)
+    return dict(step_ms=t.step_ms, prefix_ms=t.prefix_ms, resample_ms=t.resample_ms,
+                steps=t.steps, resamples=t.resamples)
+
+
 def pd_set_guide(ctx, table_ptr, n):
     _check(lib().pd_set_guide(ctx, ctypes.c_void_p(table_ptr), n), ctx)
 
@@ -352,11 +372,13 @@ class Sampler:
         pd_load(self.ctx, blob)
 
     def set_guide(self, table):
-        """table: a torch uint32-compatible int32 CUDA tensor of 8192 entries
-        (kept alive by the sampler; a refused table leaves the previous one in
-        use, and alive)."""
+        """table: a torch uint32-compatible int32 CUDA tensor of 8192 entries;
+        the library keeps a copy (a refused table leaves the previous one in
+        use)."""
+        # the library reads the table on its own stream
+        import torch
+        torch.cuda.current_stream().synchronize()
         pd_set_guide(self.ctx, table.data_ptr(), table.numel())
-        self._guide = table
 
     def reset_origin(self, inst=0):
         pd_reset_origin(self.ctx, inst)
@@ -407,3 +429,9 @@ class Sampler:
 
     def autotune(self, trial_cycles=3):
         return pd_autotune(self.ctx, trial_cycles)
+
+    def time_stages(self, enable=True):
+        pd_time_stages(self.ctx, enable)
+
+    def stage_times(self):
+        return pd_get_stage_times(self.ctx)

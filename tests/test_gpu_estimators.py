@@ -5,9 +5,11 @@
     (eq. psihat, one term per interval) and the population mean of K^beta,
     for every interval of whole runs at s != 0, with both weight forms, both
     selections and a guide;
-  * the burn-in estimators psi_burn (intervals beyond burn_in, in the spirit
-    of the transient discussion of Sec. 5.1), also with burn_in on either
-    side of the run's ends;
+  * the burn-in estimators psi_burn and k_hat_burn (intervals beyond
+    burn_in, the transient of Sec. 5.1; k_hat_burn carries the hops beyond
+    burn_in along the ancestral lines), also with burn_in on either side of
+    the run's ends, through graph replays, a checkpoint and a materialised
+    population;
   * the 64 uneven instances of the batched workload (L in {20..200},
     N = L/2, lambda in [-10, 20], Nc log-uniform in [1e3, 1e5]) in one context
     equal, bit for bit, the same instances each in a context of its own.
@@ -80,6 +82,104 @@ def test_log_and_burn_in_estimators(L, N, s, Nc, dt, M, burn, mode, sel):
         assert e["psi_burn"] == pytest.approx(lb[burn:].sum() / ((M - burn) * dt), rel=1e-12,
                                               abs=1e-15)
     assert e["k_hat"] == pytest.approx(r["k_hat"], rel=1e-12)
+    if burn >= M:
+        assert e["k_hat_burn"] == 0.0 and r["k_hat_burn"] == 0.0
+    else:
+        assert e["k_hat_burn"] == pytest.approx(r["k_hat_burn"], rel=1e-12)
+    if burn == 0:
+        assert e["k_hat_burn"] == e["k_hat"]
+
+
+def test_burn_in_survives_checkpoint_and_materialisation():
+    """k_hat_burn and psi_burn of a run restored from a checkpoint taken
+    before, at and after the burn-in, and of a run whose population was
+    materialised (pd_get_population) mid-way, equal the uninterrupted run's."""
+    L, N, s, Nc, dt, M, burn = 40, 20, 0.02, 1500, 0.5, 40, 17
+    p = pd.make_params(L, N, s, Nc, M * dt, dt, seed=31, burn_in=burn)
+    A = pd.Sampler(p)
+    A.run(M)
+    ea = A.estimates()
+    r = oracle.Oracle(L, N, s, Nc, dt, M=M, seed=31, burn_in=burn).run()
+    assert ea["hops"] == r["hops"]
+    assert ea["k_hat_burn"] == pytest.approx(r["k_hat_burn"], rel=1e-12)
+    for cut in (burn - 3, burn, burn + 1, burn + 9):
+        B = pd.Sampler(p)
+        B.run(cut)
+        blob = B.save()
+        C = pd.Sampler(p)
+        C.load(blob)
+        C.run(5)
+        C.get_population()          # materialise mid-way
+        for _ in range(M - cut - 5):
+            C.step()
+            C.resample()
+        assert C.estimates() == ea, cut
+        B.close()
+        C.close()
+
+
+def test_guide_table_is_copied():
+    """pd_set_guide keeps its own copy: changing the caller's table afterwards
+    changes nothing until pd_set_guide is called again."""
+    from guide_tables import random_table
+    t1, t2 = random_table(41), random_table(42)
+    L, N, s, Nc, dt, M = 30, 14, 0.1, 600, 0.3, 6
+    p = pd.make_params(L, N, s, Nc, M * dt, dt, seed=5, weight_mode=GUIDED)
+    dev = torch.from_numpy(t1.view(np.int32).copy()).cuda()
+    A = pd.Sampler(p)
+    A.set_guide(dev)
+    dev.copy_(torch.from_numpy(t2.view(np.int32).copy()))
+    torch.cuda.synchronize()
+    A.run(M)
+    r1 = oracle.Oracle(L, N, s, Nc, dt, M=M, seed=5, mode=GUIDED, guide=t1).run()
+    assert A.estimates()["hops"] == r1["hops"]
+    B = pd.Sampler(p)
+    B.set_guide(dev)                # now the second table
+    del dev
+    torch.cuda.empty_cache()
+    B.run(M)
+    r2 = oracle.Oracle(L, N, s, Nc, dt, M=M, seed=5, mode=GUIDED, guide=t2).run()
+    assert B.estimates()["hops"] == r2["hops"]
+    assert B.estimates()["psi"] == pytest.approx(r2["psi"], rel=1e-9)
+
+
+def test_stage_times():
+    """Stage timing records the single launches of pd_step and pd_resample
+    and leaves the results unchanged."""
+    p = pd.make_params(100, 50, 0.002, 20_000, 10 * 0.5, 0.5, seed=12)
+    A = pd.Sampler(p)
+    A.time_stages(True)
+    for _ in range(10):
+        A.step()
+        A.resample()
+    t = A.stage_times()
+    assert t["steps"] == 10 and t["resamples"] == 10
+    assert 0.0 < t["step_ms"] < 1e3 and 0.0 < t["prefix_ms"] < 1e3 and 0.0 < t["resample_ms"] < 1e3
+    A.time_stages(False)
+    B = pd.Sampler(p)
+    B.run(10)
+    assert A.estimates() == B.estimates()
+    with pytest.raises(pd.PdError):
+        A.step()
+        A.time_stages(True)
+
+
+def test_graphs_captured_ahead_change_nothing():
+    """pd_run(ctx, 0) runs nothing and captures the graphs that later calls
+    replay: the run that follows equals one that captured on first use."""
+    p = pd.make_params(100, 50, 0.002, 5000, 40 * 0.5, 0.5, seed=14)
+    A = pd.Sampler(p)
+    A.run(0)
+    assert A.estimates()["cycles"] == 0
+    A.run(3)
+    A.run(0)
+    A.run(37)
+    B = pd.Sampler(p)
+    B.run(40)
+    assert A.estimates() == B.estimates()
+    wa, Ka = A.get_population()
+    wb, Kb = B.get_population()
+    assert np.array_equal(wa, wb) and np.array_equal(Ka, Kb)
 
 
 def test_log_shorter_than_run():

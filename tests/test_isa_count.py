@@ -1,5 +1,7 @@
-"""The per-event VALU count used by bench.py's roofline equals the count in the
-gfx950 assembly of the step kernel as it is built now."""
+"""The per-event unit of bench.py's ALU roofline is frozen at the VALU count of
+the step kernel's event loop at a named commit, so that the roofline fraction
+follows throughput.  The loop as it is built now must not have grown past
+that unit (a leaner loop is fine: the same events then cost less)."""
 import os
 import shutil
 
@@ -11,6 +13,6 @@ from paper_1711_05095_amd import isa_count
 
 @pytest.mark.skipif(not (shutil.which("hipcc") or os.path.exists("/opt/rocm/bin/hipcc")),
                     reason="hipcc not available")
-def test_bench_valu_count_matches_assembly():
-    assert isa_count.count() == bench.VALU_PER_EVENT_W2
-    assert isa_count.count("_ZN2pd6k_stepILi7E") == bench.VALU_PER_EVENT_W7
+def test_event_loop_within_the_frozen_unit():
+    assert isa_count.count() <= bench.VALU_PER_EVENT_W2
+    assert isa_count.count("_ZN2pd6k_stepILi7E") <= bench.VALU_PER_EVENT_W7
