@@ -227,16 +227,20 @@ static int window13(const uint8_t* n, int L, int c)
  * and the compensating factor of the interval is
  *     ln Ups = -sum_jumps g - int (r(C) - e^{-s} S(C) 2^-16) dt,
  * which makes the weighted guided trajectories unbiased for ANY table.
- * The hop is chosen by rejection: a uniform allowed bond (64-bit word w,
- * index floor(w r / 2^64)) is accepted with probability eg[u_b] / eg_max
- * (64-bit word a, accepted iff floor(a eg_max / 2^64) < eg[u_b]), repeated
- * until accepted.  Random numbers of a clone in interval beta: event k (its
- * waiting times counted from 0) takes block (k, slot, beta, GUIDE): the
- * waiting time from words 0, 1 as in the plain dynamics, the first proposal's
- * bond word from words 2, 3; proposal p (counted over the interval from 0)
- * takes block (p, slot, beta, GUIDE_PROP): its acceptance word from words
- * 0, 1 and, if it is rejected, the next proposal's bond word from words 2, 3. */
-enum { ORC_TAG_GUIDE = 5, ORC_TAG_GUIDE_PROP = 6 };
+ * The jumps are drawn by thinning: proposals come at rate e^{-s} eg_max 2^-16
+ * per allowed bond (eg_max the largest entry, so a bound of every controlled
+ * rate), each across a uniform allowed bond b, and a proposal is taken with
+ * probability eg[u_b] / eg_max, otherwise the configuration stays.  The taken
+ * proposals are exactly the jumps of the guided dynamics.  Random numbers of
+ * a clone in interval beta: proposal k (counted over the interval from 0)
+ * takes Philox block (k, slot, beta, GUIDE): the waiting time from words 0, 1
+ * as in the plain dynamics, and the 64-bit bond word bw from words 2, 3; the
+ * bond is the q-th allowed one with q = floor(bw r / 2^64), and the rest of
+ * that product, a = (bw r) mod 2^64, decides: taken iff
+ * floor(a eg_max / 2^64) < eg[u_b].  Given q, a runs over a lattice of
+ * spacing r in [0, 2^64), so the acceptance probability is eg/eg_max to
+ * within 2 r / 2^64. */
+enum { ORC_TAG_GUIDE = 5 };
 
 static uint64_t word_of(uint32_t hi, uint32_t lo) { return ((uint64_t)hi << 32) | lo; }
 
@@ -261,8 +265,9 @@ static uint32_t step_clone_guided(const orc_params* p, double es, uint32_t egmax
 {
     const int L = p->L;
     const double dt = p->dt;
+    const double unit = es * ((double)egmax * 0x1p-16);   /* proposal rate per allowed bond */
     double tau = 0.0, A = 0.0, AS = 0.0, G = 0.0;
-    uint32_t kb = 0, k = 0, prop = 0;
+    uint32_t kb = 0, k = 0;
     int r = escape_count(n, L);
     uint64_t S = guided_total(p, n);
     while (r > 0) {
@@ -271,8 +276,7 @@ static uint32_t step_clone_guided(const orc_params* p, double es, uint32_t egmax
         ++k;
         double u = (double)((word_of(x[0], x[1]) >> 11) + 1) * 0x1p-53;
         double E = -log(u);
-        double R = es * ((double)S * 0x1p-16);
-        double w = E / R;
+        double w = E / (unit * (double)r);
         if (tau + w >= dt) {
             A = fma((double)r, dt - tau, A);
             AS = fma((double)S, dt - tau, AS);
@@ -281,18 +285,10 @@ static uint32_t step_clone_guided(const orc_params* p, double es, uint32_t egmax
         A = fma((double)r, w, A);
         AS = fma((double)S, w, AS);
         tau = tau + w;
-        uint64_t bond_word = word_of(x[2], x[3]);
-        int bond = -1;
-        uint32_t e = 0;
-        for (;;) {
-            bond = qth_active_bond(n, L, (int)mulhi64(bond_word, (uint64_t)r));
-            e = p->guide[window13(n, L, bond)];
-            uint32_t y[4];
-            draw(p, ORC_TAG_GUIDE_PROP, prop, (uint32_t)j, beta, y);
-            ++prop;
-            if (mulhi64(word_of(y[0], y[1]), (uint64_t)egmax) < (uint64_t)e) break;
-            bond_word = word_of(y[2], y[3]);
-        }
+        unsigned __int128 pr = (unsigned __int128)word_of(x[2], x[3]) * (unsigned __int128)r;
+        int bond = qth_active_bond(n, L, (int)(uint64_t)(pr >> 64));
+        uint32_t e = p->guide[window13(n, L, bond)];
+        if (mulhi64((uint64_t)pr, (uint64_t)egmax) >= (uint64_t)e) continue;   /* not taken */
         G += log((double)e * 0x1p-16);
         uint8_t t = n[bond];
         n[bond] = n[(bond + 1) % L];

@@ -118,6 +118,7 @@ struct Layout {
     size_t state[2], K[2], Kb, A, ell, anc, origin[2], ksnap[2], ykey, tmax, tsum, thops, toff,
         log, ctl;
     size_t cu64, cf64, cu32;   // guided continuation records (0: not guided)
+    size_t iters;              // guided: proposals per clone of the last interval
     size_t end;
     int ntiles;
 };
@@ -148,7 +149,8 @@ Layout layout_of(const pd_params& p, size_t base)
     const bool guided = p.weight_mode == PD_W_GUIDED;
     o.cu64 = guided ? take(8 * Nc * (W + 2)) : 0;
     o.cf64 = guided ? take(8 * Nc * 4) : 0;
-    o.cu32 = guided ? take(4 * Nc * 5) : 0;
+    o.cu32 = guided ? take(4 * Nc * 4) : 0;
+    o.iters = guided ? take(4 * Nc) : 0;
     o.tmax = take(8 * (size_t)o.ntiles);
     o.tsum = take(8 * (size_t)o.ntiles);
     o.thops = take(8 * (size_t)o.ntiles);
@@ -451,6 +453,7 @@ pd_status pd_create(const pd_params* params, int32_t n, void* d_workspace, size_
         d.cont_u64 = o.cu64 ? (uint64_t*)(b + o.cu64) : nullptr;
         d.cont_f64 = o.cf64 ? (double*)(b + o.cf64) : nullptr;
         d.cont_u32 = o.cu32 ? (uint32_t*)(b + o.cu32) : nullptr;
+        d.iters = o.iters ? (uint32_t*)(b + o.iters) : nullptr;
         ctx->dev.push_back(d);
         if (p.selection == PD_SEL_IID) ctx->any_iid = true;
         if (p.weight_mode == PD_W_GUIDED) ctx->any_guided = true;
@@ -963,6 +966,8 @@ pd_status pd_set_guide(pd_ctx* ctx, const uint32_t* d_table, size_t n)
         if (ctx->params[i].weight_mode != PD_W_GUIDED) continue;
         ctx->dev[i].guide = own;
         ctx->dev[i].guide_max = hi;
+        // proposals come at e^{-s} hi 2^-16 per allowed bond (thinning)
+        ctx->dev[i].guide_scale = 65536.0 / (ctx->dev[i].es * (double)hi);
     }
     PD_HIP(hipMemcpyAsync(ctx->d_insts, ctx->dev.data(), sizeof(InstDev) * (size_t)ctx->n,
                           hipMemcpyHostToDevice, ctx->stream));

@@ -20,17 +20,19 @@ namespace pd {
 // per lane.  The guide is the table eg[u] over 13-site bond neighbourhoods
 // (site b-6 in bit 0; the bond's sites in bits 6 and 7): the hop across an
 // allowed bond b has rate e^{-s} eg[u_b] 2^-16.  S = sum of eg over allowed
-// bonds is kept exactly in integers, so the escape rate is e^{-s} S 2^-16;
-// the hop is chosen by proposing a uniform allowed bond and accepting it with
-// probability eg / eg_max (exact 64-bit Bernoulli), and the compensating
-// factor is ln Ups = -sum_jumps ln(eg 2^-16) - int (r - e^{-s} S 2^-16) dt.
-// Random numbers of a clone in interval beta: event k (its waiting times
-// counted from 0) takes Philox block (k, slot, beta, GUIDE): the waiting time
-// from words 0, 1 and the first proposal's bond word from words 2, 3; proposal
-// p (counted over the interval from 0) takes block (p, slot, beta, GUIDE_PROP):
-// its acceptance word from words 0, 1 and, if it is rejected, the next
-// proposal's bond word from words 2, 3.  Every call site draws one block per
-// pass of its loop, so no lane of a wave waits on another lane's refill.
+// bonds is kept exactly in integers, so the escape rate is e^{-s} S 2^-16,
+// and the compensating factor is
+// ln Ups = -sum_jumps ln(eg 2^-16) - int (r - e^{-s} S 2^-16) dt.
+// The jumps come by thinning: proposals at rate e^{-s} eg_max 2^-16 per
+// allowed bond (a bound of every controlled rate, so the waiting time is E
+// times a per-r table, no division), each across a uniform allowed bond,
+// taken with probability eg / eg_max.  Every pass of the loop is one proposal
+// and draws one Philox block, so no lane waits on another lane's retries.
+// Random numbers of a clone in interval beta: proposal k (counted over the
+// interval from 0) takes block (k, slot, beta, GUIDE): the waiting time from
+// words 0, 1, the 64-bit bond word bw from words 2, 3, the bond q =
+// floor(bw r / 2^64) among the allowed ones, and the acceptance word
+// (bw r) mod 2^64, taken iff floor(word eg_max / 2^64) < eg.
 // The whole table sits in LDS: its entries of neighbourhoods whose bond is no
 // hop are 0, so a sum over neighbourhoods needs no test of the bond.
 // sum_jumps ln eg is formed as the logarithm of the running product of the eg,
@@ -92,6 +94,7 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
 {
     __shared__ __align__(16) uint32_t s_eg[kGuideEntries];
     __shared__ double s_log[kLogRows * kLogCols];
+    __shared__ double s_invg[64 * W + 1];   // guide_scale / r: 1 / (proposal rate), r <= 64 W
     __shared__ __align__(8) uint8_t s_sel[2048];
 
     const TileDesc td = tiles[tile_base + blockIdx.x];
@@ -102,6 +105,8 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
     const uint32_t e0 = (uint32_t)td.tile * kTile;   // first handed-on clone of the block
     if (CONT && e0 >= ncont) return;                  // uniform over the block
     for (int i = threadIdx.x; i < kLogRows * kLogCols; i += kTile) s_log[i] = gptr(I.log_tab)[i];
+    for (int i = threadIdx.x; i <= 64 * W; i += kTile)
+        s_invg[i] = I.guide_scale * gptr(I.inv_count)[i];
     load_select_table(s_sel, I.sel_tab, threadIdx.x, kTile);
     // 16-byte pieces (the host checks the table's alignment)
     for (int i = threadIdx.x; i < kGuideEntries / 4; i += kTile)
@@ -112,7 +117,7 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
     const uint32_t q = e0 + (uint32_t)tid;            // handed-on clone (CONT)
     if (CONT ? q >= ncont : tid >= td.count) return;  // no barrier follows
     const uint32_t beta = (uint32_t)(I.ctl->beta + 1);
-    const uint32_t c3 = TAG_GUIDE | I.tag_hi, cp = TAG_GUIDE_PROP | I.tag_hi;
+    const uint32_t c3 = TAG_GUIDE | I.tag_hi;
     const double es = I.es, dt = I.dt;
     const uint64_t egmax = I.guide_max;
     // 14 entries of at most egmax each fit 32 bits (true for any guide whose
@@ -126,7 +131,7 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
 
     int64_t j;
     uint64_t x[W], m[W], Kfrom, S;
-    uint32_t k, prop, kb;
+    uint32_t k, kb;
     double tau, A, AS, P;
     int pexp;
     if (CONT) {
@@ -140,9 +145,8 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
         AS = gptr(I.cont_f64)[2 * Nc + q];
         P = gptr(I.cont_f64)[3 * Nc + q];
         k = gptr(I.cont_u32)[Nc + q];
-        prop = gptr(I.cont_u32)[2 * Nc + q];
-        kb = gptr(I.cont_u32)[3 * Nc + q];
-        pexp = (int)gptr(I.cont_u32)[4 * Nc + q];
+        kb = gptr(I.cont_u32)[2 * Nc + q];
+        pexp = (int)gptr(I.cont_u32)[3 * Nc + q];
         bond_mask<W>(x, lb, m);
     } else {
         j = td.first + tid;
@@ -154,7 +158,7 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
         bond_mask<W>(x, lb, m);
         S = guided_total<W>(x, m, L, s_eg);
         tau = 0.0; A = 0.0; AS = 0.0; P = 1.0;
-        k = 0; prop = 0; kb = 0; pexp = 0;
+        k = 0; kb = 0; pexp = 0;
     }
     int r = popcount_words<W>(m);
     const uint32_t eb = (CONT || !budgeted) ? 0u : I.ctl->ev_budget;
@@ -168,8 +172,8 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
         const uint4 y = philox10(k, (uint32_t)j, beta, c3, I.key0, I.key1);
         ++k;
         const double E = -log_unit(unit_scaled(y.x, y.y), s_log, I.ln2_hi, I.ln2_lo, poly, 53);
-        const double R = es * ((double)S * 0x1p-16);
-        const double w = E / R;
+        // waiting time of the next proposal: E / (e^{-s} eg_max 2^-16 r)
+        const double w = E * s_invg[r];
         if (tau + w >= dt) {
             A = fma((double)r, dt - tau, A);
             AS = fma((double)S, dt - tau, AS);
@@ -178,26 +182,21 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
         A = fma((double)r, w, A);
         AS = fma((double)S, w, AS);
         tau = tau + w;
-        int b = 0;
-        uint32_t e = 0;
-        uint32_t win0 = 0;             // L >= 26: the 26 sites from b-12
-        uint32_t qh = y.z, ql = y.w;   // bond word of the first proposal
-        for (int tries = 0; tries < (1 << 20); ++tries) {
-            b = select_bit_lut<W>(m, mulhi64_small(qh, ql, (uint32_t)r), s_sel);
-            // the neighbourhood of b is bits 6..18 of the window from b-12,
-            // which the update after a hop reuses
-            if (L >= 26) {
-                win0 = ring_bits_short<W>(x, L, b >= 12 ? b - 12 : b - 12 + L, 26);
-                e = s_eg[(win0 >> 6) & 0x1FFFu];
-            } else {
-                e = s_eg[ring_bits<W>(x, L, ring_mod(b - 6, L), 13)];
-            }
-            const uint4 a = philox10(prop, (uint32_t)j, beta, cp, I.key0, I.key1);
-            ++prop;
-            if (__umul64hi(((uint64_t)a.x << 32) | a.y, egmax) < (uint64_t)e) break;
-            qh = a.z;
-            ql = a.w;
+        // bw r = q 2^64 + a with bw = (y.z << 32) | y.w: the bond and the acceptance word
+        const uint64_t plo = (uint64_t)y.w * (uint32_t)r;
+        const uint64_t phi = (uint64_t)y.z * (uint32_t)r + (plo >> 32);
+        const int b = select_bit_lut<W>(m, (uint32_t)(phi >> 32), s_sel);
+        uint32_t e, win0 = 0;          // L >= 26: the 26 sites from b-12
+        // the neighbourhood of b is bits 6..18 of the window from b-12, which
+        // the update after a hop reuses
+        if (L >= 26) {
+            win0 = ring_bits_short<W>(x, L, b >= 12 ? b - 12 : b - 12 + L, 26);
+            e = s_eg[(win0 >> 6) & 0x1FFFu];
+        } else {
+            e = s_eg[ring_bits<W>(x, L, ring_mod(b - 6, L), 13)];
         }
+        // taken iff floor(a eg_max / 2^64) < e, a = (phi << 32) | (plo mod 2^32)
+        if (mulhi64_small((uint32_t)phi, (uint32_t)plo, (uint32_t)egmax) >= e) continue;
         P *= (double)e;
         pexp += __builtin_amdgcn_frexp_exp(P);
         P = __builtin_amdgcn_frexp_mant(P);
@@ -256,9 +255,8 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
         gptr(I.cont_f64)[3 * Nc + h] = P;
         gptr(I.cont_u32)[h] = (uint32_t)j;
         gptr(I.cont_u32)[Nc + h] = k;
-        gptr(I.cont_u32)[2 * Nc + h] = prop;
-        gptr(I.cont_u32)[3 * Nc + h] = kb;
-        gptr(I.cont_u32)[4 * Nc + h] = (uint32_t)pexp;
+        gptr(I.cont_u32)[2 * Nc + h] = kb;
+        gptr(I.cont_u32)[3 * Nc + h] = (uint32_t)pexp;
         return;
     }
     // sum_jumps ln(eg 2^-16) = ln P + (pexp - 16 kb) ln 2
@@ -271,6 +269,7 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
     gptr(I.Kb)[j] = kb;
     gptr(I.A)[j] = A;
     gptr(I.ell)[j] = ell;
+    gptr(I.iters)[j] = k;
 }
 
 // Tile aggregates from the outputs written by slot, one wave per tile (the
@@ -284,9 +283,16 @@ __global__ __launch_bounds__(kTile) void k_tile_stats(const InstDev* __restrict_
     if (t >= count) return;   // uniform over the wave; no barrier follows
     const TileDesc td = tiles[tile_base + t];
     const InstDev& I = insts[td.inst];
-    uint64_t h = 0;
-    for (int i = threadIdx.x & 63; i < td.count; i += 64) h += gptr(I.Kb)[td.first + i];
+    uint64_t h = 0, it = 0;
+    for (int i = threadIdx.x & 63; i < td.count; i += 64) {
+        h += gptr(I.Kb)[td.first + i];
+        it += gptr(I.iters)[td.first + i];
+    }
     tile_aggregate(I, td.tile, I.ell + td.first, td.count, h);
+    // proposals of the tile, for the next interval's event budget (k_prefix)
+    it = wave_reduce(it, OpSum());
+    if ((threadIdx.x & 63) == 0)
+        atomicAdd((unsigned long long*)&I.ctl->iters, (unsigned long long)it);
 }
 
 hipError_t launch_tile_stats(const InstDev* insts, const TileDesc* tiles, int base, int count,

@@ -13,8 +13,7 @@ constexpr int kLogRows = 128;       // rows of the logarithm table
 constexpr int kLogCols = 3;         // c, -ln c (multiple of 2^-42), remainder
 constexpr int kLogPoly = 6;         // log1p coefficients 1/7, -1/6, ..., -1/2
 
-enum : uint32_t { TAG_INIT = 1, TAG_DYN = 2, TAG_RESAMPLE = 3, TAG_IID = 4, TAG_GUIDE = 5,
-                  TAG_GUIDE_PROP = 6 };
+enum : uint32_t { TAG_INIT = 1, TAG_DYN = 2, TAG_RESAMPLE = 3, TAG_IID = 4, TAG_GUIDE = 5 };
 constexpr int kGuideEntries = 8192; // 13-site bond neighbourhoods
 enum : int32_t { MODE_MODIFIED = 0, MODE_DIRECT = 1, MODE_GUIDED = 2 };
 enum : int32_t { SEL_EQ = 0, SEL_IID = 1 };
@@ -33,7 +32,8 @@ struct InstCtl {
     uint64_t ksum;         // scratch: sum of K over the population (estimates)
     double d_eq;           // offset d of the [eq] points of interval beta (set by k_prefix)
     uint64_t ksnap_sum;    // scratch: sum of the burn-in snapshots of K (estimates)
-    uint64_t pad_[2];
+    uint64_t iters;        // guided stage: proposals of the current interval (zeroed by k_prefix)
+    uint64_t pad_;
 };
 
 // Per-instance descriptor (written by the host at creation, read-only after).
@@ -62,6 +62,8 @@ struct InstDev {
     double* log;           // [log_cycles][2] (lbeta, mean K^beta)
     const uint32_t* guide; // [8192] guide table e^g 2^16 over bond neighbourhoods
     uint64_t guide_max;    // largest table entry (acceptance bound)
+    double guide_scale;    // 2^16 / (e^{-s} guide_max): 1 / (proposal rate of one allowed bond)
+    uint32_t* iters;       // [Nc] guided: proposals of the last interval, by slot
     const double* log_tab; // [kLogRows][kLogCols] table of the device logarithm
     const uint8_t* sel_tab;// [2048] byte table of select_bit_lut (shared)
     double ln2_hi, ln2_lo; // ln 2 = ln2_hi (a multiple of 2^-42) + ln2_lo
@@ -74,7 +76,7 @@ struct InstDev {
     // handed them on (guided instances only, else null)
     uint64_t* cont_u64;    // [W + 2][Nc]: state words, carried K, S
     double* cont_f64;      // [4][Nc]: tau, integral of r dt, integral of S dt, jump product
-    uint32_t* cont_u32;    // [5][Nc]: slot, event index, proposal index, hops, jump exponent
+    uint32_t* cont_u32;    // [4][Nc]: slot, proposal index, hops, jump exponent
 };
 
 constexpr int kMaxGroups = 16;     // step launches per cycle (one per word count)

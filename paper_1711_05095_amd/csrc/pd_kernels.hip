@@ -88,6 +88,7 @@ __global__ void k_reset_ctl(const InstDev* __restrict__ insts, int n)
     c->hops = 0;
     c->ksum = 0;
     c->ksnap_sum = 0;
+    c->iters = 0;
 }
 
 // Neumaier compensated addition.
@@ -583,9 +584,13 @@ __device__ __forceinline__ void prefix_finish(const InstDev& I, uint32_t beta, d
     c->beta = beta;
     c->d_eq = eq_offset(I, beta);
     // the guided stage's next first launch: 1.1 times this interval's mean
-    // events per clone (hops + the closing draw), the rest in its second launch
+    // proposals per clone (taken, not taken and the closing draw), the rest in
+    // its second launch
     c->ncont = 0;
-    c->ev_budget = (uint32_t)fmin(1.1 * ((double)hops / (double)I.Nc + 1.0) + 2.0, 1073741824.0);
+    const double per_clone = c->iters ? (double)c->iters / (double)I.Nc
+                                      : (double)hops / (double)I.Nc + 1.0;
+    c->iters = 0;
+    c->ev_budget = (uint32_t)fmin(1.1 * per_clone + 2.0, 1073741824.0);
 }
 
 // Tiles per thread that k_prefix keeps in registers (instances of up to

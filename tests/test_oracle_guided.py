@@ -3,8 +3,8 @@
   * with a constant table the guide is the modified dynamics, so at s = 0
     every weight is exactly 1 and psi-hat is exactly 0;
   * the configuration after one interval follows column C0 of exp(W' t), W'
-    the generator of the guided rates (pins waiting times and the rejection
-    choice of the hop);
+    the generator of the guided rates (pins the proposal rate and the
+    thinning that takes a proposal with probability eg / eg_max);
   * the mean cloning factor over one interval is (e^{W_s dt} 1)(C0) for any
     table (pins the compensating weight);
   * E[e^{t psi-hat}] = Z(s, t) for any table and any population size;

@@ -55,8 +55,10 @@ MUTATIONS = [
     ("guided_rate_scale", "*ell_out = -G - (A - (es * 0x1p-16) * AS);",
      "*ell_out = -G - (A - es * AS);", GUIDED),
     ("guided_always_accept",
-     "if (mulhi64(word_of(y[0], y[1]), (uint64_t)egmax) < (uint64_t)e) break;",
-     "if (1) break;", GUIDED),
+     "if (mulhi64((uint64_t)pr, (uint64_t)egmax) >= (uint64_t)e) continue;",
+     "if (0) continue;", GUIDED),
+    ("guided_proposal_rate_drops_bound", "const double unit = es * ((double)egmax * 0x1p-16);",
+     "const double unit = es;", GUIDED),
     ("guided_drops_jump_term", "G += log((double)e * 0x1p-16);", "G += 0.0;", GUIDED),
     ("psi_burn_counts_burn_in_interval", "if (beta > p->burn_in) psi_burn_sum += lm;",
      "if (beta >= p->burn_in) psi_burn_sum += lm;", ESTIMATORS),
