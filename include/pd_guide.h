@@ -129,6 +129,22 @@ pd_status pdg_bond_table_cond(const float* window_table, const uint64_t* states,
                               double* G, uint32_t* counts, void* work, size_t work_bytes,
                               void* hip_stream);
 
+/* pdg_bond_table_cond without the caller's workspace, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): the arguments and results are
+ * those of pdg_bond_table_cond, and the function allocates nothing.  Its
+ * scratch is the library's own array of PDG_NOALLOC_SCRATCH_BYTES (160 KiB)
+ * per GPU, enough for any n (the distillation's scratch does not grow with
+ * the sample), held until the process ends.  Every call on a GPU uses that
+ * GPU's array: calls that overlap in time on one GPU (two streams, two host
+ * threads) race on it and must be serialised by the caller.  The sums and
+ * counts are cleared on the device at the start of each call. */
+#define PDG_NOALLOC_SCRATCH_BYTES 163840
+pd_status pdg_bond_table_cond_noalloc(const float* window_table, const uint64_t* states,
+                                      int64_t ld, int32_t L, int64_t n, int32_t min_count,
+                                      double gmax, uint32_t* eg, double* G, uint32_t* counts,
+                                      void* hip_stream);
+
 const char* pdg_last_error(void);
 
 #ifdef __cplusplus

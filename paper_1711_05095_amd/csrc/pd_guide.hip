@@ -16,6 +16,8 @@
 // (exact: its inputs are +-1) run on the matrix cores in bf16 with FP32
 // accumulation; layer 3 and the activations run on the vector ALU in FP32.
 #include <hip/hip_runtime.h>
+
+#include <atomic>
 #include <math.h>
 #include <stdint.h>
 
@@ -996,6 +998,40 @@ hipError_t launch_bond_table_cond(const float* H, const uint64_t* states, int64_
     hipLaunchKernelGGL(k_cond_finish, dim3(32), dim3(256), 0, st, sums, counts, min_count, gmax,
                        Gw, eg, counts_out);
     return hipGetLastError();
+}
+
+// Scratch of the allocation-free conditional distillation: the sums, counts
+// and (when the caller passes no G) the uniform-context table of
+// launch_bond_table_cond, kCondWorkBytes whatever the number of samples.  One
+// copy per GPU, held until the process ends and shared by every call on that
+// GPU (calls that overlap on one GPU race on it; k_zero_stats clears the sums
+// and counts at the start of every call).  Host code never passes `scratch`
+// itself to a kernel: its device address comes from hipGetSymbolAddress,
+// looked up once per device.
+static __device__ __align__(256) unsigned char scratch[kCondWorkBytes];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::atomic<void*> g_scratch_addr[kScratchDevices];
+}  // namespace
+
+hipError_t cond_scratch(void** out)
+{
+    *out = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kScratchDevices) return hipErrorInvalidDevice;
+    void* p = g_scratch_addr[dev].load(std::memory_order_acquire);
+    if (!p) {
+        // with `dev` current: each GPU holds its own copy at its own address
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_addr[dev].store(p, std::memory_order_release);
+    }
+    *out = p;
+    return hipSuccess;
 }
 
 hipError_t stats_set_smem_limit()

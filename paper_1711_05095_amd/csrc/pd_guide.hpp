@@ -37,5 +37,8 @@ hipError_t launch_bond_table_cond(const float* H, const uint64_t* states, int64_
                                   int64_t n, uint32_t min_count, double gmax, uint32_t* eg,
                                   double* G, uint32_t* counts_out, void* work, hipStream_t st);
 hipError_t stats_set_smem_limit();
+// Device address, on the current device, of the library's own kCondWorkBytes
+// of scratch for launch_bond_table_cond (looked up once per device).
+hipError_t cond_scratch(void** out);
 
 }  // namespace pd

@@ -175,6 +175,29 @@ pd_status pdg_bond_table_cond(const float* window_table, const uint64_t* states,
                 "conditional bond table launch");
 }
 
+pd_status pdg_bond_table_cond_noalloc(const float* window_table, const uint64_t* states,
+                                      int64_t ld, int32_t L, int64_t n, int32_t min_count,
+                                      double gmax, uint32_t* eg, double* G, uint32_t* counts,
+                                      void* hip_stream)
+{
+    std::string m = check_batch(states, ld, L, n);
+    if (!m.empty()) return gfail(PD_EINVAL, m);
+    if (L < PDG_COND_MIN_L) return gfail(PD_EINVAL, "conditional distillation needs L >= 26");
+    if (!window_table || !eg) return gfail(PD_EINVAL, "null pointer");
+    if (min_count < 1) return gfail(PD_EINVAL, "min_count must be >= 1");
+    if (!(gmax >= 0.0) || !(gmax <= PDG_MAX_GMAX)) return gfail(PD_EINVAL, "gmax out of range");
+    // the kernels need kCondWorkBytes of scratch for any n: the library's array holds exactly that
+    static_assert(PDG_NOALLOC_SCRATCH_BYTES == kCondWorkBytes, "no-allocation scratch size");
+    void* work = nullptr;
+    pd_status st = gdev(cond_scratch(&work), "scratch address");
+    if (st != PD_OK) return st;
+    st = once_per_device(g_stats_smem_set, stats_set_smem_limit);
+    if (st != PD_OK) return st;
+    return gdev(launch_bond_table_cond(window_table, states, ld, L, n, (uint32_t)min_count, gmax,
+                                       eg, G, counts, work, (hipStream_t)hip_stream),
+                "conditional bond table launch");
+}
+
 const char* pdg_last_error(void) { return g_guide_error.c_str(); }
 
 }  // extern "C"

@@ -16,7 +16,8 @@ PDG_COND_MIN_L = 26
 PDG_COND_WORK_BYTES = 163840
 
 EXPORTS = ["pdg_workspace_bytes", "pdg_forward", "pdg_loss_grad", "pdg_adam", "pdg_train_epoch",
-           "pdg_window_table", "pdg_bond_table", "pdg_bond_table_cond", "pdg_last_error"]
+           "pdg_window_table", "pdg_bond_table", "pdg_bond_table_cond",
+           "pdg_bond_table_cond_noalloc", "pdg_last_error"]
 
 _bound = False
 
@@ -39,6 +40,8 @@ def lib():
             "pdg_bond_table": [vp, c.c_double, vp, vp, vp],
             "pdg_bond_table_cond": [vp, vp, c.c_int64, c.c_int32, c.c_int64, c.c_int32, c.c_double,
                                     vp, vp, vp, vp, c.c_size_t, vp],
+            "pdg_bond_table_cond_noalloc": [vp, vp, c.c_int64, c.c_int32, c.c_int64, c.c_int32,
+                                            c.c_double, vp, vp, vp, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -177,3 +180,19 @@ def bond_table_cond(window, states, L, min_count, gmax, eg, G=None, counts=None,
                                      float(gmax), _p(eg), _p(G), _p(counts), _p(work),
                                      work.numel(), _stream(stream)))
     return work
+
+
+def bond_table_cond_noalloc(window, states, L, min_count, gmax, eg, G=None, counts=None,
+                            stream=None):
+    """bond_table_cond with the library's own scratch (no workspace argument)."""
+    import torch
+    n, ld = _states(states, L)
+    _dev(window, torch.float32, PDG_WINDOWS, "window")
+    _dev(eg, torch.int32, PDG_WINDOWS, "eg")
+    if G is not None:
+        _dev(G, torch.float64, PDG_WINDOWS, "G")
+    if counts is not None:
+        _dev(counts, torch.int32, PDG_WINDOWS, "counts")
+    _check(lib().pdg_bond_table_cond_noalloc(_p(window), _p(states), ld, L, n, int(min_count),
+                                             float(gmax), _p(eg), _p(G), _p(counts),
+                                             _stream(stream)))
