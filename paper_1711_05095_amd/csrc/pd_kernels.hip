@@ -723,6 +723,10 @@ __device__ __forceinline__ int count_points_below(double y, double d, double Ncd
 // chooses; the per-tile arithmetic and so every result is the same for any
 // TPW).  The interval ends are y_k = C_k (Nc / T) with one quotient per tile,
 // so the end of a tile and the start of the next are the same number.
+// Slots of one clone's offspring range that its own lane writes in the
+// cloning stage; the rest the wave writes together.
+constexpr int kShortRun = 8;
+
 template <int TPW>
 __global__ __launch_bounds__(kTile) void k_resample(const InstDev* __restrict__ insts,
                                                     const TileDesc* __restrict__ tiles,
@@ -809,8 +813,23 @@ __global__ __launch_bounds__(kTile) void k_resample(const InstDev* __restrict__ 
             const auto anc = gptr(I.anc);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                if (4 * lane + i < count)
-                    for (int jj = lo; jj < hi[i]; ++jj) anc[jj] = k0 + i;
+                // a lane writes up to kShortRun slots of each of its clones; the
+                // rest of a longer range (one clone pulled into many slots, as
+                // strongly concentrated weights give) the whole wave writes, 64
+                // slots a pass, so no lane runs a range alone
+                const bool mine = 4 * lane + i < count;
+                const int end = mine ? hi[i] : lo;
+                const int cut = min(end, lo + kShortRun);
+                for (int jj = lo; jj < cut; ++jj) anc[jj] = k0 + i;
+                uint64_t longs = __ballot(cut < end);
+                while (longs) {
+                    const int src = __builtin_ctzll(longs);
+                    longs &= longs - 1;
+                    const int a = __builtin_amdgcn_readlane(cut, src);
+                    const int z = __builtin_amdgcn_readlane(end, src);
+                    const int v = __builtin_amdgcn_readlane(k0 + i, src);
+                    for (int jj = a + lane; jj < z; jj += 64) anc[jj] = v;
+                }
                 lo = hi[i];
             }
         }

@@ -138,6 +138,31 @@ def test_lockstep_cycles(L, N, s, mode, Nc):
     assert S.estimates()["cycles"] == M
 
 
+@pytest.mark.parametrize("Nc", [20_000, 300_000])
+def test_concentrated_weights_selection(Nc):
+    """Strongly concentrated weights (direct form, s = -4, dt = 2: ln Ups = 4 K^beta
+    spreads over tens of units) put most new slots on one or a few clones, whose
+    long offspring ranges the whole wave writes.  The ancestor map equals the
+    oracle's selection on the same weights, and the population follows it."""
+    L, N, s, dt = 10, 5, -4.0, 2.0
+    print(f"concentrated weights Nc={Nc}", flush=True)
+    p, o = make(L, N, s, Nc, dt, M=3, seed=17, mode=DIR)
+    S = pd.Sampler(p)
+    biggest = 0
+    for beta in (1, 2):
+        S.step()
+        w_gpu, K_gpu = S.get_population()
+        _, _, ell = S.step_outputs()
+        S.resample()
+        anc = S.ancestors()
+        assert np.all(np.diff(anc) >= 0) and anc.min() >= 0 and anc.max() < Nc
+        check_selection(anc, ell, o.eq_offset(beta), "interval %d" % beta)
+        biggest = max(biggest, int(np.bincount(anc, minlength=Nc).max()))
+        w2, K2 = S.get_population()
+        assert np.array_equal(w2, w_gpu[:, anc]) and np.array_equal(K2, K_gpu[anc])
+    assert biggest > Nc // 10, biggest     # the long-range path is exercised
+
+
 @pytest.mark.parametrize("s,mode", [(-0.4, MOD), (0.4, MOD), (0.2, DIR), (-0.2, DIR)])
 def test_whole_run_psi(s, mode):
     w = inputs.SMALL
