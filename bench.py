@@ -136,6 +136,7 @@ def bench_batch(a):
                              instance=d["instance"]) for d in specs]
     B = pd.Sampler(params)
     tuning = B.autotune(2)
+    B.run(0)                   # graphs captured before the clock starts
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     B.run(cycles)
@@ -146,6 +147,7 @@ def bench_batch(a):
     for S in singles:
         S.set_tuning(tuning["step_variant"], tuning["refill"], tuning["graph_cycles"],
                      tuning["scan_tiles"])
+        S.run(0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for S in singles:
@@ -294,6 +296,7 @@ def bench_guided_rate(a):
         if mode == pd.PD_W_GUIDED:
             S.set_guide(g["eg"])
         S.run(8)
+        S.run(0)                   # graphs captured before the clock starts
         torch.cuda.synchronize()
         h0 = sum(S.estimates(i)["hops"] for i in range(S.n))
         t0 = time.perf_counter()
@@ -479,6 +482,10 @@ def bench_sweep(a):
     else:
         S.set_tuning(a.variant, a.refill, 16, a.scan_tiles)
         tuning = S.tuning()
+    # graphs as long as possible (<= 16 cycles, even) that tile the timed steps
+    g = max([c for c in range(2, 17, 2) if a.steps % c == 0] or [16])
+    S.set_tuning(tuning["step_variant"], tuning["refill"], g, tuning["scan_tiles"])
+    tuning = S.tuning()
     S.run(a.warmup)
     S.run(0)                             # captures the graphs (runs nothing)
     torch.cuda.synchronize()

@@ -193,6 +193,16 @@ pd_status pd_get_ancestors(pd_ctx* ctx, int32_t inst, int32_t* anc);
 pd_status pd_reset_origin(pd_ctx* ctx, int32_t inst);
 pd_status pd_get_origin(pd_ctx* ctx, int32_t inst, int32_t* origin);
 
+/* Descendant counts (track_origin = 1): d_counts[k] = the number of current
+ * clones of instance `inst` whose origin is k, i.e. the descendants of the
+ * clone that sat in slot k at the last pd_reset_origin (Sec. 2.4: after a
+ * long lag their expectation is proportional to v, the dominant eigenvector
+ * of the tilted generator, of that clone's configuration).  d_counts: a
+ * caller-owned device array of Nc uint32, overwritten.  Queued on the
+ * context stream (no synchronisation).  PD_ESTATE if tracking is off or
+ * between pd_step and pd_resample. */
+pd_status pd_descendant_counts(pd_ctx* ctx, int32_t inst, uint32_t* d_counts);
+
 /* Observables (Secs. 2.4, 3.3).  pd_density_mode queues, for every clone j of
  * instance `inst` (slot order), d_out[j] = |delta rho_n|^2 with
  * delta rho_n = L^{-1/2} sum over the occupied sites X of e^{-2 pi i n X / L}

@@ -1003,6 +1003,20 @@ pd_status pd_get_origin(pd_ctx* ctx, int32_t inst, int32_t* origin)
     return PD_OK;
 }
 
+pd_status pd_descendant_counts(pd_ctx* ctx, int32_t inst, uint32_t* d_counts)
+{
+    pd_status st = check_inst(ctx, inst);
+    if (st != PD_OK) return st;
+    if (!d_counts) return fail(ctx, PD_EINVAL, "null output");
+    if (!ctx->dev[inst].origin[0]) return fail(ctx, PD_ESTATE, "instance does not track origins");
+    if (ctx->stepped) return fail(ctx, PD_ESTATE, "counts between pd_step and pd_resample");
+    st = materialise(ctx);
+    if (st != PD_OK) return st;
+    PD_HIP(launch_descendants(ctx->d_insts, inst, ctx->params[inst].Nc, ctx->cur, d_counts,
+                              ctx->stream));
+    return PD_OK;
+}
+
 pd_status pd_density_mode(pd_ctx* ctx, int32_t inst, int32_t n, double* d_out)
 {
     pd_status st = check_inst(ctx, inst);

@@ -40,6 +40,8 @@ hipError_t launch_density_mode(int W, const InstDev* insts, int inst, int64_t Nc
                                double* out, hipStream_t st);
 hipError_t launch_mean(const InstDev* insts, int inst, int64_t Nc, int cur, const double* values,
                        int ancestral, hipStream_t st);
+hipError_t launch_descendants(const InstDev* insts, int inst, int64_t Nc, int cur,
+                              uint32_t* counts, hipStream_t st);
 hipError_t launch_prefix(const InstDev* insts, int n_inst, hipStream_t st);
 hipError_t launch_resample(const InstDev* insts, const TileDesc* tiles, int ntiles, int tpb,
                            hipStream_t st);

@@ -2,7 +2,8 @@
 // squared modulus of a Fourier mode of the density (eq. fourdens) per clone,
 // and the mean and the histogram of a per-clone quantity over the current
 // population (the end-time distribution) or over the ancestors of the current
-// population at the last origin reset (the ancestral distribution, eq. Opave).
+// population at the last origin reset (the ancestral distribution, eq. Opave),
+// and the descendant counts of the clones at the last origin reset.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -146,6 +147,33 @@ hipError_t launch_histogram(const InstDev* insts, int inst, int64_t Nc, int cur,
     const int blocks = (int)(need < 2048 ? need : 2048);
     hipLaunchKernelGGL(k_histogram, dim3(blocks), dim3(kTile), 0, st, insts, inst, cur, values,
                        ancestral, lo, width, nbins, counts);
+    return hipGetLastError();
+}
+
+// counts[k] = #{j : origin[cur][j] = k}: the descendants, among the current
+// clones of instance `inst`, of the clone that sat in slot k at the last
+// origin reset (Sec. 2.4: after a long lag their expectation is proportional
+// to v of its configuration).  Zeroed by k_zero_u32 first.
+__global__ void k_zero_u32(uint32_t* __restrict__ a, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = 0u;
+}
+
+__global__ __launch_bounds__(kTile) void k_descendants(const InstDev* __restrict__ insts, int inst,
+                                                       int cur, uint32_t* __restrict__ counts)
+{
+    const InstDev& I = insts[inst];
+    const int64_t j = (int64_t)blockIdx.x * kTile + threadIdx.x;
+    if (j < I.Nc) atomicAdd(&counts[gptr(I.origin[cur])[j]], 1u);
+}
+
+hipError_t launch_descendants(const InstDev* insts, int inst, int64_t Nc, int cur,
+                              uint32_t* counts, hipStream_t st)
+{
+    const unsigned blocks = (unsigned)((Nc + kTile - 1) / kTile);
+    hipLaunchKernelGGL(k_zero_u32, dim3(blocks), dim3(kTile), 0, st, counts, Nc);
+    hipLaunchKernelGGL(k_descendants, dim3(blocks), dim3(kTile), 0, st, insts, inst, cur, counts);
     return hipGetLastError();
 }
 

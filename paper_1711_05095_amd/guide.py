@@ -17,9 +17,9 @@ cloning factors barely vary.  So:
      bond table eg = 2^16 exp(average change of f across the hop), which
      pd_set_guide takes.
 
-Everything that computes runs in libpd.so; this module moves data between
-the sampler, the host (the counts are a histogram of origin ids) and the
-training kernels.
+Everything that computes runs in libpd.so (the descendant counts too); this
+module moves data between the sampler, the host (where the samples are
+shuffled) and the training kernels.
 """
 import numpy as np
 import torch
@@ -43,9 +43,10 @@ def collect(L, N, s, Nc, dt, lag_cycles, snapshots, burn_cycles, seed, instance=
             words, _ = sm.get_population()
             sm.reset_origin()
             sm.run(lag_cycles)
-            origin = sm.origin()
             states.append(words)
-            counts.append(np.bincount(origin, minlength=Nc).astype(np.float32))
+            # descendants of each snapshot clone, counted on the GPU (pd_descendant_counts)
+            n_desc = sm.descendant_counts().cpu().numpy().view(np.uint32)
+            counts.append(n_desc.astype(np.float32))
         return np.concatenate(states, axis=1), np.concatenate(counts)
     finally:
         sm.close()

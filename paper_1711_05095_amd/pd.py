@@ -24,9 +24,9 @@ EXPORTS = ["pd_workspace_bytes", "pd_create", "pd_destroy", "pd_step", "pd_resam
            "pd_scgf", "pd_estimates_get", "pd_population_bytes", "pd_get_population",
            "pd_set_population", "pd_get_step_outputs", "pd_get_ancestors", "pd_get_log",
            "pd_save_bytes", "pd_save", "pd_load", "pd_set_guide", "pd_reset_origin",
-           "pd_get_origin", "pd_density_mode", "pd_mean", "pd_histogram", "pd_get_tuning",
-           "pd_set_tuning", "pd_autotune", "pd_time_stages", "pd_get_stage_times", "pd_last_error",
-           "pd_status_str"]
+           "pd_get_origin", "pd_descendant_counts", "pd_density_mode", "pd_mean",
+           "pd_histogram", "pd_get_tuning", "pd_set_tuning", "pd_autotune", "pd_time_stages",
+           "pd_get_stage_times", "pd_last_error", "pd_status_str"]
 
 
 class PdParams(ctypes.Structure):
@@ -95,6 +95,7 @@ def lib():
             "pd_set_guide": [vp, vp, c.c_size_t],
             "pd_reset_origin": [vp, c.c_int32],
             "pd_get_origin": [vp, c.c_int32, vp],
+            "pd_descendant_counts": [vp, c.c_int32, vp],
             "pd_density_mode": [vp, c.c_int32, c.c_int32, vp],
             "pd_mean": [vp, c.c_int32, vp, c.c_int32, P(c.c_double)],
             "pd_histogram": [vp, c.c_int32, vp, c.c_int32, c.c_double, c.c_double, c.c_int32, vp],
@@ -247,6 +248,10 @@ def pd_get_origin(ctx, inst, Nc):
     return out
 
 
+def pd_descendant_counts(ctx, inst, counts_ptr):
+    _check(lib().pd_descendant_counts(ctx, inst, ctypes.c_void_p(counts_ptr)), ctx)
+
+
 def pd_density_mode(ctx, inst, n, out_ptr):
     _check(lib().pd_density_mode(ctx, inst, int(n), ctypes.c_void_p(out_ptr)), ctx)
 
@@ -385,6 +390,17 @@ class Sampler:
 
     def origin(self, inst=0):
         return pd_get_origin(self.ctx, inst, self.params[inst].Nc)
+
+    def descendant_counts(self, inst=0):
+        """Descendants of each slot of the last origin reset among the current
+        clones, as an int32 CUDA tensor of Nc entries (uint32 counts), written
+        on the sampler's stream and complete on return."""
+        import torch
+        out = torch.empty(self.params[inst].Nc, dtype=torch.int32, device=self.workspace.device)
+        torch.cuda.current_stream().synchronize()   # the allocation is ordered on torch's stream
+        pd_descendant_counts(self.ctx, inst, out.data_ptr())
+        self.stream.synchronize()
+        return out
 
     def density_mode(self, n, inst=0):
         """|delta rho_n|^2 of every clone (slot order) as a float64 CUDA tensor."""

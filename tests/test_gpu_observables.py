@@ -128,3 +128,23 @@ def test_histogram_validation():
     assert e.value.status == pd.PD_ESTATE
     S.resample()
     assert S.histogram(v, -0.5, 1.0, 3).tolist() == [100, 0, 0]
+
+
+def test_descendant_counts_equal_origin_histogram():
+    """pd_descendant_counts counts, per slot of the last origin reset, the
+    current clones that descend from it: the histogram of the carried origins
+    (Sec. 2.4), for [eq] and [iid] selection, through a graph-replayed run."""
+    for sel in (pd.PD_SEL_EQ, pd.PD_SEL_IID):
+        Nc = 70_000
+        p = pd.make_params(40, 20, 0.05, Nc, 30 * 0.5, 0.5, seed=3, selection=sel, track_origin=1)
+        S = pd.Sampler(p)
+        S.run(5)
+        S.reset_origin()
+        S.run(25)
+        counts = S.descendant_counts().cpu().numpy().view(np.uint32)
+        want = np.bincount(S.origin(), minlength=Nc)
+        assert np.array_equal(counts, want)
+        assert counts.sum() == Nc and (counts == 0).any() and counts.max() > 1
+    q = pd.make_params(40, 20, 0.05, 100, 1.0, 0.5, seed=3)
+    with pytest.raises(pd.PdError):
+        pd.Sampler(q).descendant_counts()       # origins not tracked
