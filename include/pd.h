@@ -276,9 +276,13 @@ typedef struct {
                              track_origin: variant 0 runs instead); 4: one
                              clone per lane, the unfinished clones of a tile
                              packed into the lowest lanes between rounds of
-                             events */
+                             events; 5: as 4, but all plain instances of the
+                             context, whatever their word counts, in one
+                             persistent launch whose blocks take tiles from a
+                             work counter (largest word count and expected
+                             work first) */
     int32_t refill;       /* variants 1-3: finished lanes (1..64) that trigger a
-                             refill; variant 4: length of the first round of
+                             refill; variants 4, 5: length of the first round of
                              events in sixteenths of the expected number per
                              clone (later rounds: 0.15 of it) */
     int32_t graph_cycles; /* cycles per captured graph in pd_run (even, 0: no graph) */

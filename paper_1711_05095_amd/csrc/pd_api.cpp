@@ -210,7 +210,8 @@ struct pd_ctx {
     InstDev* d_insts = nullptr;
     TileDesc* d_tiles = nullptr;
     std::vector<TileDesc> tiles;     // host copy, step order
-    std::vector<StepLaunch> steps;   // step launches, one per word count
+    std::vector<StepLaunch> steps;   // tile groups, one per word count (and the gathers)
+    std::vector<StepLaunch> launches;// the dynamical stage's launches under the tuning
     pd_tuning tuning;
     bool any_iid = false;
     bool any_guided = false;
@@ -287,7 +288,7 @@ pd_status enqueue_step(pd_ctx* ctx, int use_anc, int src)
         PD_HIP(launch_carry_burn(ctx->d_insts, ctx->d_tiles, (int)ctx->tiles.size(), src, use_anc,
                                  ctx->stream));
     PD_TIME(ctx->ev_step);
-    for (const auto& g : ctx->steps)
+    for (const auto& g : ctx->launches)
         PD_HIP(launch_step(g, ctx->d_insts, ctx->d_tiles, src, use_anc, ctx->stream));
     PD_TIME(ctx->ev_step);
     PD_HIP(launch_prefix(ctx->d_insts, ctx->n, ctx->stream));
@@ -305,7 +306,7 @@ pd_status enqueue_cycle(pd_ctx* ctx, int use_anc, int src)
 // Applies a tuning: kernel variant and grid of every step launch.
 pd_status apply_tuning(pd_ctx* ctx, const pd_tuning& t)
 {
-    if (t.step_variant < 0 || t.step_variant > 4 || t.refill < 1 || t.refill > 64 ||
+    if (t.step_variant < 0 || t.step_variant > 5 || t.refill < 1 || t.refill > 64 ||
         t.graph_cycles < 0 || (t.graph_cycles & 1) ||
         !(t.scan_tiles == 0 || t.scan_tiles == 1 || t.scan_tiles == 2 || t.scan_tiles == 4 ||
           t.scan_tiles == 8))
@@ -314,15 +315,43 @@ pd_status apply_tuning(pd_ctx* ctx, const pd_tuning& t)
     PD_HIP(hipGetDevice(&dev));
     PD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     for (auto& g : ctx->steps) {
-        // the guided stage has no variants; the queued variants do not carry origins
+        // the guided stage has no variants; the queued variants do not carry origins;
+        // under variant 5 the groups keep variant 4 (the merged launch is built below)
         g.variant = g.guided ? 0
                   : (ctx->any_origin && t.step_variant >= 1 && t.step_variant <= 3) ? 0
+                  : t.step_variant == 5 ? 4
                   : t.step_variant;
         g.refill = t.refill;
         int per_cu = 0;
         PD_HIP(step_occupancy(g.W, g.variant, &per_cu));
         const int want = (g.count + 3) / 4;          // four waves per block, a tile each
         g.blocks = std::max(1, std::min(want, std::max(1, per_cu) * std::max(1, cus)));
+    }
+    // the launches: variant 5 merges the plain groups (the first ones in the step
+    // order) into one persistent launch, the guided groups keep theirs
+    ctx->launches.clear();
+    if (t.step_variant == 5) {
+        StepLaunch m{};
+        int wmax = 0, count = 0;
+        for (const auto& g : ctx->steps)
+            if (!g.guided) { wmax = std::max(wmax, g.W); count += g.count; }
+        if (count > 0) {
+            m.W = wmax <= 2 ? 2 : wmax <= 4 ? 4 : 8;
+            m.variant = 5;
+            m.guided = false;
+            m.base = 0;
+            m.count = count;
+            m.refill = t.refill;
+            m.counter = ctx->steps[0].counter;
+            int per_cu = 0;
+            PD_HIP(step_occupancy(m.W, 5, &per_cu));
+            m.blocks = std::max(1, std::min(count, std::max(1, per_cu) * std::max(1, cus)));
+            ctx->launches.push_back(m);
+        }
+        for (const auto& g : ctx->steps)
+            if (g.guided) ctx->launches.push_back(g);
+    } else {
+        ctx->launches = ctx->steps;
     }
     if (t.graph_cycles != ctx->tuning.graph_cycles)
         for (auto& gx : ctx->graph)
@@ -477,9 +506,11 @@ pd_status pd_create(const pd_params* params, int32_t n, void* d_workspace, size_
                             td.count * (rate * p.dt + 1.0)});
         }
     }
+    // plain tiles first (variant 5 runs them as one launch from tile 0), the
+    // larger word counts first, the larger expected work first within a word count
     std::stable_sort(cand.begin(), cand.end(), [](const Cand& a, const Cand& b) {
         if (a.guided != b.guided) return !a.guided;
-        if (a.W != b.W) return a.W < b.W;
+        if (a.W != b.W) return a.W > b.W;
         return a.cost > b.cost;
     });
     for (size_t k = 0; k < cand.size(); ++k) {
@@ -1118,6 +1149,11 @@ pd_status pd_autotune(pd_ctx* ctx, int32_t trial_cycles, pd_tuning* best)
             t.refill = rf;
             cands.push_back(t);
         }
+    t.step_variant = 5;
+    for (int f : {13, 14}) {
+        t.refill = f;
+        cands.push_back(t);
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     PD_HIP(hipEventCreate(&e0));
     PD_HIP(hipEventCreate(&e1));

@@ -244,34 +244,40 @@ struct Pack {
     uint32_t k[kTile], kb[kTile], t[kTile];
 };
 
+// The LDS arrays of one compacting tile run (the tables are filled by the
+// caller: the logarithm and selection tables once, 1 / r per instance).
 template <int W>
-__global__ __launch_bounds__(kTile) void k_step_c(const InstDev* __restrict__ insts,
-                                                  const TileDesc* __restrict__ tiles,
-                                                  int tile_base, int src, int use_anc,
-                                                  int first16)
+struct TileLds {
+    double* invr;          // [64 W + 1]: inv_scale / r
+    double* log;           // logarithm table
+    uint8_t* sel;          // selection byte table
+    double* ell;           // [kTile]
+    uint32_t* kb;          // [kTile]
+    int* wc;               // [kTile / 64]
+    Pack<W>* P;
+};
+
+// One tile of 256 clones through the interval, in rounds with compaction (the
+// body of k_step_c, also run tile after tile by k_step_cp).  Every thread of
+// the block calls it; it ends with every thread past its last barrier.
+template <int W>
+__device__ __forceinline__ void run_tile_c(const InstDev& I, const TileDesc& td,
+                                           const TileLds<W>& S, int src, int use_anc,
+                                           int first16)
 {
-    __shared__ double s_invr[64 * W + 1];     // r <= L <= 64 W
-    __shared__ double s_log[kLogRows * kLogCols];
-    __shared__ double s_ell[kTile];
-    __shared__ uint32_t s_kb[kTile];
-    __shared__ int s_wc[kTile / 64];
-    __shared__ __align__(8) uint8_t s_sel[2048];
-    __shared__ Pack<W> P;
-
-    const TileDesc td = tiles[tile_base + blockIdx.x];
-    const InstDev& I = insts[td.inst];
     const int L = I.L;
-    load_tables(I, s_log, s_invr, threadIdx.x, kTile, 64 * W, true);
-    load_select_table(s_sel, I.sel_tab, threadIdx.x, kTile);
-
     StepConst C;
-    C.invr = s_invr; C.logt = s_log; C.sel = s_sel; C.inv_scale = I.inv_scale;
+    C.invr = S.invr; C.logt = S.log; C.sel = S.sel; C.inv_scale = I.inv_scale;
     C.dt = I.dt; C.ln2_hi = I.ln2_hi; C.ln2_lo = I.ln2_lo;
 #pragma unroll
     for (int k = 0; k < kLogPoly; ++k) C.poly[k] = I.log_poly[k];
     C.beta = (uint32_t)(I.ctl->beta + 1); C.c3 = TAG_DYN | I.tag_hi;
     C.key0 = I.key0; C.key1 = I.key1; C.L = L; C.lb = (L - 1) & 63;
 
+    double* const s_ell = S.ell;
+    uint32_t* const s_kb = S.kb;
+    int* const s_wc = S.wc;
+    Pack<W>& P = *S.P;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t Nc = I.Nc;
     const int dst = src ^ 1;
@@ -366,6 +372,98 @@ __global__ __launch_bounds__(kTile) void k_step_c(const InstDev* __restrict__ in
         uint64_t h = 0;
         for (int i = tid; i < td.count; i += 64) h += s_kb[i];
         tile_aggregate(I, td.tile, s_ell, td.count, h);
+    }
+}
+
+template <int W>
+__global__ __launch_bounds__(kTile) void k_step_c(const InstDev* __restrict__ insts,
+                                                  const TileDesc* __restrict__ tiles,
+                                                  int tile_base, int src, int use_anc,
+                                                  int first16)
+{
+    __shared__ double s_invr[64 * W + 1];     // r <= L <= 64 W
+    __shared__ double s_log[kLogRows * kLogCols];
+    __shared__ double s_ell[kTile];
+    __shared__ uint32_t s_kb[kTile];
+    __shared__ int s_wc[kTile / 64];
+    __shared__ __align__(8) uint8_t s_sel[2048];
+    __shared__ Pack<W> P;
+
+    const TileDesc td = tiles[tile_base + blockIdx.x];
+    const InstDev& I = insts[td.inst];
+    load_tables(I, s_log, s_invr, threadIdx.x, kTile, 64 * W, true);
+    load_select_table(s_sel, I.sel_tab, threadIdx.x, kTile);
+    const TileLds<W> S{s_invr, s_log, s_sel, s_ell, s_kb, s_wc, &P};
+    run_tile_c<W>(I, td, S, src, use_anc, first16);   // its first barrier orders the tables
+}
+
+// ---------------------------------------------------------------------------
+// Dynamical stage, compacting, in one persistent launch for all plain tiles of
+// a context, word counts W <= WMAX mixed (the batched form): each block takes
+// tiles from the launch's work counter in the step order (largest word count
+// and expected work first) and runs each as k_step_c does, dispatching on the
+// tile's W (uniform over the block).  The logarithm and selection tables are
+// loaded once per block, 1 / r when the instance changes.  Results are those of
+// k_step_c bit for bit: random numbers are keyed by slot, outputs written by
+// slot, each tile aggregated in the same order.
+// ---------------------------------------------------------------------------
+// run_tile_c for the tile's word count w (W <= w <= WMAX), the packing buffer
+// taken as a Pack<w>.
+template <int W, int WMAX>
+__device__ __forceinline__ void step_tile_w(int w, const InstDev& I, const TileDesc& td,
+                                            double* s_invr, double* s_log, uint8_t* s_sel,
+                                            double* s_ell, uint32_t* s_kb, int* s_wc,
+                                            unsigned char* s_pack, int src, int use_anc,
+                                            int first16)
+{
+    if (w == W) {
+        const TileLds<W> S{s_invr, s_log, s_sel, s_ell, s_kb, s_wc, (Pack<W>*)s_pack};
+        run_tile_c<W>(I, td, S, src, use_anc, first16);
+        return;
+    }
+    if constexpr (W < WMAX)
+        step_tile_w<W + 1, WMAX>(w, I, td, s_invr, s_log, s_sel, s_ell, s_kb, s_wc, s_pack, src,
+                                 use_anc, first16);
+}
+
+template <int WMAX>
+__global__ __launch_bounds__(kTile) void k_step_cp(const InstDev* __restrict__ insts,
+                                                   const TileDesc* __restrict__ tiles,
+                                                   int tile_base, int tile_count,
+                                                   uint32_t* __restrict__ counter, int src,
+                                                   int use_anc, int first16)
+{
+    __shared__ double s_invr[64 * WMAX + 1];
+    __shared__ double s_log[kLogRows * kLogCols];
+    __shared__ double s_ell[kTile];
+    __shared__ uint32_t s_kb[kTile];
+    __shared__ int s_wc[kTile / 64];
+    __shared__ __align__(8) uint8_t s_sel[2048];
+    __shared__ __align__(16) unsigned char s_pack[sizeof(Pack<WMAX>)];
+    __shared__ int s_next;
+
+    for (int i = threadIdx.x; i < kLogRows * kLogCols; i += kTile) s_log[i] = gptr(insts[0].log_tab)[i];
+    load_select_table(s_sel, insts[0].sel_tab, threadIdx.x, kTile);
+    int inst = -1;
+    for (;;) {
+        if (threadIdx.x == 0) s_next = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int n = s_next;
+        __syncthreads();   // every thread has read s_next before it is written again
+        if (n >= tile_count) break;
+        const TileDesc td = tiles[tile_base + n];
+        const InstDev& I = insts[td.inst];
+        if (td.inst != inst) {
+            // the previous tile's last barrier is behind every thread: the old
+            // 1 / r is no longer read
+            inst = td.inst;
+            const double sc = I.inv_scale;
+            for (int r = threadIdx.x; r <= 64 * I.W; r += kTile)
+                s_invr[r] = sc * gptr(I.inv_count)[r];
+        }
+        // run_tile_c's first barrier orders the tables and the packing buffer
+        step_tile_w<1, WMAX>(I.W, I, td, s_invr, s_log, s_sel, s_ell, s_kb, s_wc, s_pack, src,
+                             use_anc, first16);
     }
 }
 
@@ -995,6 +1093,20 @@ hipError_t launch_step(const StepLaunch& s, const InstDev* insts, const TileDesc
         break;
         PD_W_SWITCH(s.W, PD_CASE)
 #undef PD_CASE
+    } else if (s.variant == 5) {
+        // one persistent launch over every plain tile; s.W is the bucket (2, 4, 8)
+        switch (s.W) {
+            case 2: hipLaunchKernelGGL(k_step_cp<2>, dim3(s.blocks), dim3(kTile), 0, st, insts,
+                                       tiles, s.base, s.count, s.counter, src, use_anc, s.refill);
+                    break;
+            case 4: hipLaunchKernelGGL(k_step_cp<4>, dim3(s.blocks), dim3(kTile), 0, st, insts,
+                                       tiles, s.base, s.count, s.counter, src, use_anc, s.refill);
+                    break;
+            case 8: hipLaunchKernelGGL(k_step_cp<8>, dim3(s.blocks), dim3(kTile), 0, st, insts,
+                                       tiles, s.base, s.count, s.counter, src, use_anc, s.refill);
+                    break;
+            default: return hipErrorInvalidValue;
+        }
     } else if (s.variant == 1) {
 #define PD_CASE(w)                                                                            \
     case w:                                                                                   \
@@ -1039,6 +1151,14 @@ hipError_t step_occupancy(int W, int variant, int* blocks_per_cu)
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_step_c<w>, kTile, 0);
         PD_W_SWITCH(W, PD_CASE)
 #undef PD_CASE
+    }
+    if (variant == 5) {
+        switch (W) {
+            case 2: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_step_cp<2>, kTile, 0);
+            case 4: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_step_cp<4>, kTile, 0);
+            case 8: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_step_cp<8>, kTile, 0);
+            default: return hipErrorInvalidValue;
+        }
     }
 #define PD_CASE(w)                                                                            \
     case w:                                                                                   \

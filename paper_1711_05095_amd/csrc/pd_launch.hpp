@@ -9,8 +9,10 @@ namespace pd {
 // One launch of the dynamical stage: the tiles [base, base + count) of the
 // step order, all with W words per state.
 struct StepLaunch {
-    int W;
-    int variant;           // 0: one clone per lane; 1..3: persistent queued waves
+    int W;                 // words per state (variant 5: the bucket 2, 4 or 8 of the largest)
+    int variant;           // 0: one clone per lane; 1..3: persistent queued waves; 4:
+                           // compacting, a block per tile; 5: compacting, one persistent
+                           // launch over every plain tile (mixed W)
     bool guided;           // guided instances (always one clone per lane)
     int base, count;       // tiles
     int blocks;            // grid of the persistent variant

@@ -196,9 +196,11 @@ def test_log_shorter_than_run():
         S.log(n + 1)
 
 
-def test_batched_workload_equals_separate():
+@pytest.mark.parametrize("variant", [4, 5])
+def test_batched_workload_equals_separate(variant):
     """The 64-instance batched workload, a few graph-replayed cycles in one
-    context, against each instance in a context of its own."""
+    context (one compacting launch per word count, or all 64 instances in one
+    persistent launch), against each instance in a context of its own."""
     specs = inputs.batched_instances()
     assert len(specs) == 64
     M = 6
@@ -207,6 +209,7 @@ def test_batched_workload_equals_separate():
     print("batched workload: %d instances, %d clones" % (len(params), sum(d["Nc"] for d in specs)),
           flush=True)
     B = pd.Sampler(params)
+    B.set_tuning(variant, 13, 16, 1)
     B.run(M)
     for i, q in enumerate(params):
         S = pd.Sampler(q)

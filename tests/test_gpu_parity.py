@@ -611,7 +611,7 @@ def test_launch_variants_bit_identical():
     ref = None
     for variant, refill, graph, tpb in [(0, 8, 16, 1), (1, 1, 16, 1), (1, 8, 0, 2), (1, 32, 4, 1),
                                         (1, 64, 2, 4), (4, 8, 16, 8), (4, 8, 0, 1), (2, 8, 2, 1),
-                                        (3, 16, 16, 2)]:
+                                        (3, 16, 16, 2), (5, 13, 16, 1), (5, 8, 0, 2)]:
         S = pd.Sampler(params)
         S.set_tuning(variant, refill, graph, tpb)
         S.run(M)
@@ -656,11 +656,13 @@ def test_batch_equals_separate():
         assert np.array_equal(ws, wb) and np.array_equal(Ks, Kb)
 
 
-def test_mixed_forms_in_one_context_equal_separate():
+@pytest.mark.parametrize("variant", [4, 5])
+def test_mixed_forms_in_one_context_equal_separate(variant):
     """One context holding instances of every weight form and both selections
     (modified, direct, guided; [eq] and [iid]), of uneven L and Nc, run through
     graph-replayed cycles with origins tracked: each instance equals, bit for
-    bit, the same instance alone in a context of its own."""
+    bit, the same instance alone in a context of its own (with the plain
+    instances in one launch per word count, or all in one persistent launch)."""
     from guide_tables import random_table
     table = _guide_tensor(random_table(11))
     EQ = pd.PD_SEL_EQ
@@ -673,6 +675,7 @@ def test_mixed_forms_in_one_context_equal_separate():
               for i, (L, N, s, Nc, dt, mode, sel) in enumerate(specs)]
     B = pd.Sampler(params)
     B.set_guide(table)
+    B.set_tuning(variant, 13, 16, 1)
     B.run(3)
     for i in range(len(params)):
         B.reset_origin(i)
