@@ -142,8 +142,9 @@ pd_status pd_resample(pd_ctx* ctx);
 /* `cycles` repetitions of (pd_step, pd_resample) -- the cloning algorithm's
  * cycle of Sec. 2.3 -- replayed from captured HIP graphs of graph_cycles
  * cycles (pd_tuning; the remainder as single launches).  Asynchronous.
- * cycles = 0 runs nothing and captures the graphs that later calls replay (a
- * graph is otherwise captured on its first use).  Graphs need a stream other
+ * cycles = 0 runs nothing and captures the graphs that later calls replay,
+ * uploading them to the device (a graph is otherwise captured and uploaded on
+ * its first use).  Graphs need a stream other
  * than the legacy default stream; with NULL every cycle is a single launch.
  * PD_ESTATE if a pd_step is waiting for its pd_resample. */
 pd_status pd_run(pd_ctx* ctx, int64_t cycles);

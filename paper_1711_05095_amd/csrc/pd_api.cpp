@@ -637,6 +637,8 @@ pd_status capture_graph(pd_ctx* ctx, int which)
     hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     PD_HIP(ei);
+    // the executable's upload to the device is paid here, not by its first replay
+    PD_HIP(hipGraphUpload(ex, ctx->stream));
     return PD_OK;
 }
 
