@@ -55,6 +55,14 @@ PEAK_HBM_GBS = 8000.0
 VALU_PER_EVENT_W2 = 160
 VALU_PER_EVENT_W7 = 285   # the same loop for 400-site states (7 words), same commit
 VALU_UNIT_SOURCE = "event loop of k_step<2> at commit 6d3c1d5"
+# The guided stage's unit (isa_count.guided_paths, k_step_g<2> at commit
+# d06e9ac, a trained table at L >= 26): 183 VALU instructions per random draw
+# (a proposal: Philox block, waiting time, the 26-site window, the acceptance
+# product; or the closing draw) and 98 more per taken proposal (the jump term,
+# the 14 + 14 table reads that keep the controlled escape rate S, the hop).
+VALU_PER_DRAW_G2 = 183
+VALU_PER_HOP_G2 = 98
+GUIDED_UNIT_SOURCE = "paths of k_step_g<2>'s loop at commit d06e9ac"
 # Counter readings of the step kernel on the bench's workload (rocprofv3
 # SQ_INSTS_VALU, SQ_BUSY_CYCLES, SQ_WAVES; profiles/k_step_sweep_L100_Nc1e5.txt):
 # VALU wave-instructions issued per CU per cycle of the kernel, and the
@@ -68,7 +76,7 @@ RESAMPLE_BYTES_PER_CLONE = 12
 # HBM bytes per launch of the step kernel on this workload, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE runs scaled by a plain 1 GiB copy (factors 2 and
 # 1), valid only for the kernel sources they were taken on (STEP_SOURCES).
-STEP_TRAFFIC = {"bytes": 239.5e6, "kernels_sha1": "e5595ab71d48", "kernel": "k_step_c<2>"}
+STEP_TRAFFIC = {"bytes": 240.7e6, "kernels_sha1": "2889b1a91689", "kernel": "k_step_c<2>"}
 STEP_SOURCES = ["pd_kernels.hip", "pd_tile.hpp", "pd_device.hpp", "pd_internal.hpp"]
 
 
@@ -280,7 +288,10 @@ def bench_guided_rate(a):
     """Throughput of the guided dynamical stage against the plain one on the
     same workload: a guide trained at L=100, lambda=15 (Nc=1e5, 10 snapshots,
     lag 100 intervals), then 32 instances x Nc=1e5 (one lambda, 32 seeds),
-    dt=0.5, a.steps cycles each after 8 warm-up cycles."""
+    dt=0.5, a.steps cycles each after 8 warm-up cycles.  Then 20 single-launch
+    cycles with HIP events around the stages give the guided dynamical stage's
+    duration, set against the ALU roofline in the guided unit (VALU per draw
+    and per taken proposal)."""
     import torch
     from paper_1711_05095_amd import guide
     L, N, lam, dt = 100, 50, 15.0, 0.5
@@ -288,15 +299,16 @@ def bench_guided_rate(a):
     g = guide.train_guide(L, N, s, Nc=100_000, dt=dt, lag_cycles=100, snapshots=10,
                           burn_cycles=400, epochs=10, lr=1e-3, decay=0.8, gmax=1.0, seed=9)
     steps = min(a.steps, 200)
+    n_ev = 20
     out = {}
     for name, mode in (("plain", pd.PD_W_MODIFIED), ("guided", pd.PD_W_GUIDED)):
-        ps = [pd.make_params(L, N, s, 100_000, (steps + 8) * dt, dt, seed=2000 + i, instance=i,
-                             weight_mode=mode) for i in range(32)]
+        ps = [pd.make_params(L, N, s, 100_000, (steps + 8 + n_ev) * dt, dt, seed=2000 + i,
+                             instance=i, weight_mode=mode) for i in range(32)]
         S = pd.Sampler(ps)
         if mode == pd.PD_W_GUIDED:
             S.set_guide(g["eg"])
+        S.run(0)                   # graphs captured and uploaded before the clock starts
         S.run(8)
-        S.run(0)                   # graphs captured before the clock starts
         torch.cuda.synchronize()
         h0 = sum(S.estimates(i)["hops"] for i in range(S.n))
         t0 = time.perf_counter()
@@ -306,6 +318,26 @@ def bench_guided_rate(a):
         h = sum(S.estimates(i)["hops"] for i in range(S.n)) - h0
         out[name] = {"hops_per_second": h / el, "ms_per_cycle": el / steps * 1e3,
                      "hops_per_clone_interval": h / (steps * 32 * 100_000)}
+        if mode == pd.PD_W_GUIDED:
+            e0 = [S.estimates(i) for i in range(S.n)]
+            S.time_stages(True)
+            for _ in range(n_ev):
+                S.step()
+                S.resample()
+            tm = S.stage_times()
+            S.time_stages(False)
+            e1 = [S.estimates(i) for i in range(S.n)]
+            hops_c = sum(b["hops"] - c["hops"] for b, c in zip(e1, e0)) / n_ev
+            draws_c = sum(b["draws"] - c["draws"] for b, c in zip(e1, e0)) / n_ev
+            ach = (draws_c * VALU_PER_DRAW_G2 + hops_c * VALU_PER_HOP_G2) / (tm["step_ms"] / 1e3)
+            out[name]["roofline"] = {
+                "bound": "alu", "kernel": "k_step_g<2> (both launches) + k_tile_stats",
+                "achieved": ach / 1e12, "peak": PEAK_VALU_LANE_OPS / 1e12,
+                "unit": "T VALU lane-instr/s", "frac": ach / PEAK_VALU_LANE_OPS,
+                "per_unit": "%d VALU instr per draw + %d per taken proposal (%s)"
+                            % (VALU_PER_DRAW_G2, VALU_PER_HOP_G2, GUIDED_UNIT_SOURCE),
+                "stage_ms_mean": tm["step_ms"], "draws_per_cycle": draws_c,
+                "hops_per_cycle": hops_c, "draws_per_hop": draws_c / hops_c}
         S.close()
     return {"metric": "clone-hops/s, guided", "value": out["guided"]["hops_per_second"],
             "unit": "clone-hops/s", "n_gpus": 1, "steps": steps, "warmup": 8,

@@ -109,6 +109,10 @@ typedef struct {
                              ancestor carried at the end of interval burn_in); equal to k_hat
                              when burn_in = 0; 0 until beta > burn_in.  With burn_in > 0,
                              pd_set_population restarts K' at 0 for the clones it installs */
+    uint64_t draws;       /* guided instances: random draws of the guided dynamical stage so
+                             far, one per proposed hop (taken or not, Sec. 2.2 by thinning)
+                             and one closing draw per clone per interval; 0 for the other
+                             forms */
 } pd_estimates;
 
 typedef struct pd_ctx pd_ctx;   /* opaque, host-side, owned by the library */

@@ -119,6 +119,7 @@ struct Layout {
         log, ctl;
     size_t cu64, cf64, cu32;   // guided continuation records (0: not guided)
     size_t iters;              // guided: proposals per clone of the last interval
+    size_t rate[2];            // guided: S of each clone at the end of its interval
     size_t end;
     int ntiles;
 };
@@ -151,6 +152,8 @@ Layout layout_of(const pd_params& p, size_t base)
     o.cf64 = guided ? take(8 * Nc * 4) : 0;
     o.cu32 = guided ? take(4 * Nc * 4) : 0;
     o.iters = guided ? take(4 * Nc) : 0;
+    o.rate[0] = guided ? take(8 * Nc) : 0;
+    o.rate[1] = guided ? take(8 * Nc) : 0;
     o.tmax = take(8 * (size_t)o.ntiles);
     o.tsum = take(8 * (size_t)o.ntiles);
     o.thops = take(8 * (size_t)o.ntiles);
@@ -373,6 +376,17 @@ pd_status check_inst(pd_ctx* ctx, int32_t inst)
     return PD_OK;
 }
 
+// The guided stage of instance i forms S from the state at its next step: the
+// carried rates no longer match the population or the table.
+pd_status drop_carried_rates(pd_ctx* ctx, int i)
+{
+    static const uint32_t zero = 0;
+    if (ctx->params[i].weight_mode != PD_W_GUIDED) return PD_OK;
+    PD_HIP(hipMemcpyAsync(&ctx->dev[i].ctl->s_carried, &zero, sizeof zero, hipMemcpyHostToDevice,
+                          ctx->stream));
+    return PD_OK;
+}
+
 // Makes state[cur] hold the population in slot order.
 pd_status materialise(pd_ctx* ctx)
 {
@@ -483,6 +497,8 @@ pd_status pd_create(const pd_params* params, int32_t n, void* d_workspace, size_
         d.cont_f64 = o.cf64 ? (double*)(b + o.cf64) : nullptr;
         d.cont_u32 = o.cu32 ? (uint32_t*)(b + o.cu32) : nullptr;
         d.iters = o.iters ? (uint32_t*)(b + o.iters) : nullptr;
+        d.rate[0] = o.rate[0] ? (uint64_t*)(b + o.rate[0]) : nullptr;
+        d.rate[1] = o.rate[1] ? (uint64_t*)(b + o.rate[1]) : nullptr;
         ctx->dev.push_back(d);
         if (p.selection == PD_SEL_IID) ctx->any_iid = true;
         if (p.weight_mode == PD_W_GUIDED) ctx->any_guided = true;
@@ -714,6 +730,7 @@ pd_status pd_estimates_get(pd_ctx* ctx, int32_t inst, pd_estimates* out)
                           ? (double)(c.ksum - c.ksnap_sum) /
                                 ((double)p.Nc * (double)p.L * (double)(c.beta - p.burn_in) * p.dt)
                           : 0.0;
+    out->draws = c.draws;
     return PD_OK;
 }
 
@@ -791,6 +808,8 @@ pd_status pd_set_population(pd_ctx* ctx, int32_t inst, const void* host, size_t 
     if (d.ksnap[0])
         PD_HIP(hipMemcpyAsync(d.ksnap[ctx->cur], (const char*)host + 8 * Nc * W, 8 * Nc,
                               hipMemcpyHostToDevice, ctx->stream));
+    st = drop_carried_rates(ctx, inst);
+    if (st != PD_OK) return st;
     PD_HIP(hipStreamSynchronize(ctx->stream));
     ctx->stepped = false;
     ctx->anc_valid = false;
@@ -916,6 +935,7 @@ pd_status pd_load(pd_ctx* ctx, const void* host, size_t bytes)
         const size_t Nc = (size_t)p.Nc, W = (size_t)words_of(p.L);
         std::memcpy(&ctl[i], at, sizeof(InstCtl));
         ctl[i].ncont = 0;
+        ctl[i].s_carried = 0;   // the guided rates are not part of a checkpoint
         if (ctl[i].beta < 0) return fail(ctx, PD_EINVAL, "checkpoint has a negative interval count");
         at += sizeof(InstCtl);
         std::string m = check_states(p, at);
@@ -1004,6 +1024,10 @@ pd_status pd_set_guide(pd_ctx* ctx, const uint32_t* d_table, size_t n)
     }
     PD_HIP(hipMemcpyAsync(ctx->d_insts, ctx->dev.data(), sizeof(InstDev) * (size_t)ctx->n,
                           hipMemcpyHostToDevice, ctx->stream));
+    for (int i = 0; i < ctx->n; ++i) {
+        const pd_status st = drop_carried_rates(ctx, i);
+        if (st != PD_OK) return st;
+    }
     PD_HIP(hipStreamSynchronize(ctx->stream));
     ctx->guide_set = true;
     return PD_OK;

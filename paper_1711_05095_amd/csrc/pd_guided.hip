@@ -156,7 +156,10 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
         Kfrom = gptr(I.K[src])[from];
         if (I.origin[0]) gptr(I.origin[dst])[j] = gptr(I.origin[src])[from];
         bond_mask<W>(x, lb, m);
-        S = guided_total<W>(x, m, L, s_eg);
+        // S as the clone's ancestor ended the last interval (the same integer
+        // the sum over the allowed hops gives), unless the population or the
+        // table has changed since
+        S = I.ctl->s_carried ? gptr(I.rate[src])[from] : guided_total<W>(x, m, L, s_eg);
         tau = 0.0; A = 0.0; AS = 0.0; P = 1.0;
         k = 0; kb = 0; pexp = 0;
     }
@@ -270,6 +273,7 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
     gptr(I.A)[j] = A;
     gptr(I.ell)[j] = ell;
     gptr(I.iters)[j] = k;
+    gptr(I.rate[dst])[j] = S;
 }
 
 // Tile aggregates from the outputs written by slot, one wave per tile (the

@@ -33,7 +33,10 @@ struct InstCtl {
     double d_eq;           // offset d of the [eq] points of interval beta (set by k_prefix)
     uint64_t ksnap_sum;    // scratch: sum of the burn-in snapshots of K (estimates)
     uint64_t iters;        // guided stage: proposals of the current interval (zeroed by k_prefix)
-    uint64_t pad_;
+    uint64_t draws;        // guided stage: random draws over the run (proposals and closing draws)
+    uint32_t s_carried;    // guided: rate[src] holds S of the population (set by k_prefix;
+                           // cleared wherever the population or the table changes otherwise)
+    uint32_t pad_;
 };
 
 // Per-instance descriptor (written by the host at creation, read-only after).
@@ -64,6 +67,8 @@ struct InstDev {
     uint64_t guide_max;    // largest table entry (acceptance bound)
     double guide_scale;    // 2^16 / (e^{-s} guide_max): 1 / (proposal rate of one allowed bond)
     uint32_t* iters;       // [Nc] guided: proposals of the last interval, by slot
+    uint64_t* rate[2];     // [Nc] guided: S (sum of the table over the allowed hops) of each
+                           // clone at the end of its interval, two buffers like K (else null)
     const double* log_tab; // [kLogRows][kLogCols] table of the device logarithm
     const uint8_t* sel_tab;// [2048] byte table of select_bit_lut (shared)
     double ln2_hi, ln2_lo; // ln 2 = ln2_hi (a multiple of 2^-42) + ln2_lo

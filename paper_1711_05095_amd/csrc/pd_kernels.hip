@@ -89,6 +89,8 @@ __global__ void k_reset_ctl(const InstDev* __restrict__ insts, int n)
     c->ksum = 0;
     c->ksnap_sum = 0;
     c->iters = 0;
+    c->draws = 0;
+    c->s_carried = 0;
 }
 
 // Neumaier compensated addition.
@@ -687,7 +689,10 @@ __device__ __forceinline__ void prefix_finish(const InstDev& I, uint32_t beta, d
     c->ncont = 0;
     const double per_clone = c->iters ? (double)c->iters / (double)I.Nc
                                       : (double)hops / (double)I.Nc + 1.0;
+    c->draws += c->iters;
     c->iters = 0;
+    // the guided stage has just written S of every clone it stepped
+    if (I.mode == MODE_GUIDED) c->s_carried = 1;
     c->ev_budget = (uint32_t)fmin(1.1 * per_clone + 2.0, 1073741824.0);
 }
 
@@ -1019,7 +1024,7 @@ __global__ __launch_bounds__(kTile) void k_carry_burn(const InstDev* __restrict_
 }
 
 // Materialise the population: dst[j] = src[anc[j]] for the state, K and the
-// carried origins and burn-in snapshots.
+// carried origins, burn-in snapshots and guided rates.
 template <int W>
 __global__ __launch_bounds__(kTile) void k_gather(const InstDev* __restrict__ insts,
                                                   const TileDesc* __restrict__ tiles,
@@ -1036,6 +1041,7 @@ __global__ __launch_bounds__(kTile) void k_gather(const InstDev* __restrict__ in
     I.K[src ^ 1][j] = I.K[src][from];
     if (I.origin[0]) I.origin[src ^ 1][j] = I.origin[src][from];
     if (I.ksnap[0]) I.ksnap[src ^ 1][j] = I.ksnap[src][from];
+    if (I.rate[0]) I.rate[src ^ 1][j] = I.rate[src][from];
 }
 
 // origin[cur][j] = j for every clone of instance `inst`.

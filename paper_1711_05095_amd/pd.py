@@ -41,7 +41,8 @@ class PdParams(ctypes.Structure):
 class PdEstimates(ctypes.Structure):
     _fields_ = [("psi", ctypes.c_double), ("psi_burn", ctypes.c_double),
                 ("k_hat", ctypes.c_double), ("t", ctypes.c_double), ("cycles", ctypes.c_int64),
-                ("hops", ctypes.c_uint64), ("k_hat_burn", ctypes.c_double)]
+                ("hops", ctypes.c_uint64), ("k_hat_burn", ctypes.c_double),
+                ("draws", ctypes.c_uint64)]
 
 
 class PdStageTimes(ctypes.Structure):
@@ -183,7 +184,7 @@ def pd_estimates_get(ctx, inst=0):
     e = PdEstimates()
     _check(lib().pd_estimates_get(ctx, inst, ctypes.byref(e)), ctx)
     return dict(psi=e.psi, psi_burn=e.psi_burn, k_hat=e.k_hat, k_hat_burn=e.k_hat_burn, t=e.t,
-                cycles=e.cycles, hops=e.hops)
+                cycles=e.cycles, hops=e.hops, draws=e.draws)
 
 
 def words_of(L):

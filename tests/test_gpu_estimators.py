@@ -143,6 +143,78 @@ def test_guide_table_is_copied():
     assert B.estimates()["psi"] == pytest.approx(r2["psi"], rel=1e-9)
 
 
+@pytest.mark.parametrize("L,N,s,Nc,dt,M", [(30, 14, 0.1, 600, 0.3, 6),
+                                           (100, 50, 0.15, 1_000_000, 0.5, 3)])
+def test_guided_draw_count(L, N, s, Nc, dt, M):
+    """pd_estimates.draws counts the guided stage's random draws: one per
+    proposed hop and one closing draw per clone per interval (every clone has
+    an allowed hop when 0 < N < L).  With every allowed neighbourhood at the
+    table's largest entry each proposal is taken, so draws = hops + Nc M
+    exactly; a random table also rejects proposals; a plain instance of the
+    same context reports none.  Nc = 1e6 runs the guided stage as two
+    launches (the clones past the first launch's budget handed on)."""
+    from guide_tables import constant_table, random_table
+    for table, exact in ((constant_table(), True), (random_table(43), False)):
+        ps = [pd.make_params(L, N, s, Nc, M * dt, dt, seed=6, weight_mode=GUIDED),
+              pd.make_params(L, N, s, 1000, M * dt, dt, seed=7, instance=1)]
+        S = pd.Sampler(ps)
+        S.set_guide(torch.from_numpy(table.view(np.int32).copy()).cuda())
+        S.run(M)
+        e = S.estimates(0)
+        print("L=%d Nc=%d exact=%s: hops %d draws %d" % (L, Nc, exact, e["hops"], e["draws"]),
+              flush=True)
+        if exact:
+            assert e["draws"] == e["hops"] + Nc * M
+        else:
+            assert e["draws"] > e["hops"] + Nc * M
+        assert S.estimates(1)["draws"] == 0
+        S.close()
+
+
+def test_guided_rates_follow_population_and_table_changes():
+    """The guided stage carries each clone's S (the table summed over its
+    allowed hops) from one interval to the next and forms it afresh wherever
+    the population or the table changed otherwise.  Three such points, each
+    against a context restored from a checkpoint taken there (a checkpoint
+    holds no rates, so that context sums S from the states): a materialised
+    population (the rates are gathered with the states), pd_set_guide with
+    another table, and pd_set_population."""
+    from guide_tables import random_table
+    from layout import pack
+    L, N, s, Nc, dt = 40, 18, 0.1, 700, 0.4
+    p = pd.make_params(L, N, s, Nc, 40 * dt, dt, seed=8, weight_mode=GUIDED)
+    g1, g2 = (torch.from_numpy(random_table(k).view(np.int32).copy()).cuda() for k in (51, 52))
+
+    def restored(blob, table, cycles):
+        C = pd.Sampler(p)
+        C.set_guide(table)
+        C.load(blob)
+        C.run(cycles)
+        return C
+
+    def same(A, C):
+        wa, Ka = A.get_population()
+        wc, Kc = C.get_population()
+        assert np.array_equal(wa, wc) and np.array_equal(Ka, Kc)
+        assert A.estimates() == C.estimates()
+
+    A = pd.Sampler(p)
+    A.set_guide(g1)
+    A.run(4)
+    blob = A.save()                 # materialises the population
+    A.run(2)
+    same(A, restored(blob, g1, 2))
+    blob = A.save()
+    A.set_guide(g2)
+    A.run(3)
+    same(A, restored(blob, g2, 3))
+    occ = inputs.random_population(L, N, Nc, seed=9)
+    A.set_population(pack(occ), inputs.random_counts(Nc, seed=10))
+    blob = A.save()
+    A.run(3)
+    same(A, restored(blob, g2, 3))
+
+
 def test_stage_times():
     """Stage timing records the single launches of pd_step and pd_resample
     and leaves the results unchanged."""

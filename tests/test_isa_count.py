@@ -16,3 +16,10 @@ from paper_1711_05095_amd import isa_count
 def test_event_loop_within_the_frozen_unit():
     assert isa_count.count() <= bench.VALU_PER_EVENT_W2
     assert isa_count.count("_ZN2pd6k_stepILi7E") <= bench.VALU_PER_EVENT_W7
+
+
+@pytest.mark.skipif(not (shutil.which("hipcc") or os.path.exists("/opt/rocm/bin/hipcc")),
+                    reason="hipcc not available")
+def test_guided_paths_within_the_frozen_unit():
+    per_draw, per_hop = isa_count.guided_paths()
+    assert per_draw <= bench.VALU_PER_DRAW_G2 and per_hop <= bench.VALU_PER_HOP_G2
