@@ -165,6 +165,12 @@ pd_status pd_scgf(pd_ctx* ctx, double* psi, double* k_hat, int64_t* cycles_done)
  * left out (the transient of Sec. 5.1). */
 pd_status pd_estimates_get(pd_ctx* ctx, int32_t inst, pd_estimates* out);
 
+/* The hop counts so far (pd_estimates.hops) of every instance, written to the
+ * caller-owned device array d_hops[n] (uint64, n = the context's instances) by
+ * a launch queued on the context stream, without synchronising: a progress or
+ * throughput probe that leaves the device busy.  PD_EINVAL if d_hops is NULL. */
+pd_status pd_hop_counts(pd_ctx* ctx, uint64_t* d_hops);
+
 /* Host image of a population: uint64 state words [W][Nc] (word w of clone j
  * at w*Nc + j; site i is bit i%64 of word i/64, bits >= L are zero), then
  * uint64 K[Nc] (hops accumulated along the clone's ancestry).  W = ceil(L/64). */

@@ -1060,6 +1060,14 @@ pd_status pd_get_origin(pd_ctx* ctx, int32_t inst, int32_t* origin)
     return PD_OK;
 }
 
+pd_status pd_hop_counts(pd_ctx* ctx, uint64_t* d_hops)
+{
+    if (!ctx) return PD_EINVAL;
+    if (!d_hops) return fail(ctx, PD_EINVAL, "null output");
+    PD_HIP(launch_hop_counts(ctx->d_insts, ctx->n, d_hops, ctx->stream));
+    return PD_OK;
+}
+
 pd_status pd_descendant_counts(pd_ctx* ctx, int32_t inst, uint32_t* d_counts)
 {
     pd_status st = check_inst(ctx, inst);

@@ -42,6 +42,7 @@ hipError_t launch_density_mode(int W, const InstDev* insts, int inst, int64_t Nc
                                double* out, hipStream_t st);
 hipError_t launch_mean(const InstDev* insts, int inst, int64_t Nc, int cur, const double* values,
                        int ancestral, hipStream_t st);
+hipError_t launch_hop_counts(const InstDev* insts, int n, uint64_t* out, hipStream_t st);
 hipError_t launch_descendants(const InstDev* insts, int inst, int64_t Nc, int cur,
                               uint32_t* counts, hipStream_t st);
 hipError_t launch_prefix(const InstDev* insts, int n_inst, hipStream_t st);

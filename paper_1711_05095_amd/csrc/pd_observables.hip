@@ -168,6 +168,19 @@ __global__ __launch_bounds__(kTile) void k_descendants(const InstDev* __restrict
     if (j < I.Nc) atomicAdd(&counts[gptr(I.origin[cur])[j]], 1u);
 }
 
+// d_out[i] = hops of instance i so far, for every instance of the context.
+__global__ __launch_bounds__(kTile) void k_hop_counts(const InstDev* __restrict__ insts, int n,
+                                                     uint64_t* __restrict__ out)
+{
+    for (int i = threadIdx.x; i < n; i += kTile) out[i] = insts[i].ctl->hops;
+}
+
+hipError_t launch_hop_counts(const InstDev* insts, int n, uint64_t* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_hop_counts, dim3(1), dim3(kTile), 0, st, insts, n, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_descendants(const InstDev* insts, int inst, int64_t Nc, int cur,
                               uint32_t* counts, hipStream_t st)
 {

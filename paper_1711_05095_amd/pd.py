@@ -21,9 +21,9 @@ PD_MAX_L = 512
 
 # Exported functions of include/pd.h (the ABI test checks each one is present).
 EXPORTS = ["pd_workspace_bytes", "pd_create", "pd_destroy", "pd_step", "pd_resample", "pd_run",
-           "pd_scgf", "pd_estimates_get", "pd_population_bytes", "pd_get_population",
-           "pd_set_population", "pd_get_step_outputs", "pd_get_ancestors", "pd_get_log",
-           "pd_save_bytes", "pd_save", "pd_load", "pd_set_guide", "pd_reset_origin",
+           "pd_scgf", "pd_estimates_get", "pd_hop_counts", "pd_population_bytes",
+           "pd_get_population", "pd_set_population", "pd_get_step_outputs", "pd_get_ancestors",
+           "pd_get_log", "pd_save_bytes", "pd_save", "pd_load", "pd_set_guide", "pd_reset_origin",
            "pd_get_origin", "pd_descendant_counts", "pd_density_mode", "pd_mean",
            "pd_histogram", "pd_get_tuning", "pd_set_tuning", "pd_autotune", "pd_time_stages",
            "pd_get_stage_times", "pd_last_error", "pd_status_str"]
@@ -97,6 +97,7 @@ def lib():
             "pd_reset_origin": [vp, c.c_int32],
             "pd_get_origin": [vp, c.c_int32, vp],
             "pd_descendant_counts": [vp, c.c_int32, vp],
+            "pd_hop_counts": [vp, vp],
             "pd_density_mode": [vp, c.c_int32, c.c_int32, vp],
             "pd_mean": [vp, c.c_int32, vp, c.c_int32, P(c.c_double)],
             "pd_histogram": [vp, c.c_int32, vp, c.c_int32, c.c_double, c.c_double, c.c_int32, vp],
@@ -249,6 +250,10 @@ def pd_get_origin(ctx, inst, Nc):
     return out
 
 
+def pd_hop_counts(ctx, hops_ptr):
+    _check(lib().pd_hop_counts(ctx, ctypes.c_void_p(hops_ptr)), ctx)
+
+
 def pd_descendant_counts(ctx, inst, counts_ptr):
     _check(lib().pd_descendant_counts(ctx, inst, ctypes.c_void_p(counts_ptr)), ctx)
 
@@ -391,6 +396,16 @@ class Sampler:
 
     def origin(self, inst=0):
         return pd_get_origin(self.ctx, inst, self.params[inst].Nc)
+
+    def hop_counts(self, out):
+        """Queues a copy of every instance's hop count into `out` (an int64
+        CUDA tensor of n entries, read as uint64) on the sampler's stream, with
+        no synchronisation (the stream first waits for torch's current stream,
+        where `out` was allocated)."""
+        import torch
+        assert out.is_cuda and out.dtype.itemsize == 8 and out.numel() >= self.n
+        self.stream.wait_stream(torch.cuda.current_stream())
+        pd_hop_counts(self.ctx, out.data_ptr())
 
     def descendant_counts(self, inst=0):
         """Descendants of each slot of the last origin reset among the current

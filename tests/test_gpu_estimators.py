@@ -215,6 +215,24 @@ def test_guided_rates_follow_population_and_table_changes():
     same(A, restored(blob, g2, 3))
 
 
+def test_hop_counts_snapshot():
+    """pd_hop_counts queues a copy of every instance's hop count on the stream:
+    after a sync it equals pd_estimates.hops of each instance, and a snapshot
+    taken before more cycles keeps the earlier values."""
+    ps = [pd.make_params(30 + 10 * i, 12 + 5 * i, 0.05 * i, 500 + 300 * i, 20.0, 0.5, seed=20 + i,
+                         instance=i) for i in range(3)]
+    S = pd.Sampler(ps)
+    S.run(4)
+    early = torch.zeros(3, dtype=torch.int64, device="cuda")
+    S.hop_counts(early)
+    S.run(3)
+    late = torch.zeros(3, dtype=torch.int64, device="cuda")
+    S.hop_counts(late)
+    S.stream.synchronize()
+    assert late.cpu().tolist() == [S.estimates(i)["hops"] for i in range(3)]
+    assert all(0 < e < l for e, l in zip(early.cpu().tolist(), late.cpu().tolist()))
+
+
 def test_stage_times():
     """Stage timing records the single launches of pd_step and pd_resample
     and leaves the results unchanged."""
