@@ -12,6 +12,7 @@ uniform variate in [0, 1) instead of (0, 1] changes one value in 2^53."""
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 import pytest
 
@@ -91,22 +92,39 @@ def _run_pins(tmp_path, source, files):
     src.write_text(source)
     subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-shared", "-fPIC",
                            str(src), "-o", str(lib), "-lm"])
-    env = dict(os.environ, PD_ORACLE_LIB=str(lib))
+    # one thread per run: the runs go side by side
+    env = dict(os.environ, PD_ORACLE_LIB=str(lib), OMP_NUM_THREADS="1",
+               OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
     return subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                            "-m", "not gpu"] + files, cwd=ROOT, env=env, capture_output=True,
                           text=True, timeout=900)
 
 
-def test_unmodified_copy_passes(tmp_path):
-    r = _run_pins(tmp_path, open(ORACLE_C).read(), PLAIN + GUIDED + ESTIMATORS[1:])
+@pytest.fixture(scope="module")
+def pin_runs(tmp_path_factory):
+    """The pins run against every copy (the control and each planted mistake),
+    in separate processes side by side."""
+    source = open(ORACLE_C).read()
+    jobs = {"control": (source, PLAIN + GUIDED + ESTIMATORS[1:])}
+    for name, orig, mutated, files in MUTATIONS:
+        if source.count(orig) == 1:
+            jobs[name] = (source.replace(orig, mutated), files)
+    workers = max(1, min(8, os.cpu_count() or 1))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        futs = {k: ex.submit(_run_pins, tmp_path_factory.mktemp(k), src, files)
+                for k, (src, files) in jobs.items()}
+        return {k: f.result() for k, f in futs.items()}
+
+
+def test_unmodified_copy_passes(pin_runs):
+    r = pin_runs["control"]
     assert r.returncode == 0, r.stdout[-3000:]
 
 
 @pytest.mark.parametrize("name,orig,mutated,files", MUTATIONS, ids=[m[0] for m in MUTATIONS])
-def test_planted_mistake_fails_a_pin(tmp_path, name, orig, mutated, files):
-    source = open(ORACLE_C).read()
-    assert source.count(orig) == 1, name   # the mistake goes where it is meant to
-    r = _run_pins(tmp_path, source.replace(orig, mutated), files)
+def test_planted_mistake_fails_a_pin(pin_runs, name, orig, mutated, files):
+    assert open(ORACLE_C).read().count(orig) == 1, name   # the mistake goes where it is meant to
+    r = pin_runs[name]
     # 1: a test failed (not a crash, a collection error or an interruption)
     assert r.returncode == 1, (name, r.stdout[-3000:])
 
