@@ -794,6 +794,54 @@ def test_call_order_and_validation():
     assert e.value.status == pd.PD_EINVAL
 
 
+def test_bench_sweep_launch_sampled():
+    """The headline workload in the launch configuration bench.py times: the
+    L=100 transition sweep (32 lambdas x Nc=1e5 in one context), the
+    autotuner's choice with graphs of 10 cycles, 5 warm-up cycles and 20
+    graph-replayed ones.  The next cycle is checked on 1000 sampled clones of
+    three instances against the oracle (states, hops, log-weights), and the
+    whole selection of those instances against the oracle's on the GPU's
+    log-weights."""
+    w = inputs.SWEEP
+    L, N, dt, Nc = w["L"], w["N"], w["dt"], 100_000
+    lams = w["lambdas"]
+    print("bench sweep: %d instances x Nc=%d" % (len(lams), Nc), flush=True)
+    params = [pd.make_params(L, N, inputs.s_of_lambda(lam, L), Nc, 60 * dt, dt,
+                             seed=w["seed0"] + i, instance=i) for i, lam in enumerate(lams)]
+    S = pd.Sampler(params)
+    t = S.autotune(8)
+    S.set_tuning(t["step_variant"], t["refill"], 10, t["scan_tiles"])
+    S.run(0)
+    S.run(5)
+    S.run(20)
+    beta = 26
+    assert S.estimates(0)["cycles"] == beta - 1
+    rng = np.random.default_rng(5)
+    picks = [0, 13, 31]
+    before = {}
+    for i in picks:
+        words, K = S.get_population(i)
+        slots = np.sort(rng.choice(Nc, 1000, replace=False))
+        before[i] = (slots, unpack(words[:, slots], L), K[slots].copy())
+    S.step()
+    ells = {}
+    for i in picks:
+        slots, occ_s, K_s = before[i]
+        o = oracle.Oracle(L, N, inputs.s_of_lambda(lams[i], L), Nc, dt, M=60,
+                          seed=w["seed0"] + i, instance=i)
+        Kb_o, A_o, ell_o = o.step_slots(beta, slots, occ_s, K_s)
+        w_g, K_g = S.get_population(i)
+        Kb_g, A_g, ell_g = S.step_outputs(i)
+        assert np.array_equal(Kb_g[slots], Kb_o), i
+        assert np.array_equal(w_g[:, slots], pack(occ_s)), i
+        assert np.array_equal(K_g[slots], K_s), i
+        assert np.allclose(ell_g[slots], ell_o, rtol=1e-12, atol=1e-300), i
+        ells[i] = (ell_g, o.eq_offset(beta))
+    S.resample()
+    for i in picks:
+        check_selection(S.ancestors(i), ells[i][0], ells[i][1], "bench sweep %d" % i)
+
+
 @pytest.mark.parametrize("L,N,lam,Nc,dt", [(100, 50, 20.0, 100_000, 0.5),
                                            (100, 50, 20.0, 1_000_000, 0.5),
                                            (400, 200, 20.0, 1_000_000, 1.0)])
