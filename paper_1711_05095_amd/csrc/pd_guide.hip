@@ -88,22 +88,23 @@ __host__ __device__ inline int net_ext_words(int L)
 __host__ __device__ inline size_t net_ext_bytes(int L) { return (8 * net_ext_words(L) + 15) / 16 * 16; }
 
 // Bytes of one wave's region: the bit string, the position-major array (h1,
-// then g2 once the forward pass is past a row), the channel-major h1 and g2,
-// and at least the 32 x 160 floats of the end-of-block reduction.
+// then g2 once the forward pass is past a row), the channel-major h1, and at
+// least the 16 x 160 floats of one half of the end-of-block reduction.
 __host__ __device__ inline size_t net_wave_bytes(int L)
 {
     const size_t LP = net_lp(L), P = LP + 4;
-    const size_t arrays = net_ext_bytes(L) + P * RS * 2 + 2 * CH * P * 2;
-    const size_t red = sizeof(float) * CH * Q;
+    const size_t arrays = net_ext_bytes(L) + P * RS * 2 + CH * P * 2;
+    const size_t red = sizeof(float) * 16 * Q;
     return ((arrays > red ? arrays : red) + 15) / 16 * 16;
 }
 
-// Waves per block: as many as fit beside the shared part (at most 4).
+// Waves per block: as many as fit beside the shared part (at most 8: two
+// waves per SIMD, the most the kernel's 256 registers allow).
 __host__ __device__ inline int net_waves(int L)
 {
     const size_t avail = 163840 - kNetShared;
     const int w = (int)(avail / net_wave_bytes(L));
-    return w < 1 ? 1 : (w > 4 ? 4 : w);
+    return w < 1 ? 1 : (w > 8 ? 8 : w);
 }
 
 // tanh(x) = 1 - 2 / (e^{2x} + 1) from the hardware base-2 exponential and
@@ -183,14 +184,19 @@ __device__ __forceinline__ void build_ext(uint64_t* ext, uint64_t word_of_lane, 
 // rows 0, 1 and LP + 2, LP + 3 copied from the rows of their sites; for g2
 // (position-major only) rows 0, 1 and L + 2, L + 3 copied, rows LP + 2 and
 // LP + 3 zero where they are not those.  dst / src rows per lane slot are
-// precomputed (src < 0: zero).
+// precomputed (src < 0: zero), packed as two signed 16-bit halves to keep the
+// registers they hold through the sample loop few.
 struct HaloSlots {
-    int dst[3], src[3];
+    uint32_t ds[3];
+    __device__ void set(int s, int dst, int src) { ds[s] = (uint32_t)(dst & 0xFFFF) | ((uint32_t)src << 16); }
+    __device__ int dst(int s) const { return (int)(int16_t)(ds[s] & 0xFFFFu); }
+    __device__ int src(int s) const { return (int)(int16_t)(ds[s] >> 16); }
 };
 
 // ---------------------------------------------------------------------------
-// Forward and backward passes, one sample per wave, several waves per block
-// sharing the weights.
+// Forward and backward passes, one sample per wave, up to 8 waves per block
+// sharing the weights: two waves per SIMD, which the 256 registers and the
+// per-wave LDS below are sized for.
 //
 // Layer 1 (1 -> 32, K = 5 padded to 16) and layer 2 (32 -> 32, K = 160) run
 // on the matrix cores with positions as the rows of each product and channels
@@ -200,23 +206,25 @@ struct HaloSlots {
 // contraction index is taken tap-major, q = t * 32 + c', so that one 16x16x32
 // step covers one tap: its A operand is 8 consecutive channels of h1 (or g2)
 // at one position, a 16-byte read of the position-major array, and its B
-// operand (the weights) stays in registers for the whole kernel.  The
-// weight-gradient pass contracts over positions (16x16x16) and reads the
-// channel-major copies; the tap shift of its B operand is formed from two
-// aligned 8-byte reads with byte alignment, all five taps from one pair.
+// operand (the weights) a 16-byte read of the shared weights at each product.
+// The weight-gradient pass contracts over positions (16x16x16): its A operand
+// (4 positions of one g2 channel) is four 2-byte reads of the position-major
+// array, its B operand comes from the channel-major copy of h1, the tap shift
+// formed from two aligned 8-byte reads with byte alignment, all five taps from
+// one pair.
 //
-// The two layer-2 passes are software-pipelined over position tiles (A
-// operands read a tile ahead, the products of the next tile in flight during
-// the epilogue of the current one).  The position-major array holds h1 during
-// the forward pass and g2 after it: each tile writes its g2 at the end of its
-// epilogue, after the reads of the next tile, the only one that shares rows
-// with it, were issued.  The scalar delta = d loss / d f of a sample is applied
+// The forward pass reads the A operands of the next tile before the epilogue
+// of the current one; the input-gradient pass runs one tile at a time (the
+// other wave of the SIMD covers the latency).  The position-major array holds
+// h1 during the forward pass and g2 after it: each tile writes its g2 at the
+// end of its epilogue, after the reads of the next tile, the only one that
+// shares rows with it, were issued.  The scalar delta = d loss / d f of a sample is applied
 // after the matrix products (in float32): the products run on
 // g2 = w3s (1 - h2^2) and the results are scaled by delta.  Layer-1
 // activations are recomputed on the matrix cores where 1 - h1^2 is needed.
 // ---------------------------------------------------------------------------
 template <int MODE>
-__global__ __launch_bounds__(256) void k_net(const float* __restrict__ theta,
+__global__ __launch_bounds__(512) void k_net(const float* __restrict__ theta,
                                              const uint64_t* __restrict__ states,
                                              const float* __restrict__ counts, int L, int64_t n,
                                              int64_t ld, float inv_n, float* __restrict__ f_out,
@@ -243,7 +251,6 @@ __global__ __launch_bounds__(256) void k_net(const float* __restrict__ theta,
     const uint32_t* ext32 = (const uint32_t*)wbase;
     uint16_t* HP = (uint16_t*)(wbase + net_ext_bytes(L));   // [P][RS]: h1, then g2
     uint16_t* H1C = HP + P * RS;                              // [32][P]
-    uint16_t* G2C = H1C + CH * P;                             // [32][P], zero beyond L
 
     for (int i = threadIdx.x; i < CH * Q; i += blockDim.x) {
         const int c = i / Q, rest = i % Q, cp = rest / KS, t = rest % KS;   // W2[c][c'][t]
@@ -278,15 +285,13 @@ __global__ __launch_bounds__(256) void k_net(const float* __restrict__ theta,
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
         const int idx = lane + 64 * s, k = idx >> 5;
-        H1s.dst[s] = H1s.src[s] = -1;
+        H1s.set(s, -1, -1);
         if (k < 4) {
             const int R = k < 2 ? k : LP + k;   // 0, 1, LP + 2, LP + 3
-            H1s.dst[s] = R;
-            H1s.src[s] = (R - 2 + 2 * L) % L + 2;
+            H1s.set(s, R, (R - 2 + 2 * L) % L + 2);
         }
         const int RG = k == 0 ? 0 : k == 1 ? 1 : k == 2 ? LP + 2 : k == 3 ? LP + 3 : L + k - 2;
-        G2s.dst[s] = RG;
-        G2s.src[s] = RG < 2 ? RG + L : (RG == L + 2 || RG == L + 3) ? RG - L : -1;
+        G2s.set(s, RG, RG < 2 ? RG + L : (RG == L + 2 || RG == L + 3) ? RG - L : -1);
     }
     const int p0 = (lane - 4 + L) % L;
     __syncthreads();
@@ -299,17 +304,11 @@ __global__ __launch_bounds__(256) void k_net(const float* __restrict__ theta,
         b2s[mt] = S.b2[mt * 16 + r];
         w3c[mt] = S.w3s[mt * 16 + r];
     }
-    // the layer-2 B operands of both passes stay in registers: output channel
-    // mt * 16 + r, tap t, input channels 8 g4 .. 8 g4 + 7 (forward), and the
-    // transposed weights for the input gradient
-    bf16x8 Wf[2][KS], Wb[2][KS];
-#pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-        for (int t = 0; t < KS; ++t) {
-            Wf[mt][t] = ld8(S.W2R + (mt * 16 + r) * WS + t * 32 + 8 * g4);
-            if (MODE == 1) Wb[mt][t] = ld8(S.W2T + (mt * 16 + r) * WS + t * 32 + 8 * g4);
-        }
+    // the layer-2 B operands of both passes, read from LDS at each product:
+    // output channel mt * 16 + r, tap t, input channels 8 g4 .. 8 g4 + 7
+    // (forward), and the transposed weights for the input gradient
+    const uint16_t* const wf = S.W2R + r * WS + 8 * g4;
+    const uint16_t* const wb = S.W2T + r * WS + 8 * g4;
 
     // per-lane accumulators over the block's samples: the layer-2 weight
     // gradient for c = mt * 16 + 4 g4 + v and q = qt * 16 + r, the layer-1
@@ -357,22 +356,21 @@ __global__ __launch_bounds__(256) void k_net(const float* __restrict__ theta,
         wave_sync();
 #pragma unroll
         for (int s = 0; s < 3; ++s) {
-            if (H1s.dst[s] >= 0) {
+            if (H1s.dst(s) >= 0) {
                 const int c = (lane + 64 * s) & 31;
-                const uint16_t v = HP[H1s.src[s] * RS + c];
-                HP[H1s.dst[s] * RS + c] = v;
-                H1C[c * P + H1s.dst[s]] = v;
+                const uint16_t v = HP[H1s.src(s) * RS + c];
+                HP[H1s.dst(s) * RS + c] = v;
+                H1C[c * P + H1s.dst(s)] = v;
             }
         }
         wave_sync();
         // layers 2 and 3, positions as rows: one A operand (8 channels of h1 at
-        // one position) serves both channel tiles.  Software-pipelined: while
-        // the epilogue of tile nt runs, the products of tile nt+1 are in the
-        // matrix cores and the A operands of tile nt+2 are being read (tiles past
-        // the last are clamped to it and their results dropped).  Tile nt writes
-        // its g2 (position-major, over the h1 rows) at the end of its epilogue:
-        // its rows end at row (nt+1)*16 + 1, which only tile nt+1 reads, and that
-        // read was issued before; LDS operations of a wave complete in order.
+        // one position) serves both channel tiles.  The A operands of tile nt+1
+        // are read before the epilogue of tile nt (a tile past the last is
+        // clamped to it and its reads dropped).  Tile nt writes its g2
+        // (position-major, over the h1 rows) at the end of its epilogue: its rows
+        // end at row (nt+1)*16 + 1, which only tile nt+1 reads, and that read was
+        // issued before; LDS operations of a wave complete in order.
         float fpart = 0.0f, s2p[2] = {0.0f, 0.0f}, g2p[2] = {0.0f, 0.0f};
         auto load_h = [&](bf16x8 (&A)[KS], int nt) {
             const int row = min(nt, NT - 1) * 16 + r;
@@ -384,8 +382,8 @@ __global__ __launch_bounds__(256) void k_net(const float* __restrict__ theta,
             z[1] = f32x4{b2s[1], b2s[1], b2s[1], b2s[1]};
 #pragma unroll
             for (int t = 0; t < KS; ++t) {
-                z[0] = mfma32(A[t], Wf[0][t], z[0]);
-                z[1] = mfma32(A[t], Wf[1][t], z[1]);
+                z[0] = mfma32(A[t], ld8(wf + t * 32), z[0]);
+                z[1] = mfma32(A[t], ld8(wf + 16 * WS + t * 32), z[1]);
             }
         };
         auto epi_f = [&](const f32x4 (&z)[2], int nt) {
@@ -406,7 +404,6 @@ __global__ __launch_bounds__(256) void k_net(const float* __restrict__ theta,
                 }
                 if (MODE == 1) {
                     const u32x2 pk{pk_bf16(g2[0], g2[1]), pk_bf16(g2[2], g2[3])};
-                    *reinterpret_cast<u32x2*>(G2C + (mt * 16 + r) * P + jo) = pk;
                     uint16_t* hp = HP + (jo + 2) * RS + mt * 16 + r;
                     hp[0] = (uint16_t)pk[0];
                     hp[RS] = (uint16_t)(pk[0] >> 16);
@@ -417,18 +414,16 @@ __global__ __launch_bounds__(256) void k_net(const float* __restrict__ theta,
         };
         {
             bf16x8 A0[KS], A1[KS];
-            f32x4 zc[2], zn[2];
+            f32x4 z[2];
             load_h(A0, 0);
-            load_h(A1, 1);
-            mm_f(A0, zc);
             for (int nt = 0; nt < NT; nt += 2) {
-                mm_f(A1, zn);          // tile nt+1
-                load_h(A0, nt + 2);
-                epi_f(zc, nt);
+                mm_f(A0, z);           // tile nt
+                load_h(A1, nt + 1);    // before tile nt's epilogue writes over rows it reads
+                epi_f(z, nt);
                 if (nt + 1 < NT) {
-                    mm_f(A0, zc);      // tile nt+2
-                    load_h(A1, nt + 3);
-                    epi_f(zn, nt + 1);
+                    mm_f(A1, z);       // tile nt+1
+                    load_h(A0, nt + 2);
+                    epi_f(z, nt + 1);
                 }
             }
         }
@@ -453,16 +448,11 @@ __global__ __launch_bounds__(256) void k_net(const float* __restrict__ theta,
             gb2[mt] += delta * g2p[mt];
         }
         wave_sync();
-#pragma unroll
-        for (int s = 0; s < 3; ++s) {
-            const int c = (lane + 64 * s) & 31;
-            const uint16_t v = G2s.src[s] >= 0 ? HP[G2s.src[s] * RS + c] : (uint16_t)0;
-            HP[G2s.dst[s] * RS + c] = v;
-        }
-        wave_sync();
         // weight gradient of layer 2: sum over positions of g2[c][j] h1[c'][j + t - 2]
-        // for c = mt * 16 + 4 g4 + v and c' = h * 16 + r; the five taps of B from one
-        // aligned pair of 8-byte reads
+        // for c = mt * 16 + 4 g4 + v and c' = h * 16 + r; A (4 positions of one g2
+        // channel) from four 2-byte reads of the position-major array, which holds
+        // g2 at row j + 2 and zeros for j >= L until the halo copy below; the five
+        // taps of B from one aligned pair of 8-byte reads of the channel-major h1
 #pragma unroll
         for (int hm = 0; hm < 4; ++hm) {
             const int h = hm >> 1, mt = hm & 1;
@@ -470,9 +460,11 @@ __global__ __launch_bounds__(256) void k_net(const float* __restrict__ theta,
 #pragma unroll
             for (int t = 0; t < KS; ++t) d[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
             const uint16_t* hrow = H1C + (h * 16 + r) * P + 4 * g4;
-            const uint16_t* grow = G2C + (mt * 16 + r) * P + 4 * g4;
+            const uint16_t* gcol = HP + (4 * g4 + 2) * RS + mt * 16 + r;
             for (int jt = 0; jt < NT; ++jt) {
-                const bf16x4 A = ld4(grow + jt * 16);
+                const uint16_t* gp = gcol + jt * 16 * RS;
+                const bf16x4 A = as_bf16x4((uint32_t)gp[0] | ((uint32_t)gp[RS] << 16),
+                                           (uint32_t)gp[2 * RS] | ((uint32_t)gp[3 * RS] << 16));
                 const u32x2 lo = *reinterpret_cast<const u32x2*>(hrow + jt * 16);
                 const u32x2 hi = *reinterpret_cast<const u32x2*>(hrow + jt * 16 + 4);
                 d[0] = mfma16(A, as_bf16x4(lo[0], lo[1]), d[0]);
@@ -488,8 +480,17 @@ __global__ __launch_bounds__(256) void k_net(const float* __restrict__ theta,
 #pragma unroll
                 for (int v = 0; v < 4; ++v) acc[mt][2 * t + h][v] += delta * d[t][v];
         }
-        // input gradient of layer 2 and the layer-1 backward, positions as rows,
-        // pipelined as the forward pass (this pass only reads the arrays)
+        wave_sync();
+        // circular halo rows of g2 for the input gradient
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const int c = (lane + 64 * s) & 31;
+            const uint16_t v = G2s.src(s) >= 0 ? HP[G2s.src(s) * RS + c] : (uint16_t)0;
+            HP[G2s.dst(s) * RS + c] = v;
+        }
+        wave_sync();
+        // input gradient of layer 2 and the layer-1 backward, positions as rows
+        // (this pass only reads the arrays)
         auto load_g = [&](bf16x8 (&A)[KS], int nt) {
             const int row = min(nt, NT - 1) * 16 + r;
 #pragma unroll
@@ -499,8 +500,8 @@ __global__ __launch_bounds__(256) void k_net(const float* __restrict__ theta,
             d[0] = d[1] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
             for (int t = 0; t < KS; ++t) {
-                d[0] = mfma32(A[t], Wb[0][t], d[0]);
-                d[1] = mfma32(A[t], Wb[1][t], d[1]);
+                d[0] = mfma32(A[t], ld8(wb + t * 32), d[0]);
+                d[1] = mfma32(A[t], ld8(wb + 16 * WS + t * 32), d[1]);
             }
             // layer-1 pre-activations again, on the matrix cores
             const int j = min(nt, NT - 1) * 16 + r;
@@ -531,51 +532,40 @@ __global__ __launch_bounds__(256) void k_net(const float* __restrict__ theta,
                                  gW1[mt]);
             }
         };
-        {
-            bf16x8 A0[KS], A1[KS];
-            f32x4 dc[2], dn[2], zc[2], zn[2];
-            load_g(A0, 0);
-            load_g(A1, 1);
-            mm_b(A0, 0, dc, zc);
-            for (int nt = 0; nt < NT; nt += 2) {
-                mm_b(A1, nt + 1, dn, zn);      // tile nt+1
-                load_g(A0, nt + 2);
-                epi_b(dc, zc, nt);
-                if (nt + 1 < NT) {
-                    mm_b(A0, nt + 2, dc, zc);  // tile nt+2
-                    load_g(A1, nt + 3);
-                    epi_b(dn, zn, nt + 1);
-                }
-            }
+        // one tile at a time: the other wave of the SIMD covers the latency
+        for (int nt = 0; nt < NT; ++nt) {
+            bf16x8 A[KS];
+            f32x4 dc[2], zc[2];
+            load_g(A, nt);
+            mm_b(A, nt, dc, zc);
+            epi_b(dc, zc, nt);
         }
         wave_sync();
     }
     if (MODE == 0) return;
 
     // Block sums in a fixed order (no atomics, so the result is reproducible):
-    // first the layer-2 weight gradient, then the small parameters, each
-    // through the per-wave regions.
+    // the layer-2 weight gradient in two halves of 16 output channels, then the
+    // small parameters, each through the per-wave regions.
     __syncthreads();   // every wave is done with its region
-    float* red = (float*)wbase;   // at least CH * Q floats per wave
+    float* red = (float*)wbase;   // at least 16 * Q floats per wave
+    float* out = partial + (int64_t)blockIdx.x * (kGuideParams + 1);
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
+    for (int mt = 0; mt < 2; ++mt) {
 #pragma unroll
         for (int qt = 0; qt < 10; ++qt)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int c = mt * 16 + 4 * g4 + v, q = qt * 16 + r;
-                red[c * Q + q] = acc[mt][qt][v];
-            }
-    __syncthreads();
-    float* out = partial + (int64_t)blockIdx.x * (kGuideParams + 1);
-    for (int i = threadIdx.x; i < CH * Q; i += blockDim.x) {
-        const int c = i / Q, q = i % Q, t = q >> 5, cp = q & 31;
-        float sum = 0.0f;
-        for (int w = 0; w < nw; ++w)
-            sum += ((const float*)(smem + kNetShared + (size_t)w * net_wave_bytes(L)))[i];
-        out[OFF_W2 + c * Q + cp * KS + t] = sum;
+            for (int v = 0; v < 4; ++v) red[(4 * g4 + v) * Q + qt * 16 + r] = acc[mt][qt][v];
+        __syncthreads();
+        for (int i = threadIdx.x; i < 16 * Q; i += blockDim.x) {
+            const int c = mt * 16 + i / Q, q = i % Q, t = q >> 5, cp = q & 31;
+            float sum = 0.0f;
+            for (int w = 0; w < nw; ++w)
+                sum += ((const float*)(smem + kNetShared + (size_t)w * net_wave_bytes(L)))[i];
+            out[OFF_W2 + c * Q + cp * KS + t] = sum;
+        }
+        __syncthreads();   // the half is read before the next one is written
     }
-    __syncthreads();
     // small parameters: the W1 gradient at red[c * 5 + t] (lanes r < 5), the
     // per-channel partials of b1, b2 and W3 at red[160 + (k * 4 + g4) * 32 + c]
     // and the scalars at red[544 + k]
