@@ -444,6 +444,54 @@ def test_guided_full_size_sampled(L, N, s, dt):
     check_selection(S.ancestors(), ell_g, o.eq_offset(3), "guided full size")
 
 
+def test_bench_guided_launch_sampled():
+    """The guided leg of bench.py's guided-rate workload as it is timed: 32
+    guided instances x Nc=1e5 at L=100, lambda=15 in one context (the stage in
+    two launches, escape rates carried between intervals), 8 single cycles and
+    16 graph-replayed ones; then one cycle checked on 1000 sampled clones of
+    three instances against the oracle and those instances' whole selections."""
+    from guide_tables import random_table
+    L, N, lam, dt, Nc = 100, 50, 15.0, 0.5, 100_000
+    s = inputs.s_of_lambda(lam, L)
+    table = random_table(12)
+    print("bench guided: 32 instances x Nc=%d" % Nc, flush=True)
+    params = [pd.make_params(L, N, s, Nc, 60 * dt, dt, seed=2000 + i, instance=i,
+                             weight_mode=GUIDED) for i in range(32)]
+    S = pd.Sampler(params)
+    S.set_guide(_guide_tensor(table))
+    S.set_tuning(4, 13, 16, 1)
+    S.run(0)
+    S.run(8)
+    S.run(16)
+    beta = 25
+    assert S.estimates(0)["cycles"] == beta - 1
+    rng = np.random.default_rng(6)
+    picks = [0, 17, 31]
+    before = {}
+    for i in picks:
+        words, K = S.get_population(i)
+        slots = np.sort(rng.choice(Nc, 1000, replace=False))
+        before[i] = (slots, unpack(words[:, slots], L), K[slots].copy())
+    S.step()
+    ells = {}
+    for i in picks:
+        slots, occ_s, K_s = before[i]
+        o = oracle.Oracle(L, N, s, Nc, dt, M=60, seed=2000 + i, instance=i, mode=GUIDED,
+                          guide=table)
+        Kb_o, A_o, ell_o = o.step_slots(beta, slots, occ_s, K_s)
+        w_g, K_g = S.get_population(i)
+        Kb_g, A_g, ell_g = S.step_outputs(i)
+        assert np.array_equal(Kb_g[slots], Kb_o), i
+        assert np.array_equal(w_g[:, slots], pack(occ_s)), i
+        assert np.array_equal(K_g[slots], K_s), i
+        assert np.allclose(A_g[slots], A_o, rtol=1e-12), i
+        assert np.allclose(ell_g[slots], ell_o, rtol=1e-11, atol=1e-12), i
+        ells[i] = (ell_g, o.eq_offset(beta))
+    S.resample()
+    for i in picks:
+        check_selection(S.ancestors(i), ells[i][0], ells[i][1], "bench guided %d" % i)
+
+
 def test_guided_whole_run_and_guide_validation():
     from guide_tables import constant_table, random_table
     w = inputs.SMALL
