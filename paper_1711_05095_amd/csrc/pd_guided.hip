@@ -167,14 +167,22 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
     const uint32_t eb = (CONT || !budgeted) ? 0u : I.ctl->ev_budget;
     const uint32_t kend = eb ? eb : 0xFFFFFFFFu;   // the first launch stops at event kend
     bool done = true;
+    // A draw's random numbers depend only on (draw index, slot, interval), not
+    // on the state: those of draw k + 1 are formed while draw k is decided, so
+    // their chain of dependent instructions runs beside the bond choice.  They
+    // are formed only where another draw follows (not after the closing one).
+    uint4 y{0u, 0u, 0u, 0u};
+    double E = 0.0;
+    if (r > 0 && (CONT || k < kend)) {
+        y = philox10(k, (uint32_t)j, beta, c3, I.key0, I.key1);
+        E = -log_unit(unit_scaled(y.x, y.y), s_log, I.ln2_hi, I.ln2_lo, poly, 53);
+    }
     while (r > 0 && k < (1u << 30)) {
         if (!CONT && k >= kend) {
             done = false;
             break;
         }
-        const uint4 y = philox10(k, (uint32_t)j, beta, c3, I.key0, I.key1);
         ++k;
-        const double E = -log_unit(unit_scaled(y.x, y.y), s_log, I.ln2_hi, I.ln2_lo, poly, 53);
         // waiting time of the next proposal: E / (e^{-s} eg_max 2^-16 r)
         const double w = E * s_invg[r];
         if (tau + w >= dt) {
@@ -185,9 +193,12 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
         A = fma((double)r, w, A);
         AS = fma((double)S, w, AS);
         tau = tau + w;
+        const uint32_t yz = y.z, yw = y.w;
+        y = philox10(k, (uint32_t)j, beta, c3, I.key0, I.key1);
+        E = -log_unit(unit_scaled(y.x, y.y), s_log, I.ln2_hi, I.ln2_lo, poly, 53);
         // bw r = q 2^64 + a with bw = (y.z << 32) | y.w: the bond and the acceptance word
-        const uint64_t plo = (uint64_t)y.w * (uint32_t)r;
-        const uint64_t phi = (uint64_t)y.z * (uint32_t)r + (plo >> 32);
+        const uint64_t plo = (uint64_t)yw * (uint32_t)r;
+        const uint64_t phi = (uint64_t)yz * (uint32_t)r + (plo >> 32);
         const int b = select_bit_lut<W>(m, (uint32_t)(phi >> 32), s_sel);
         uint32_t e, win0 = 0;          // L >= 26: the 26 sites from b-12
         // the neighbourhood of b is bits 6..18 of the window from b-12, which
