@@ -148,6 +148,41 @@ __device__ __forceinline__ bool one_event(const StepConst& C, uint32_t slot, uin
     return false;
 }
 
+// one_event with the draw's random numbers formed beforehand (y, E): an
+// event's Philox block and logarithm depend only on (event index, slot,
+// interval), so when MORE, those of the next event are formed beside this
+// event's hop, their chains of dependent instructions side by side.  Not
+// after the closing draw, nor (MORE = false) after the last event of a round.
+__device__ __forceinline__ void draw_event(const StepConst& C, uint32_t slot, uint32_t k,
+                                           uint4& y, double& E)
+{
+    y = philox10(k, slot, C.beta, C.c3, C.key0, C.key1);
+    E = -log_unit(unit_scaled(y.x, y.y), C.logt, C.ln2_hi, C.ln2_lo, C.poly, 53);
+}
+
+template <int W, bool MORE>
+__device__ __forceinline__ bool event_ahead(const StepConst& C, uint32_t slot, uint64_t (&x)[W],
+                                            uint64_t (&m)[W], int& r, double& tau, double& A,
+                                            uint32_t& k, uint32_t& kb, uint4& y, double& E)
+{
+    if (r == 0) return true;
+    ++k;
+    const double w = E * C.invr[r];   // the table holds inv_scale / r
+    if (tau + w >= C.dt || k >= 0x80000000u) {
+        A = fma((double)r, C.dt - tau, A);
+        return true;
+    }
+    A = fma((double)r, w, A);
+    tau = tau + w;
+    const uint32_t q = mulhi64_small(y.z, y.w, (uint32_t)r);
+    if (MORE) draw_event(C, slot, k, y, E);
+    hop<W>(x, select_bit_lut<W>(m, q, C.sel), C.L);
+    bond_mask<W>(x, C.lb, m);
+    r = popcount_words<W>(m);
+    ++kb;
+    return false;
+}
+
 // The logarithm table and 1 / r (scaled by the instance's inv_scale when
 // `scaled`: one instance per block).
 __device__ __forceinline__ void load_tables(const InstDev& I, double* s_log, double* s_invr,
@@ -316,8 +351,21 @@ __device__ __forceinline__ void run_tile_c(const InstDev& I, const TileDesc& td,
 
     bool fin = false;   // finished in this round, outputs not yet written
     for (;;) {
-        for (int it = 0; active && it < budget; ++it) {
-            if (one_event<W, true>(C, (uint32_t)(td.first + t), x, m, r, tau, A, k, kb)) {
+        {
+            const uint32_t slot = (uint32_t)(td.first + t);
+            uint4 y{0u, 0u, 0u, 0u};
+            double E = 0.0;
+            if (active && r > 0) draw_event(C, slot, k, y, E);
+            int it = 0;
+            for (; active && it + 1 < budget; ++it) {
+                if (event_ahead<W, true>(C, slot, x, m, r, tau, A, k, kb, y, E)) {
+                    active = false;
+                    fin = true;
+                }
+            }
+            // the round's last event forms no draw after it
+            if (active && it < budget &&
+                event_ahead<W, false>(C, slot, x, m, r, tau, A, k, kb, y, E)) {
                 active = false;
                 fin = true;
             }
