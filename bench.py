@@ -68,7 +68,7 @@ GUIDED_UNIT_SOURCE = "paths of k_step_g<2>'s loop at commit d06e9ac"
 # VALU wave-instructions issued per CU per cycle of the kernel, and the
 # fraction of issued lane slots that the frozen unit accounts for.
 STEP_COUNTERS = {"source": "profiles/k_step_sweep_L100_Nc1e5.txt",
-                 "valu_issue_per_cu_cycle": 0.965, "lane_utilisation": 0.786}
+                 "valu_issue_per_cu_cycle": 0.980, "lane_utilisation": 0.778}
 # HBM bytes the cloning stage must move per clone: ln Ups read (8) by the
 # resample scan, ancestor written (4); the gather of the states is fused into
 # the next dynamical stage's load.
@@ -76,7 +76,7 @@ RESAMPLE_BYTES_PER_CLONE = 12
 # HBM bytes per launch of the step kernel on this workload, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE runs scaled by a plain 1 GiB copy (factors 2 and
 # 1), valid only for the kernel sources they were taken on (STEP_SOURCES).
-STEP_TRAFFIC = {"bytes": 240.2e6, "kernels_sha1": "2889b1a91689", "kernel": "k_step_c<2>"}
+STEP_TRAFFIC = {"bytes": 241.2e6, "kernels_sha1": "6731b2b7688c", "kernel": "k_step_c<2>"}
 STEP_SOURCES = ["pd_kernels.hip", "pd_tile.hpp", "pd_device.hpp", "pd_internal.hpp"]
 
 
