@@ -144,6 +144,7 @@ def test_guide_table_is_copied():
 
 
 @pytest.mark.parametrize("L,N,s,Nc,dt,M", [(30, 14, 0.1, 600, 0.3, 6),
+                                           (20, 9, 0.2, 500, 0.5, 6),
                                            (100, 50, 0.15, 1_000_000, 0.5, 3)])
 def test_guided_draw_count(L, N, s, Nc, dt, M):
     """pd_estimates.draws counts the guided stage's random draws: one per
@@ -231,6 +232,9 @@ def test_hop_counts_snapshot():
     S.stream.synchronize()
     assert late.cpu().tolist() == [S.estimates(i)["hops"] for i in range(3)]
     assert all(0 < e < l for e, l in zip(early.cpu().tolist(), late.cpu().tolist()))
+    with pytest.raises(pd.PdError) as e:
+        pd.pd_hop_counts(S.ctx, 0)
+    assert e.value.status == pd.PD_EINVAL
 
 
 def test_stage_times():
