@@ -205,8 +205,9 @@ def bench_guide(a):
     learned guide, trained on the GPU from plain populations at Nc = 1e5 and
     distilled on them; at L = 400 the L = 100 guide fine-tuned on L = 400
     populations), the cheapest (Nc, t_obs) of a grid whose RMS error over
-    8 seeds against psi_ref is <= 1e-3; psi_ref = mean of plain runs at
-    Nc = 1e6 with the same t_obs (psi-hat's large-Nc limit depends on t_obs).
+    8 seeds against psi_ref is <= 1e-3; psi_ref = mean of 2 plain runs at
+    Nc = 1e6 with the same t_obs (psi-hat's large-Nc limit depends on t_obs),
+    reported with its standard error.
     The reported time is one run at that grid point (median of 3).  Guide
     training (collection, training, distillation) is timed separately."""
     import torch
@@ -244,12 +245,14 @@ def bench_guide(a):
                                   gmax=1.0, seed=9)
         trained[(L, lam)] = g["trainer"]
         t_train = time.perf_counter() - t0
-        refs = {}
+        refs, refs_se = {}, {}
         for t_obs in P["t_grid"]:
             psi, _ = _estimates(L, N, lam, 1_000_000, t_obs, dt, 2, pd.PD_W_MODIFIED, seed=1,
                                 inst0=100)
             refs[t_obs] = float(psi.mean())
+            refs_se[t_obs] = float(np.std(psi, ddof=1) / np.sqrt(len(psi)))
         row = {"L": L, "lambda": lam, "dt": dt, "train_seconds": t_train, "psi_ref": refs,
+               "psi_ref_se": refs_se,
                "guide": "fine-tuned from L=%d" % P["finetune_from"][0] if "finetune_from" in P
                else "trained at this point"}
         grid = sorted(((nc, t) for nc in P["nc_grid"] for t in P["t_grid"]),
@@ -605,8 +608,10 @@ def bench_guided_vs_plain(a):
     against psi_ref at every grid point; among the points that pass
     (RMS <= 1e-3), the smallest passing Nc at each (dt, t_obs) is timed (one
     run, median of 3), and the fastest is the form's result.  psi_ref = mean
-    of 2 plain runs at Nc=1e6, the same t_obs and the point's first dt.  The guide is trained on the GPU from plain populations
-    (Nc=1e5) and distilled on them; its training time is reported apart."""
+    of 2 plain runs at Nc=1e6, the same t_obs and the point's first dt,
+    reported with its standard error.  The guide is trained on the GPU from
+    plain populations (Nc=1e5) and distilled on them; its training time is
+    reported apart."""
     import torch
     from paper_1711_05095_amd import guide
     t_start = time.perf_counter()
@@ -628,13 +633,15 @@ def bench_guided_vs_plain(a):
                               seed=9)
         torch.cuda.synchronize()
         t_train = time.perf_counter() - t0
-        refs = {}
+        refs, refs_se = {}, {}
         for t_obs in P["t_grid"]:
             psi, _ = _estimates(L, N, lam, 1_000_000, t_obs, dt, 2, pd.PD_W_MODIFIED, seed=1,
                                 inst0=100)
             refs[t_obs] = float(psi.mean())
+            refs_se[t_obs] = float(np.std(psi, ddof=1) / np.sqrt(len(psi)))
         row = {"L": L, "N": N, "lambda": lam, "dt": dt, "train_seconds": t_train,
-               "psi_ref": {str(k): v for k, v in refs.items()}, "grid": []}
+               "psi_ref": {str(k): v for k, v in refs.items()},
+               "psi_ref_se": {str(k): v for k, v in refs_se.items()}, "grid": []}
         for name, mode, eg in (("plain", pd.PD_W_MODIFIED, None),
                                ("guided", pd.PD_W_GUIDED, g["eg"])):
             passing = {}
