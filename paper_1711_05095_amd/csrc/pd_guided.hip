@@ -97,24 +97,30 @@ __global__ __launch_bounds__(kTile) void k_step_g(const InstDev* __restrict__ in
     __shared__ double s_invg[64 * W + 1];   // guide_scale / r: 1 / (proposal rate), r <= 64 W
     __shared__ __align__(8) uint8_t s_sel[2048];
 
-    const TileDesc td = tiles[tile_base + blockIdx.x];
+    // a block runs a whole tile, or (blocks of one wave, for launches smaller
+    // than the chip, so that the waves spread over more CUs) a quarter of one
+    const bool quarter = blockDim.x == 64u;          // uniform: no division
+    const int nb = quarter ? 64 : kTile;
+    const int sub = quarter ? (int)(blockIdx.x & 3u) : 0;
+    const TileDesc td = tiles[tile_base + (int)(quarter ? blockIdx.x >> 2 : blockIdx.x)];
     const InstDev& I = insts[td.inst];
     const int L = I.L;
     const int64_t Nc = I.Nc;
     const uint32_t ncont = CONT ? I.ctl->ncont : 0u;
-    const uint32_t e0 = (uint32_t)td.tile * kTile;   // first handed-on clone of the block
+    // first handed-on clone of the block
+    const uint32_t e0 = (uint32_t)td.tile * kTile + (uint32_t)(sub * nb);
     if (CONT && e0 >= ncont) return;                  // uniform over the block
-    for (int i = threadIdx.x; i < kLogRows * kLogCols; i += kTile) s_log[i] = gptr(I.log_tab)[i];
-    for (int i = threadIdx.x; i <= 64 * W; i += kTile)
+    for (int i = threadIdx.x; i < kLogRows * kLogCols; i += nb) s_log[i] = gptr(I.log_tab)[i];
+    for (int i = threadIdx.x; i <= 64 * W; i += nb)
         s_invg[i] = I.guide_scale * gptr(I.inv_count)[i];
-    load_select_table(s_sel, I.sel_tab, threadIdx.x, kTile);
+    load_select_table(s_sel, I.sel_tab, threadIdx.x, nb);
     // 16-byte pieces (the host checks the table's alignment)
-    for (int i = threadIdx.x; i < kGuideEntries / 4; i += kTile)
+    for (int i = threadIdx.x; i < kGuideEntries / 4; i += nb)
         reinterpret_cast<uint4*>(s_eg)[i] = reinterpret_cast<const uint4*>(I.guide)[i];
     __syncthreads();
 
-    const int tid = threadIdx.x;
-    const uint32_t q = e0 + (uint32_t)tid;            // handed-on clone (CONT)
+    const int tid = sub * nb + (int)threadIdx.x;       // the clone's place in its tile
+    const uint32_t q = (uint32_t)td.tile * kTile + (uint32_t)tid;   // handed-on clone (CONT)
     if (CONT ? q >= ncont : tid >= td.count) return;  // no barrier follows
     const uint32_t beta = (uint32_t)(I.ctl->beta + 1);
     const uint32_t c3 = TAG_GUIDE | I.tag_hi;
@@ -322,14 +328,16 @@ hipError_t launch_step_guided(int W, int count, const InstDev* insts, const Tile
                               int base, int src, int use_anc, hipStream_t st)
 {
     const int split = count >= kSplitTiles;
+    // fewer tiles than CUs: one-wave blocks, a quarter tile each
+    const int nsub = count < kQuarterTiles ? 4 : 1;
     switch (W) {
 #define PD_CASE(w)                                                                            \
     case w:                                                                                   \
-        hipLaunchKernelGGL((k_step_g<w, false>), dim3(count), dim3(kTile), 0, st, insts,      \
-                           tiles, base, src, use_anc, split);                                 \
+        hipLaunchKernelGGL((k_step_g<w, false>), dim3(count * nsub), dim3(kTile / nsub), 0,  \
+                           st, insts, tiles, base, src, use_anc, split);                     \
         if (split)                                                                            \
-            hipLaunchKernelGGL((k_step_g<w, true>), dim3(count), dim3(kTile), 0, st, insts,   \
-                               tiles, base, src, use_anc, 1);                                 \
+            hipLaunchKernelGGL((k_step_g<w, true>), dim3(count * nsub), dim3(kTile / nsub),  \
+                               0, st, insts, tiles, base, src, use_anc, 1);                  \
         break;
         PD_CASE(1) PD_CASE(2) PD_CASE(3) PD_CASE(4) PD_CASE(5) PD_CASE(6) PD_CASE(7)
         PD_CASE(8)

@@ -30,6 +30,9 @@ hipError_t launch_step(const StepLaunch& s, const InstDev* insts, const TileDesc
 // leaves idle hold no other work back, and a second launch would only add its
 // own time.
 constexpr int kSplitTiles = 2 * 7 * 256;
+// Guided launches of fewer tiles than the chip has CUs run blocks of one wave
+// (a quarter tile each), so that their waves spread over four times as many CUs.
+constexpr int kQuarterTiles = 256;
 
 hipError_t launch_step_guided(int W, int count, const InstDev* insts, const TileDesc* tiles,
                               int base, int src, int use_anc, hipStream_t st);
