@@ -25,11 +25,12 @@ hipError_t launch_init(const InstDev* insts, int n_inst, const TileDesc* tiles, 
 hipError_t launch_step(const StepLaunch& s, const InstDev* insts, const TileDesc* tiles, int src,
                        int use_anc, hipStream_t st);
 // Tiles from which the guided stage is split in two launches (a budgeted one,
-// then the clones it handed on, densely): below it the whole launch is
-// resident at once (7 blocks per CU), so the lanes a wave's Poisson tail
-// leaves idle hold no other work back, and a second launch would only add its
-// own time.
-constexpr int kSplitTiles = 2 * 7 * 256;
+// then the clones it handed on, densely).  Below it each SIMD holds fewer than
+// four of the launch's waves, so the lanes that a wave's Poisson tail leaves
+// idle cost few issue slots that another wave could have used, and a second
+// launch only adds its own time (measured at 391 to 2528 tiles, L = 50 and
+// 100: the split costs 3% at 586 and 782 tiles and saves 3% at 1172 and 2528).
+constexpr int kSplitTiles = 4 * 256;
 // Guided launches of fewer tiles than the chip has CUs run blocks of one wave
 // (a quarter tile each), so that their waves spread over four times as many CUs.
 constexpr int kQuarterTiles = 256;
