@@ -252,11 +252,31 @@ __global__ __launch_bounds__(512) void k_net(const float* __restrict__ theta,
     uint16_t* HP = (uint16_t*)(wbase + net_ext_bytes(L));   // [P][RS]: h1, then g2
     uint16_t* H1C = HP + P * RS;                              // [32][P]
 
-    for (int i = threadIdx.x; i < CH * Q; i += blockDim.x) {
-        const int c = i / Q, rest = i % Q, cp = rest / KS, t = rest % KS;   // W2[c][c'][t]
-        const uint16_t v = f2bf(theta[OFF_W2 + i]);
-        S.W2R[c * WS + t * CH + cp] = v;
-        S.W2T[cp * WS + t * CH + c] = v;
+    // the wave's first sample word, loaded before the set-up so that its
+    // latency overlaps it
+    const int64_t stride = (int64_t)gridDim.x * nw;
+    int64_t smp = (int64_t)blockIdx.x * nw + wv;
+    uint64_t word = (lane < W && smp < n) ? states[(int64_t)lane * ld + smp] : 0ull;
+    // W2 as bfloat16, row-major and transposed: each thread issues its loads
+    // ten at a time before the stores (a loop of one load per iteration
+    // would wait out the memory latency at every element)
+    for (int i0 = threadIdx.x; i0 < CH * Q; i0 += 10 * blockDim.x) {
+        float v[10];
+#pragma unroll
+        for (int u = 0; u < 10; ++u) {
+            const int i = i0 + u * (int)blockDim.x;
+            v[u] = i < CH * Q ? theta[OFF_W2 + i] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < 10; ++u) {
+            const int i = i0 + u * (int)blockDim.x;
+            if (i < CH * Q) {
+                const int c = i / Q, rest = i % Q, cp = rest / KS, t = rest % KS;   // W2[c][c'][t]
+                const uint16_t h = f2bf(v[u]);
+                S.W2R[c * WS + t * CH + cp] = h;
+                S.W2T[cp * WS + t * CH + c] = h;
+            }
+        }
     }
     for (int c = threadIdx.x; c < CH; c += blockDim.x) {
         S.b1[c] = theta[OFF_B1 + c];
@@ -325,9 +345,6 @@ __global__ __launch_bounds__(512) void k_net(const float* __restrict__ theta,
         gb1[a] = gW3[a] = gb2[a] = 0.0f;
     }
 
-    const int64_t stride = (int64_t)gridDim.x * nw;
-    int64_t smp = (int64_t)blockIdx.x * nw + wv;
-    uint64_t word = (lane < W && smp < n) ? states[(int64_t)lane * ld + smp] : 0ull;
     for (; smp < n; smp += stride) {
         const uint64_t word_next =
             (lane < W && smp + stride < n) ? states[(int64_t)lane * ld + smp + stride] : 0ull;
@@ -559,9 +576,15 @@ __global__ __launch_bounds__(512) void k_net(const float* __restrict__ theta,
         __syncthreads();
         for (int i = threadIdx.x; i < 16 * Q; i += blockDim.x) {
             const int c = mt * 16 + i / Q, q = i % Q, t = q >> 5, cp = q & 31;
+            float v[8];   // the waves' values read at once (nw <= 8), summed in wave order
+#pragma unroll
+            for (int w = 0; w < 8; ++w)
+                v[w] = w < nw ? ((const float*)(smem + kNetShared + (size_t)w * net_wave_bytes(L)))[i]
+                              : 0.0f;
             float sum = 0.0f;
-            for (int w = 0; w < nw; ++w)
-                sum += ((const float*)(smem + kNetShared + (size_t)w * net_wave_bytes(L)))[i];
+#pragma unroll
+            for (int w = 0; w < 8; ++w)
+                if (w < nw) sum += v[w];
             out[OFF_W2 + c * Q + cp * KS + t] = sum;
         }
         __syncthreads();   // the half is read before the next one is written
@@ -587,19 +610,32 @@ __global__ __launch_bounds__(512) void k_net(const float* __restrict__ theta,
     }
     __syncthreads();
     for (int i = threadIdx.x; i < CH * KS + 3 * CH + 3; i += blockDim.x) {
-        float sum = 0.0f;
-        for (int w = 0; w < nw; ++w) {
-            const float* R = (const float*)(smem + kNetShared + (size_t)w * net_wave_bytes(L));
-            if (i < CH * KS) {
-                sum += R[i];
-            } else if (i < CH * KS + 3 * CH) {
-                const int k = (i - CH * KS) >> 5, c = (i - CH * KS) & 31;
+        // the cnt values of parameter i in each wave's region, every wave's
+        // read at once (nw <= 8), then summed wave by wave in order
+        int o[4] = {0, 0, 0, 0}, cnt = 1;
+        if (i < CH * KS) {
+            o[0] = i;
+        } else if (i < CH * KS + 3 * CH) {
+            const int k = (i - CH * KS) >> 5, c = (i - CH * KS) & 31;
 #pragma unroll
-                for (int g = 0; g < 4; ++g) sum += R[160 + (k * 4 + g) * 32 + c];
-            } else {
-                sum += R[544 + (i - CH * KS - 3 * CH)];
-            }
+            for (int g = 0; g < 4; ++g) o[g] = 160 + (k * 4 + g) * 32 + c;
+            cnt = 4;
+        } else {
+            o[0] = 544 + (i - CH * KS - 3 * CH);
         }
+        float v[8][4];
+#pragma unroll
+        for (int w = 0; w < 8; ++w) {
+            const float* R = (const float*)(smem + kNetShared + (size_t)w * net_wave_bytes(L));
+#pragma unroll
+            for (int g = 0; g < 4; ++g) v[w][g] = (w < nw && g < cnt) ? R[o[g]] : 0.0f;
+        }
+        float sum = 0.0f;
+#pragma unroll
+        for (int w = 0; w < 8; ++w)
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+                if (w < nw && g < cnt) sum += v[w][g];
         if (i < CH * KS) {
             out[OFF_W1 + i] = sum;
         } else if (i < CH * KS + 3 * CH) {
@@ -644,8 +680,11 @@ __global__ __launch_bounds__(256) void k_net_reduce(const float* __restrict__ pa
     const int pl = threadIdx.x & 15, part = threadIdx.x >> 4;
     const int p = blockIdx.x * 16 + pl;
     double acc = 0.0;
-    if (p <= kGuideParams)
+    if (p <= kGuideParams) {
+        // eight loads in flight at a time; the sum keeps the order of b
+#pragma unroll 8
         for (int b = part; b < blocks; b += 16) acc += partial[(int64_t)b * (kGuideParams + 1) + p];
+    }
     s[pl][part] = acc;
     __syncthreads();
     if (part == 0 && p <= kGuideParams) {
@@ -872,6 +911,9 @@ int guide_blocks(int64_t n) { return (int)(n < kGuideBlocks ? n : kGuideBlocks);
 
 static size_t net_block_smem(int L) { return kNetShared + net_waves(L) * net_wave_bytes(L); }
 
+constexpr int kNetBlocks = 256;   // the compute units of the chip
+static_assert(kNetBlocks <= kGuideBlocks, "partials of k_net fit the guide workspace");
+
 static void adam_corrections(int step, float* bc1, float* bc2)
 {
     *bc1 = 1.0f - powf(0.9f, (float)step);
@@ -886,7 +928,10 @@ static hipError_t launch_net_pass(int mode, const float* theta, const uint64_t* 
 {
     const int nw = net_waves(L);
     const int64_t want = (n + nw - 1) / nw;
-    const int blocks = (int)(want < 512 ? want : 512);   // <= guide_blocks(n): fits the workspace
+    // one block per CU (its waves fill the LDS and the registers), a single
+    // round of blocks: each block pays its set-up and its reduction once, and
+    // the partials to sum are as few as can be
+    const int blocks = (int)(want < kNetBlocks ? want : kNetBlocks);   // fits the workspace
     const size_t sm = net_block_smem(L);
     if (blocks_out) *blocks_out = blocks;
     if (mode == 0)
