@@ -13,7 +13,8 @@
 // Weights enter the arithmetic rounded to bfloat16 (the FP32 master copy is
 // what Adam updates, biases stay FP32); the 32 x 160 x L contractions of
 // layer 2 (forward, the weight gradient and the input gradient) and layer 1
-// (exact: its inputs are +-1) run on the matrix cores in bf16 with FP32
+// (exact: its inputs are +-1; in the training kernel over its 32 possible
+// input windows, once per block) run on the matrix cores in bf16 with FP32
 // accumulation; layer 3 and the activations run on the vector ALU in FP32.
 #include <hip/hip_runtime.h>
 
@@ -64,7 +65,8 @@ __device__ __forceinline__ f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c)
 // 16-byte bank groups; channel-major rows of P = LP + 4 halves (2 x odd
 // dwords) do the same for the 8-byte reads of the weight-gradient pass.
 constexpr int WS = 168, RS = 40;
-constexpr int kNetShared = 2 * CH * WS * 2 + 4 * (3 * CH);  // bytes
+constexpr int kWindows = 32;        // input windows of layer 1 (5 sites of +-1)
+constexpr int kNetShared = 2 * CH * WS * 2 + 4 * (3 * CH) + kWindows * CH * (4 + 2);  // bytes
 
 struct NetShared {
     uint16_t* W2R;   // [c][t * 32 + c']  = W2[c][c'][t]   (row stride WS)
@@ -72,6 +74,8 @@ struct NetShared {
     float* b1;
     float* b2;
     float* w3s;      // sum_t W3[c][t] (bf16 values)
+    float* D1;       // [w][c]: 1 - h1^2 of channel c at input window w (float32)
+    uint16_t* T1;    // [w][c]: h1 of channel c at input window w (bfloat16)
 };
 
 __host__ __device__ inline int net_lp(int L) { return (L + 15) / 16 * 16; }
@@ -198,11 +202,13 @@ struct HaloSlots {
 // sharing the weights: two waves per SIMD, which the 256 registers and the
 // per-wave LDS below are sized for.
 //
-// Layer 1 (1 -> 32, K = 5 padded to 16) and layer 2 (32 -> 32, K = 160) run
-// on the matrix cores with positions as the rows of each product and channels
-// as its columns: a lane ends with one channel at 4 consecutive positions, so
-// per-channel sums take one register per channel tile and the W1 gradient is
-// one more product (bf16 dz1 against the exact +-1 inputs).  The layer-2
+// Layer 1 (1 -> 32, K = 5 padded to 16) runs once per block on the matrix
+// cores, over the 32 input windows it can see, into a table of h1 and
+// 1 - h1^2 that the passes read per position.  Layer 2 (32 -> 32, K = 160)
+// runs on the matrix cores with positions as the rows of each product and
+// channels as its columns: a lane ends with one channel at 4 consecutive
+// positions, so per-channel sums take one register per channel tile and the
+// W1 gradient is one more product (bf16 dz1 against the exact +-1 inputs).  The layer-2
 // contraction index is taken tap-major, q = t * 32 + c', so that one 16x16x32
 // step covers one tap: its A operand is 8 consecutive channels of h1 (or g2)
 // at one position, a 16-byte read of the position-major array, and its B
@@ -220,8 +226,7 @@ struct HaloSlots {
 // end of its epilogue, after the reads of the next tile, the only one that
 // shares rows with it, were issued.  The scalar delta = d loss / d f of a sample is applied
 // after the matrix products (in float32): the products run on
-// g2 = w3s (1 - h2^2) and the results are scaled by delta.  Layer-1
-// activations are recomputed on the matrix cores where 1 - h1^2 is needed.
+// g2 = w3s (1 - h2^2) and the results are scaled by delta.
 // ---------------------------------------------------------------------------
 template <int MODE>
 __global__ __launch_bounds__(512) void k_net(const float* __restrict__ theta,
@@ -246,6 +251,8 @@ __global__ __launch_bounds__(512) void k_net(const float* __restrict__ theta,
     S.b1 = (float*)(S.W2T + CH * WS);
     S.b2 = S.b1 + CH;
     S.w3s = S.b2 + CH;
+    S.D1 = S.w3s + CH;
+    S.T1 = (uint16_t*)(S.D1 + kWindows * CH);
     char* wbase = smem + kNetShared + (size_t)wv * net_wave_bytes(L);
     uint64_t* ext = (uint64_t*)wbase;
     const uint32_t* ext32 = (const uint32_t*)wbase;
@@ -299,6 +306,24 @@ __global__ __launch_bounds__(512) void k_net(const float* __restrict__ theta,
     }
     const uint32_t m0 = g4 == 0 ? 0xFFFFFFFFu : (g4 == 1 ? 0x0000FFFFu : 0u);
     const uint32_t m1 = g4 == 0 ? 0xFFFFFFFFu : 0u;
+    // Layer 1 as tables over its 32 input windows: a position's pre-activation
+    // depends only on the 5 inputs (+-1) of its window, so h1 takes one of 32
+    // values per channel.  Four products of 16 windows x 16 channels, the
+    // product a position tile would use (the same operands and accumulator), give
+    // T1 = h1 as bfloat16 and D1 = 1 - h1^2 in float32.
+    for (int job = wv; job < 4; job += nw) {
+        const int mt = job & 1, wt = job >> 1, c = mt * 16 + r;
+        const float b1c = theta[OFF_B1 + c];
+        const f32x4 z = mfma16(l1_operand((uint32_t)(wt * 16 + r), g4, m0, m1), W1op[mt],
+                               f32x4{b1c, b1c, b1c, b1c});
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int w = wt * 16 + 4 * g4 + v;
+            const float h = tanh_fast(z[v]);
+            S.T1[w * CH + c] = (uint16_t)pk_bf16(h, 0.0f);
+            if (MODE == 1) S.D1[w * CH + c] = 1.0f - h * h;
+        }
+    }
     const uint32_t ma = r < KS ? 0xFFFFFFFFu : 0u;
     // halo slots: idx = lane + 64 s over 4 rows (h1) / 6 rows (g2) of 32 channels
     HaloSlots H1s, G2s;
@@ -317,10 +342,9 @@ __global__ __launch_bounds__(512) void k_net(const float* __restrict__ theta,
     __syncthreads();
     const float b3 = theta[OFF_B3], c0 = theta[OFF_C0];
     // the lane's channels c = mt * 16 + r
-    float b1s[2], b2s[2], w3c[2];
+    float b2s[2], w3c[2];
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt) {
-        b1s[mt] = S.b1[mt * 16 + r];
         b2s[mt] = S.b2[mt * 16 + r];
         w3c[mt] = S.w3s[mt * 16 + r];
     }
@@ -351,17 +375,19 @@ __global__ __launch_bounds__(512) void k_net(const float* __restrict__ theta,
         build_ext(ext, word, p0, L, next, lane);
         word = word_next;
         wave_sync();
-        // layer 1, positions as rows: the lane reads the window of position
-        // nt * 16 + r and ends with channel mt * 16 + r at rows R0 .. R0 + 3
+        // layer 1 from the table: the lane writes channel mt * 16 + r at rows
+        // R0 .. R0 + 3, whose windows are bits v .. v + 4 of the string from R0
         for (int nt = 0; nt < NT; ++nt) {
-            const bf16x4 Aa = l1_operand(ext_window(ext32, nt * 16 + 2 + r), g4, m0, m1);
             const int R0 = nt * 16 + 2 + 4 * g4;
+            const uint32_t x = ext_window(ext32, R0);
+            int wo[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) wo[v] = (int)((x >> v) & 31u) * CH;
 #pragma unroll
             for (int mt = 0; mt < 2; ++mt) {
                 const int c = mt * 16 + r;
-                const f32x4 z = mfma16(Aa, W1op[mt], f32x4{b1s[mt], b1s[mt], b1s[mt], b1s[mt]});
-                const uint32_t lo = pk_bf16(tanh_fast(z[0]), tanh_fast(z[1]));
-                const uint32_t hi = pk_bf16(tanh_fast(z[2]), tanh_fast(z[3]));
+                const uint32_t lo = (uint32_t)S.T1[wo[0] + c] | ((uint32_t)S.T1[wo[1] + c] << 16);
+                const uint32_t hi = (uint32_t)S.T1[wo[2] + c] | ((uint32_t)S.T1[wo[3] + c] << 16);
                 *reinterpret_cast<uint32_t*>(H1C + c * P + R0) = lo;
                 *reinterpret_cast<uint32_t*>(H1C + c * P + R0 + 2) = hi;
                 HP[R0 * RS + c] = (uint16_t)lo;
@@ -513,25 +539,25 @@ __global__ __launch_bounds__(512) void k_net(const float* __restrict__ theta,
 #pragma unroll
             for (int t = 0; t < KS; ++t) A[t] = ld8(HP + (row - t + 4) * RS + 8 * g4);
         };
-        auto mm_b = [&](const bf16x8 (&A)[KS], int nt, f32x4 (&d)[2], f32x4 (&z1)[2]) {
+        auto mm_b = [&](const bf16x8 (&A)[KS], f32x4 (&d)[2]) {
             d[0] = d[1] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
             for (int t = 0; t < KS; ++t) {
                 d[0] = mfma32(A[t], ld8(wb + t * 32), d[0]);
                 d[1] = mfma32(A[t], ld8(wb + 16 * WS + t * 32), d[1]);
             }
-            // layer-1 pre-activations again, on the matrix cores
-            const int j = min(nt, NT - 1) * 16 + r;
-            const bf16x4 Aa = l1_operand(ext_window(ext32, j + 2), g4, m0, m1);
-#pragma unroll
-            for (int mt = 0; mt < 2; ++mt)
-                z1[mt] = mfma16(Aa, W1op[mt], f32x4{b1s[mt], b1s[mt], b1s[mt], b1s[mt]});
         };
-        auto epi_b = [&](const f32x4 (&d)[2], const f32x4 (&z1)[2], int nt) {
+        auto epi_b = [&](const f32x4 (&d)[2], int nt) {
             const int jo = nt * 16 + 4 * g4;
             float vm[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) vm[v] = jo + v < L ? delta : 0.0f;
+            // 1 - h1^2 at positions jo + v from the table (windows: bits v .. v + 4
+            // of the string from row jo + 2)
+            const uint32_t xw = ext_window(ext32, jo + 2);
+            int wo[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) wo[v] = (int)((xw >> v) & 31u) * CH;
             // inputs a at positions jo + i + t - 2 for tap t = r (B of the W1 gradient)
             const uint32_t xa = ext_window(ext32, jo + r + 2);
             const bf16x4 Ba = as_bf16x4((0xBF80BF80u ^ (((xa & 1u) << 15) | ((xa & 2u) << 30))) & ma,
@@ -541,8 +567,7 @@ __global__ __launch_bounds__(512) void k_net(const float* __restrict__ theta,
                 float dz[4];
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const float h = tanh_fast(z1[mt][v]);
-                    dz[v] = vm[v] * d[mt][v] * (1.0f - h * h);
+                    dz[v] = vm[v] * d[mt][v] * S.D1[wo[v] + mt * 16 + r];
                     gb1[mt] += dz[v];
                 }
                 gW1[mt] = mfma16(as_bf16x4(pk_bf16(dz[0], dz[1]), pk_bf16(dz[2], dz[3])), Ba,
@@ -552,10 +577,10 @@ __global__ __launch_bounds__(512) void k_net(const float* __restrict__ theta,
         // one tile at a time: the other wave of the SIMD covers the latency
         for (int nt = 0; nt < NT; ++nt) {
             bf16x8 A[KS];
-            f32x4 dc[2], zc[2];
+            f32x4 dc[2];
             load_g(A, nt);
-            mm_b(A, nt, dc, zc);
-            epi_b(dc, zc, nt);
+            mm_b(A, dc);
+            epi_b(dc, nt);
         }
         wave_sync();
     }
