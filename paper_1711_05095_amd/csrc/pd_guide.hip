@@ -74,8 +74,8 @@ struct NetShared {
     float* b1;
     float* b2;
     float* w3s;      // sum_t W3[c][t] (bf16 values)
-    float* D1;       // [w][c]: 1 - h1^2 of channel c at input window w (float32)
-    uint16_t* T1;    // [w][c]: h1 of channel c at input window w (bfloat16)
+    float* D1;       // [w][2 r + mt]: 1 - h1^2 of channel mt * 16 + r at input window w
+    uint16_t* T1;    // [w][2 r + mt]: h1 (bfloat16) of channel mt * 16 + r at input window w
 };
 
 __host__ __device__ inline int net_lp(int L) { return (L + 15) / 16 * 16; }
@@ -310,7 +310,8 @@ __global__ __launch_bounds__(512) void k_net(const float* __restrict__ theta,
     // depends only on the 5 inputs (+-1) of its window, so h1 takes one of 32
     // values per channel.  Four products of 16 windows x 16 channels, the
     // product a position tile would use (the same operands and accumulator), give
-    // T1 = h1 as bfloat16 and D1 = 1 - h1^2 in float32.
+    // T1 = h1 as bfloat16 and D1 = 1 - h1^2 in float32, the two channels
+    // r and 16 + r of a lane side by side (one read serves both channel tiles).
     for (int job = wv; job < 4; job += nw) {
         const int mt = job & 1, wt = job >> 1, c = mt * 16 + r;
         const float b1c = theta[OFF_B1 + c];
@@ -320,8 +321,8 @@ __global__ __launch_bounds__(512) void k_net(const float* __restrict__ theta,
         for (int v = 0; v < 4; ++v) {
             const int w = wt * 16 + 4 * g4 + v;
             const float h = tanh_fast(z[v]);
-            S.T1[w * CH + c] = (uint16_t)pk_bf16(h, 0.0f);
-            if (MODE == 1) S.D1[w * CH + c] = 1.0f - h * h;
+            S.T1[w * CH + 2 * r + mt] = (uint16_t)pk_bf16(h, 0.0f);
+            if (MODE == 1) S.D1[w * CH + 2 * r + mt] = 1.0f - h * h;
         }
     }
     const uint32_t ma = r < KS ? 0xFFFFFFFFu : 0u;
@@ -380,14 +381,17 @@ __global__ __launch_bounds__(512) void k_net(const float* __restrict__ theta,
         for (int nt = 0; nt < NT; ++nt) {
             const int R0 = nt * 16 + 2 + 4 * g4;
             const uint32_t x = ext_window(ext32, R0);
-            int wo[4];
+            uint32_t tp[4];   // h1 of channels r (low half) and 16 + r at row R0 + v
 #pragma unroll
-            for (int v = 0; v < 4; ++v) wo[v] = (int)((x >> v) & 31u) * CH;
+            for (int v = 0; v < 4; ++v)
+                tp[v] = *reinterpret_cast<const uint32_t*>(S.T1 + (int)((x >> v) & 31u) * CH + 2 * r);
 #pragma unroll
             for (int mt = 0; mt < 2; ++mt) {
                 const int c = mt * 16 + r;
-                const uint32_t lo = (uint32_t)S.T1[wo[0] + c] | ((uint32_t)S.T1[wo[1] + c] << 16);
-                const uint32_t hi = (uint32_t)S.T1[wo[2] + c] | ((uint32_t)S.T1[wo[3] + c] << 16);
+                const uint32_t lo = mt == 0 ? (tp[0] & 0xFFFFu) | (tp[1] << 16)
+                                            : (tp[0] >> 16) | (tp[1] & 0xFFFF0000u);
+                const uint32_t hi = mt == 0 ? (tp[2] & 0xFFFFu) | (tp[3] << 16)
+                                            : (tp[2] >> 16) | (tp[3] & 0xFFFF0000u);
                 *reinterpret_cast<uint32_t*>(H1C + c * P + R0) = lo;
                 *reinterpret_cast<uint32_t*>(H1C + c * P + R0 + 2) = hi;
                 HP[R0 * RS + c] = (uint16_t)lo;
@@ -555,9 +559,10 @@ __global__ __launch_bounds__(512) void k_net(const float* __restrict__ theta,
             // 1 - h1^2 at positions jo + v from the table (windows: bits v .. v + 4
             // of the string from row jo + 2)
             const uint32_t xw = ext_window(ext32, jo + 2);
-            int wo[4];
+            f32x2 dp[4];   // channels r and 16 + r
 #pragma unroll
-            for (int v = 0; v < 4; ++v) wo[v] = (int)((xw >> v) & 31u) * CH;
+            for (int v = 0; v < 4; ++v)
+                dp[v] = *reinterpret_cast<const f32x2*>(S.D1 + (int)((xw >> v) & 31u) * CH + 2 * r);
             // inputs a at positions jo + i + t - 2 for tap t = r (B of the W1 gradient)
             const uint32_t xa = ext_window(ext32, jo + r + 2);
             const bf16x4 Ba = as_bf16x4((0xBF80BF80u ^ (((xa & 1u) << 15) | ((xa & 2u) << 30))) & ma,
@@ -567,7 +572,7 @@ __global__ __launch_bounds__(512) void k_net(const float* __restrict__ theta,
                 float dz[4];
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    dz[v] = vm[v] * d[mt][v] * S.D1[wo[v] + mt * 16 + r];
+                    dz[v] = vm[v] * d[mt][v] * dp[v][mt];
                     gb1[mt] += dz[v];
                 }
                 gW1[mt] = mfma16(as_bf16x4(pk_bf16(dz[0], dz[1]), pk_bf16(dz[2], dz[3])), Ba,
