@@ -139,7 +139,7 @@ def window_bound(tb):
 
 
 @pytest.mark.parametrize("L,n", [(5, 200), (13, 300), (37, 1000), (64, 300), (100, 1000),
-                                 (200, 257), (512, 70)])
+                                 (200, 257), (288, 120), (512, 70)])
 def test_forward_matches_reference(L, n):
     th = theta_for(L)
     occ = inputs.random_population(L, L // 2, n, seed=L + 1)
@@ -203,7 +203,14 @@ def test_column_slices_of_a_wider_array():
     assert torch.equal(g_cut, g_copy)
 
 
-@pytest.mark.parametrize("L,n", [(5, 150), (13, 200), (64, 300), (100, 900), (512, 70)])
+# L = 288 runs 3 waves per block (L = 512: 1), so one wave builds two of the
+# four layer-1 table tiles.  Its parameters make e^(f + c0) small against the
+# counts, as at the other sizes here: where e^(f + c0) dominates (L = 232 and
+# 296 with these parameters), delta carries the shift of f that the bf16
+# rounding of h1 makes (up to ~1e-2 at these L, inside the forward bound) and
+# every gradient group moves by that fraction, 0.9-1.3%, against the 1e-2 below
+@pytest.mark.parametrize("L,n", [(5, 150), (13, 200), (64, 300), (100, 900), (288, 80),
+                                 (512, 70)])
 def test_loss_and_gradient_match_reference(L, n):
     th = theta_for(L + 7)
     occ = inputs.random_population(L, L // 2, n, seed=L + 2)
